@@ -1,0 +1,545 @@
+/*
+ * FP64 CPU oracle for the LBM-IBM method of Beny & Latt, "Efficient LBM on
+ * GPUs for dense moving objects using immersed boundary condition"
+ * (arXiv 1904.02108).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg use it.  It shares no code, header or table with the HIP
+ * library: every constant below is written out here on its own.
+ *
+ * Plain, slow, obviously correct: double precision everywhere, one loop per
+ * definition, no blocking or fusion beyond what the paper's step list states.
+ *
+ * Readings of the paper taken here (each is listed with its reason in the
+ * design notes of the repository):
+ *   - eq. (3) printed without a density factor; the step list evaluates the
+ *     equilibrium with rho, so Eq_i = rho t_i [ ... ] (mass must be conserved).
+ *   - Peskin's 4-point kernel, §3: the square root of the outer branch reads
+ *     sqrt(-7 + 12|r| - 4 r^2) (the only reading continuous at |r| = 1, 2).
+ *   - Delta-u accumulates s(k) g(k) from the first iteration on, as the text
+ *     of §3 states (Algorithm 1's reset at the first iteration is read as the
+ *     per-time-step reset of the accumulator).
+ *   - The final spread of §3 / Algorithm 2 accumulates into G.
+ *   - Inner spread: s(k) g(k) by default ("consistent" weighting); the
+ *     paper-literal unweighted g(k) is selected with ORC_IBM_INNER_UNWEIGHTED.
+ *   - Point velocity by finite difference of positions (Algorithm 1):
+ *     u_b(n) = x(n) - x(n-1), theta_n = theta0 + omega n.
+ *   - Forcing: the paper's velocity shift U^G = U + tau G (§2, step 3), or
+ *     Guo's scheme with F = rho G.
+ *   - Walls: halfway bounce-back (walls half a cell outside the first and last
+ *     cell); a moving wall adds 6 t_i rho_w (e_i . u_w) to the reflected
+ *     population (Ladd).  Where a link leaves the box through several walls at
+ *     once, the wall of the lowest axis index (x, then y, then z) supplies u_w.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q 19
+
+/* ---------------------------------------------------------------------------
+ * D3Q19 velocity set (§2: 19 populations per cell, vectors e_i linking a cell
+ * to its neighbours).  Order: rest; the 6 axis links as (+,-) pairs along
+ * x, y, z; the 12 diagonal links as (+,-) pairs in the xy, xz, yz planes.
+ * ------------------------------------------------------------------------- */
+static const int C[Q][3] = {
+    {0, 0, 0},
+    {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+/* Lattice weights t_i (§2; the paper refers to the standard D3Q19 values). */
+static double weight(int i) {
+  if (i == 0) return 1.0 / 3.0;
+  if (i <= 6) return 1.0 / 18.0;
+  return 1.0 / 36.0;
+}
+
+/* Index of the direction opposite to i, found by search (no table). */
+static int opposite(int i) {
+  for (int j = 0; j < Q; ++j)
+    if (C[j][0] == -C[i][0] && C[j][1] == -C[i][1] && C[j][2] == -C[i][2])
+      return j;
+  return -1;
+}
+
+enum { ORC_BC_PERIODIC = 0, ORC_BC_BOUNCEBACK = 1 };
+enum { ORC_FORCE_GUO = 0, ORC_FORCE_SHIFT = 1 };
+enum { ORC_IBM_INNER_UNWEIGHTED = 1 };
+enum { ORC_OK = 0, ORC_ERR_DOMAIN = -5 };
+
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t bc[3];          /* per axis: periodic or bounce-back on both faces */
+  int32_t forcing;        /* ORC_FORCE_GUO or ORC_FORCE_SHIFT */
+  int32_t pad_;
+  double tau;             /* BGK relaxation time */
+  double rho_wall;        /* density used in the moving-wall correction */
+  double wall_u[3][2][3]; /* [axis][low face, high face][component] */
+  double g_ext[3];        /* uniform acceleration added to G in every cell */
+} orc_params;
+
+typedef struct {
+  double center[3];
+  double axis[3];
+  double theta0;
+  double omega;
+} orc_body;
+
+static int64_t ncells(const orc_params* p) {
+  return (int64_t)p->nx * p->ny * p->nz;
+}
+
+static int64_t cell_index(const orc_params* p, int x, int y, int z) {
+  return (int64_t)x + (int64_t)p->nx * ((int64_t)y + (int64_t)p->ny * z);
+}
+
+/* Tables for the pin tests. */
+void orc_d3q19(int32_t* e, double* w, int32_t* opp) {
+  for (int i = 0; i < Q; ++i) {
+    for (int a = 0; a < 3; ++a) e[3 * i + a] = C[i][a];
+    w[i] = weight(i);
+    opp[i] = opposite(i);
+  }
+}
+
+/* ---------------------------------------------------------------------------
+ * Equilibrium, eq. (3), with the density factor (see header):
+ *   Eq_i = rho t_i [1 + 3 e_i.u + 9/2 (e_i.u)^2 - 3/2 u.u]
+ * ------------------------------------------------------------------------- */
+void orc_equilibrium(double rho, const double u[3], double eq[Q]) {
+  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  for (int i = 0; i < Q; ++i) {
+    double eu = C[i][0] * u[0] + C[i][1] * u[1] + C[i][2] * u[2];
+    eq[i] = rho * weight(i) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+  }
+}
+
+/* Moments of one cell, eq. (1): rho = sum f_i, U = (1/rho) sum e_i f_i. */
+static void cell_moments(const double* f, int64_t n, int64_t c, double* rho,
+                         double U[3]) {
+  double r = 0.0, m[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < Q; ++i) {
+    double fi = f[(int64_t)i * n + c];
+    r += fi;
+    for (int a = 0; a < 3; ++a) m[a] += C[i][a] * fi;
+  }
+  *rho = r;
+  for (int a = 0; a < 3; ++a) U[a] = m[a] / r;
+}
+
+/* Density and velocity on every cell (§2, step 1).
+ * f: [19][ncell], rho: [ncell], U: [3][ncell]. */
+void orc_moments(const orc_params* p, const double* f, double* rho, double* U) {
+  int64_t n = ncells(p);
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < n; ++c) {
+    double r, u[3];
+    cell_moments(f, n, c, &r, u);
+    rho[c] = r;
+    for (int a = 0; a < 3; ++a) U[(int64_t)a * n + c] = u[a];
+  }
+}
+
+/* Uniform equilibrium state Eq(rho0, u0) in every cell. */
+void orc_init_equilibrium(const orc_params* p, double rho0, const double u0[3],
+                          double* f) {
+  int64_t n = ncells(p);
+  double eq[Q];
+  orc_equilibrium(rho0, u0, eq);
+  for (int i = 0; i < Q; ++i)
+    for (int64_t c = 0; c < n; ++c) f[(int64_t)i * n + c] = eq[i];
+}
+
+/* ---------------------------------------------------------------------------
+ * Collision with forcing (§2, steps 3-5; eq. (2)) followed by streaming
+ * (§2, step 6; eq. (4)), written as a push: the post-collision population
+ * f*_i at X travels to X + e_i.  On a bounce-back axis a population whose
+ * destination lies outside the box returns to X in the opposite direction.
+ *
+ * f: post-stream populations at time t, [19][ncell].
+ * G: force field [3][ncell] (acceleration; NULL = zero); g_ext is added.
+ * f_out: post-stream populations at time t+1.
+ * ------------------------------------------------------------------------- */
+void orc_collide_stream(const orc_params* p, const double* f, const double* G,
+                        double* f_out) {
+  const int64_t n = ncells(p);
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const int dims[3] = {nx, ny, nz};
+  const double tau = p->tau;
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const int64_t c = cell_index(p, x, y, z);
+        double rho, U[3];
+        cell_moments(f, n, c, &rho, U);
+        double g[3];
+        for (int a = 0; a < 3; ++a)
+          g[a] = (G ? G[(int64_t)a * n + c] : 0.0) + p->g_ext[a];
+
+        double ueq[3], eq[Q], post[Q];
+        if (p->forcing == ORC_FORCE_SHIFT) {
+          /* step 3: U^G = U + tau G, used in the equilibrium only */
+          for (int a = 0; a < 3; ++a) ueq[a] = U[a] + tau * g[a];
+          orc_equilibrium(rho, ueq, eq);
+          for (int i = 0; i < Q; ++i) {
+            double fi = f[(int64_t)i * n + c];
+            post[i] = fi + (eq[i] - fi) / tau;
+          }
+        } else {
+          /* Guo forcing: F = rho G, u = U + G/2,
+           * S_i = (1 - 1/(2 tau)) t_i [3 (e_i - u) + 9 (e_i.u) e_i] . F */
+          double F[3];
+          for (int a = 0; a < 3; ++a) {
+            F[a] = rho * g[a];
+            ueq[a] = U[a] + 0.5 * g[a];
+          }
+          orc_equilibrium(rho, ueq, eq);
+          for (int i = 0; i < Q; ++i) {
+            double eu = C[i][0] * ueq[0] + C[i][1] * ueq[1] + C[i][2] * ueq[2];
+            double s = 0.0;
+            for (int a = 0; a < 3; ++a)
+              s += (3.0 * (C[i][a] - ueq[a]) + 9.0 * eu * C[i][a]) * F[a];
+            double fi = f[(int64_t)i * n + c];
+            post[i] = fi + (eq[i] - fi) / tau +
+                      (1.0 - 0.5 / tau) * weight(i) * s;
+          }
+        }
+
+        /* streaming, eq. (4) */
+        const int pos[3] = {x, y, z};
+        for (int i = 0; i < Q; ++i) {
+          int dst[3];
+          int wall_axis = -1, wall_face = 0;
+          for (int a = 0; a < 3; ++a) {
+            int d = pos[a] + C[i][a];
+            if (d < 0 || d >= dims[a]) {
+              if (p->bc[a] == ORC_BC_PERIODIC) {
+                d = (d + dims[a]) % dims[a];
+              } else if (wall_axis < 0) {
+                wall_axis = a;
+                wall_face = d < 0 ? 0 : 1;
+              }
+            }
+            dst[a] = d;
+          }
+          if (wall_axis < 0) {
+            f_out[(int64_t)i * n + cell_index(p, dst[0], dst[1], dst[2])] =
+                post[i];
+          } else {
+            int o = opposite(i);
+            const double* uw = p->wall_u[wall_axis][wall_face];
+            double eu = C[o][0] * uw[0] + C[o][1] * uw[1] + C[o][2] * uw[2];
+            f_out[(int64_t)o * n + c] =
+                post[i] + 6.0 * weight(o) * p->rho_wall * eu;
+          }
+        }
+      }
+}
+
+/* Sums of mass and momentum over the box: out = {sum rho, sum rho U}. */
+void orc_sums(const orc_params* p, const double* f, double out[4]) {
+  const int64_t n = ncells(p);
+  double s[4] = {0, 0, 0, 0};
+  for (int64_t c = 0; c < n; ++c)
+    for (int i = 0; i < Q; ++i) {
+      double fi = f[(int64_t)i * n + c];
+      s[0] += fi;
+      for (int a = 0; a < 3; ++a) s[1 + a] += C[i][a] * fi;
+    }
+  for (int k = 0; k < 4; ++k) out[k] = s[k];
+}
+
+/* ---------------------------------------------------------------------------
+ * Peskin's 4-point discrete delta (§3), with the outer-branch reading
+ * sqrt(-7 + 12|r| - 4 r^2); zero for |r| >= 2.
+ * ------------------------------------------------------------------------- */
+double orc_delta(double r) {
+  double a = fabs(r);
+  if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
+  if (a <= 2.0) {
+    double q = -7.0 + 12.0 * a - 4.0 * a * a;
+    if (q < 0.0) q = 0.0; /* rounding at a = 2 */
+    return (5.0 - 2.0 * a - sqrt(q)) / 8.0;
+  }
+  return 0.0;
+}
+
+/* Cell coordinate on an axis: wraps on periodic axes; on bounce-back axes a
+ * coordinate outside the box is reported with -1. */
+static int axis_cell(const orc_params* p, int a, long v) {
+  const int dims[3] = {p->nx, p->ny, p->nz};
+  long d = dims[a];
+  if (v >= 0 && v < d) return (int)v;
+  if (p->bc[a] == ORC_BC_PERIODIC) return (int)(((v % d) + d) % d);
+  return -1;
+}
+
+/*
+ * Window of one Lagrangian point: the 5x5x5 cells centred on the nearest
+ * cell (Algorithm 2); cells at distance >= 2 on some axis get weight 0.
+ * Calls fn(cell, weight) for every cell with a nonzero weight.  Returns
+ * ORC_ERR_DOMAIN if a nonzero weight would fall outside a walled box.
+ */
+typedef struct {
+  int64_t cell[125];
+  double w[125];
+  int count;
+} orc_window;
+
+static int point_window(const orc_params* p, const double x[3], orc_window* out) {
+  long base[3];
+  double wa[3][5];
+  int ca[3][5];
+  for (int a = 0; a < 3; ++a) {
+    base[a] = lround(x[a]);
+    for (int j = 0; j < 5; ++j) {
+      long X = base[a] - 2 + j;
+      wa[a][j] = orc_delta(x[a] - (double)X);
+      ca[a][j] = axis_cell(p, a, X);
+      if (wa[a][j] != 0.0 && ca[a][j] < 0) return ORC_ERR_DOMAIN;
+    }
+  }
+  out->count = 0;
+  for (int k = 0; k < 5; ++k)
+    for (int j = 0; j < 5; ++j)
+      for (int i = 0; i < 5; ++i) {
+        double w = wa[0][i] * wa[1][j] * wa[2][k];
+        if (w == 0.0) continue;
+        out->cell[out->count] = cell_index(p, ca[0][i], ca[1][j], ca[2][k]);
+        out->w[out->count] = w;
+        out->count++;
+      }
+  return ORC_OK;
+}
+
+/* Interpolation (§3): u(k) = sum_X U(X) w(x-X) w(y-Y) w(z-Z).
+ * x: [n][3] point positions; U: [3][ncell]; u_out: [n][3]. */
+int orc_interpolate(const orc_params* p, int64_t npts, const double* x,
+                    const double* U, double* u_out) {
+  const int64_t n = ncells(p);
+  int err = ORC_OK;
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < npts; ++k) {
+    orc_window win;
+    if (point_window(p, x + 3 * k, &win) != ORC_OK) {
+#pragma omp atomic write
+      err = ORC_ERR_DOMAIN;
+      continue;
+    }
+    double u[3] = {0, 0, 0};
+    for (int t = 0; t < win.count; ++t)
+      for (int a = 0; a < 3; ++a) u[a] += U[(int64_t)a * n + win.cell[t]] * win.w[t];
+    for (int a = 0; a < 3; ++a) u_out[3 * k + a] = u[a];
+  }
+  return err;
+}
+
+/* Spreading (§3): acc(X) += sum_k v(k) w(x-X) w(y-Y) w(z-Z).
+ * v: [n][3]; acc: [3][ncell], accumulated in place.  Serial over points. */
+int orc_spread(const orc_params* p, int64_t npts, const double* x,
+               const double* v, double* acc) {
+  const int64_t n = ncells(p);
+  orc_window win;
+  for (int64_t k = 0; k < npts; ++k) {
+    if (point_window(p, x + 3 * k, &win) != ORC_OK) return ORC_ERR_DOMAIN;
+    for (int t = 0; t < win.count; ++t)
+      for (int a = 0; a < 3; ++a)
+        acc[(int64_t)a * n + win.cell[t]] += v[3 * k + a] * win.w[t];
+  }
+  return ORC_OK;
+}
+
+/* ---------------------------------------------------------------------------
+ * Rigid motion (§4.2, Algorithm 1): rotation by theta_n = theta0 + omega n
+ * about the body axis through its centre; point velocity by the finite
+ * difference of positions between steps n and n-1.
+ * rest: [n][3] relative to the body centre; body_off: [nb+1] point ranges.
+ * ------------------------------------------------------------------------- */
+static void rotate(const double axis_in[3], double theta, const double r[3],
+                   double out[3]) {
+  double len = sqrt(axis_in[0] * axis_in[0] + axis_in[1] * axis_in[1] +
+                    axis_in[2] * axis_in[2]);
+  double a[3] = {axis_in[0] / len, axis_in[1] / len, axis_in[2] / len};
+  double c = cos(theta), s = sin(theta);
+  double adr = a[0] * r[0] + a[1] * r[1] + a[2] * r[2];
+  double axr[3] = {a[1] * r[2] - a[2] * r[1], a[2] * r[0] - a[0] * r[2],
+                   a[0] * r[1] - a[1] * r[0]};
+  for (int i = 0; i < 3; ++i)
+    out[i] = r[i] * c + axr[i] * s + a[i] * adr * (1.0 - c); /* Rodrigues */
+}
+
+void orc_kinematics(int64_t npts, const double* rest, const int64_t* body_off,
+                    int32_t nbodies, const orc_body* bodies, int64_t step,
+                    double* x_out, double* ub_out) {
+  for (int b = 0; b < nbodies; ++b) {
+    const orc_body* B = &bodies[b];
+    double th_now = B->theta0 + B->omega * (double)step;
+    double th_prev = B->theta0 + B->omega * (double)(step - 1);
+    for (int64_t k = body_off[b]; k < body_off[b + 1] && k < npts; ++k) {
+      double now[3], prev[3];
+      rotate(B->axis, th_now, rest + 3 * k, now);
+      rotate(B->axis, th_prev, rest + 3 * k, prev);
+      for (int a = 0; a < 3; ++a) {
+        x_out[3 * k + a] = B->center[a] + now[a];
+        ub_out[3 * k + a] = now[a] - prev[a];
+      }
+    }
+  }
+}
+
+/* ---------------------------------------------------------------------------
+ * Multi-direct forcing (§3; Algorithms 1 and 2), n_iter sweeps:
+ *   U_0 = U;  du = 0
+ *   for it in 0 .. n_iter-1:
+ *     u_it(k) = interpolation of U_it at x(k)
+ *     g_it(k) = u_b(k) - u_it(k)
+ *     du(k)  += s(k) g_it(k)
+ *     if it < n_iter-1:  U_{it+1} = U_it + spread of s(k) g_it(k)
+ *                        (or of g_it(k) with ORC_IBM_INNER_UNWEIGHTED)
+ *   G = spread of du(k)
+ * U0 is not modified.  resid[it] = sum_k s(k) |g_it(k)|^2.
+ * G_out: [3][ncell] overwritten.  du_out, g_out: [n][3] (nullable).
+ * ------------------------------------------------------------------------- */
+int orc_ibm(const orc_params* p, int64_t npts, const double* x,
+            const double* ub, const double* s, const double* U0,
+            int32_t n_iter, int32_t flags, double* G_out, double* du_out,
+            double* g_out, double* resid) {
+  const int64_t n = ncells(p);
+  double* U = (double*)malloc(sizeof(double) * 3 * n);
+  double* u = (double*)malloc(sizeof(double) * 3 * (npts > 0 ? npts : 1));
+  double* g = (double*)malloc(sizeof(double) * 3 * (npts > 0 ? npts : 1));
+  double* v = (double*)malloc(sizeof(double) * 3 * (npts > 0 ? npts : 1));
+  double* du = (double*)calloc(3 * (npts > 0 ? npts : 1), sizeof(double));
+  int err = ORC_OK;
+  memcpy(U, U0, sizeof(double) * 3 * n);
+  for (int it = 0; it < n_iter && err == ORC_OK; ++it) {
+    err = orc_interpolate(p, npts, x, U, u);
+    if (err != ORC_OK) break;
+    double r = 0.0;
+    for (int64_t k = 0; k < npts; ++k) {
+      double m = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        g[3 * k + a] = ub[3 * k + a] - u[3 * k + a];
+        du[3 * k + a] += s[k] * g[3 * k + a];
+        m += g[3 * k + a] * g[3 * k + a];
+      }
+      r += s[k] * m;
+    }
+    if (resid) resid[it] = r;
+    if (it < n_iter - 1) {
+      for (int64_t k = 0; k < npts; ++k)
+        for (int a = 0; a < 3; ++a)
+          v[3 * k + a] = (flags & ORC_IBM_INNER_UNWEIGHTED)
+                             ? g[3 * k + a]
+                             : s[k] * g[3 * k + a];
+      err = orc_spread(p, npts, x, v, U);
+    }
+  }
+  if (err == ORC_OK) {
+    memset(G_out, 0, sizeof(double) * 3 * n);
+    err = orc_spread(p, npts, x, du, G_out);
+  }
+  if (err == ORC_OK) {
+    if (du_out) memcpy(du_out, du, sizeof(double) * 3 * npts);
+    if (g_out) memcpy(g_out, g, sizeof(double) * 3 * npts);
+  }
+  free(U);
+  free(u);
+  free(g);
+  free(v);
+  free(du);
+  return err;
+}
+
+/* ---------------------------------------------------------------------------
+ * One full time step (§2 step list, with §3 for step 2):
+ *   1. rho, U from f                       (eq. 1)
+ *   2. G = immersedBoundary(object, U)     (§3; skipped when npts == 0)
+ *   3-5. forcing, equilibrium, collision   (eqs. 2-3)
+ *   6. streaming                           (eq. 4)
+ * f (post-stream state at time `step`) is replaced by the state at step+1.
+ * Optional outputs (NULL to skip): sums of f before the step; G; point
+ * positions, velocities, last deficit and accumulated correction; residuals.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int64_t npts;
+  const double* rest;      /* [n][3] */
+  const double* area;      /* [n]    */
+  const int64_t* body_off; /* [nb+1] */
+  int32_t nbodies;
+  int32_t n_iter;
+  int32_t flags;
+  int32_t pad_;
+  const orc_body* bodies;
+} orc_points;
+
+typedef struct {
+  double* sums;  /* [4] */
+  double* G;     /* [3][ncell] */
+  double* x;     /* [n][3] */
+  double* ub;    /* [n][3] */
+  double* g;     /* [n][3] */
+  double* du;    /* [n][3] */
+  double* resid; /* [n_iter] */
+} orc_step_out;
+
+int orc_step(const orc_params* p, double* f, const orc_points* pts,
+             int64_t step, const orc_step_out* out) {
+  const int64_t n = ncells(p);
+  double* fn = (double*)malloc(sizeof(double) * Q * n);
+  double* G = NULL;
+  int err = ORC_OK;
+  if (out && out->sums) orc_sums(p, f, out->sums);
+  if (pts && pts->npts > 0) {
+    int64_t m = pts->npts;
+    double* rho = (double*)malloc(sizeof(double) * n);
+    double* U = (double*)malloc(sizeof(double) * 3 * n);
+    double* x = (double*)malloc(sizeof(double) * 3 * m);
+    double* ub = (double*)malloc(sizeof(double) * 3 * m);
+    G = (double*)malloc(sizeof(double) * 3 * n);
+    orc_moments(p, f, rho, U);
+    orc_kinematics(m, pts->rest, pts->body_off, pts->nbodies, pts->bodies,
+                   step, x, ub);
+    err = orc_ibm(p, m, x, ub, pts->area, U, pts->n_iter, pts->flags, G,
+                  out ? out->du : NULL, out ? out->g : NULL,
+                  out ? out->resid : NULL);
+    if (out && out->x) memcpy(out->x, x, sizeof(double) * 3 * m);
+    if (out && out->ub) memcpy(out->ub, ub, sizeof(double) * 3 * m);
+    free(rho);
+    free(U);
+    free(x);
+    free(ub);
+  }
+  if (err == ORC_OK) {
+    if (out && out->G) {
+      if (G)
+        memcpy(out->G, G, sizeof(double) * 3 * n);
+      else
+        memset(out->G, 0, sizeof(double) * 3 * n);
+    }
+    orc_collide_stream(p, f, G, fn);
+    memcpy(f, fn, sizeof(double) * Q * n);
+  }
+  free(G);
+  free(fn);
+  return err;
+}
+
+/* n_steps full steps starting at time `step0`; sums_hist (nullable) gets
+ * the sums before each step, [n_steps][4]. */
+int orc_run(const orc_params* p, double* f, const orc_points* pts,
+            int64_t step0, int64_t n_steps, double* sums_hist) {
+  for (int64_t s = 0; s < n_steps; ++s) {
+    orc_step_out o;
+    memset(&o, 0, sizeof(o));
+    o.sums = sums_hist ? sums_hist + 4 * s : NULL;
+    int err = orc_step(p, f, pts, step0 + s, &o);
+    if (err != ORC_OK) return err;
+  }
+  return ORC_OK;
+}

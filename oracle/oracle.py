@@ -1,0 +1,286 @@
+"""ctypes front end of the FP64 oracle (``lbm_ibm_oracle.c``).
+
+Test infrastructure: only ``tests/``, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` use it.  It builds the C source with gcc on first
+use (or when the source is newer than the shared library) and exposes numpy
+functions whose names follow the C entry points.
+
+Array conventions (shared with the HIP library's export format only by
+definition, not by code):
+  populations f: float64 [19, nz, ny, nx], D3Q19 order of the C source
+  rho: [nz, ny, nx]; U, G: [3, nz, ny, nx]
+  points: [n, 3]; bodies: [nb, 8] = (cx, cy, cz, ax, ay, az, theta0, omega)
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lbm_ibm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+BC_PERIODIC, BC_BOUNCEBACK = 0, 1
+FORCE_GUO, FORCE_SHIFT = 0, 1
+IBM_INNER_UNWEIGHTED = 1
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (OpenMP, -O2, strict IEEE double)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Params(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("nz", ct.c_int32),
+                ("bc", ct.c_int32 * 3), ("forcing", ct.c_int32), ("pad_", ct.c_int32),
+                ("tau", ct.c_double), ("rho_wall", ct.c_double),
+                ("wall_u", ct.c_double * 18), ("g_ext", ct.c_double * 3)]
+
+
+class _Points(ct.Structure):
+    _fields_ = [("npts", ct.c_int64), ("rest", ct.c_void_p), ("area", ct.c_void_p),
+                ("body_off", ct.c_void_p), ("nbodies", ct.c_int32), ("n_iter", ct.c_int32),
+                ("flags", ct.c_int32), ("pad_", ct.c_int32), ("bodies", ct.c_void_p)]
+
+
+class _StepOut(ct.Structure):
+    _fields_ = [("sums", ct.c_void_p), ("G", ct.c_void_p), ("x", ct.c_void_p),
+                ("ub", ct.c_void_p), ("g", ct.c_void_p), ("du", ct.c_void_p),
+                ("resid", ct.c_void_p)]
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            lib = ct.CDLL(build())
+            P = ct.POINTER(Params)
+            vp, i64, i32, d = ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_double
+            lib.orc_d3q19.argtypes = [vp, vp, vp]
+            lib.orc_equilibrium.argtypes = [d, vp, vp]
+            lib.orc_moments.argtypes = [P, vp, vp, vp]
+            lib.orc_init_equilibrium.argtypes = [P, d, vp, vp]
+            lib.orc_collide_stream.argtypes = [P, vp, vp, vp]
+            lib.orc_sums.argtypes = [P, vp, vp]
+            lib.orc_delta.argtypes = [d]
+            lib.orc_delta.restype = d
+            lib.orc_interpolate.argtypes = [P, i64, vp, vp, vp]
+            lib.orc_interpolate.restype = ct.c_int
+            lib.orc_spread.argtypes = [P, i64, vp, vp, vp]
+            lib.orc_spread.restype = ct.c_int
+            lib.orc_kinematics.argtypes = [i64, vp, vp, i32, vp, i64, vp, vp]
+            lib.orc_ibm.argtypes = [P, i64, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp]
+            lib.orc_ibm.restype = ct.c_int
+            lib.orc_step.argtypes = [P, vp, ct.POINTER(_Points), i64, ct.POINTER(_StepOut)]
+            lib.orc_step.restype = ct.c_int
+            lib.orc_run.argtypes = [P, vp, ct.POINTER(_Points), i64, i64, vp]
+            lib.orc_run.restype = ct.c_int
+            _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc):
+    if rc != 0:
+        raise OracleError("oracle returned %d (support outside a walled box)" % rc)
+
+
+def params(shape, tau, bc=(0, 0, 0), forcing=FORCE_GUO, rho_wall=1.0,
+           wall_u=None, g_ext=(0.0, 0.0, 0.0)) -> Params:
+    """shape = (nx, ny, nz); wall_u[axis][face][component] (face 0 = low)."""
+    p = Params()
+    p.nx, p.ny, p.nz = (int(v) for v in shape)
+    for a in range(3):
+        p.bc[a] = int(bc[a])
+    p.forcing = int(forcing)
+    p.tau = float(tau)
+    p.rho_wall = float(rho_wall)
+    wu = np.zeros((3, 2, 3)) if wall_u is None else np.asarray(wall_u, dtype=np.float64)
+    for i, v in enumerate(wu.reshape(-1)):
+        p.wall_u[i] = float(v)
+    for a in range(3):
+        p.g_ext[a] = float(g_ext[a])
+    return p
+
+
+def grid_shape(p: Params):
+    return (p.nz, p.ny, p.nx)
+
+
+def d3q19():
+    lib = _load()
+    e = np.zeros((19, 3), np.int32)
+    w = np.zeros(19)
+    opp = np.zeros(19, np.int32)
+    lib.orc_d3q19(_ptr(e), _ptr(w), _ptr(opp))
+    return e, w, opp
+
+
+def delta(r):
+    lib = _load()
+    r = np.asarray(r, dtype=np.float64)
+    return np.vectorize(lambda v: lib.orc_delta(float(v)), otypes=[np.float64])(r)
+
+
+def equilibrium(rho, u):
+    lib = _load()
+    u = _f64(u)
+    eq = np.zeros(19)
+    lib.orc_equilibrium(float(rho), _ptr(u), _ptr(eq))
+    return eq
+
+
+def init_equilibrium(p, rho0=1.0, u0=(0.0, 0.0, 0.0)):
+    lib = _load()
+    f = np.zeros((19,) + grid_shape(p))
+    u0 = _f64(u0)
+    lib.orc_init_equilibrium(ct.byref(p), float(rho0), _ptr(u0), _ptr(f))
+    return f
+
+
+def moments(p, f):
+    lib = _load()
+    f = _f64(f)
+    rho = np.zeros(grid_shape(p))
+    U = np.zeros((3,) + grid_shape(p))
+    lib.orc_moments(ct.byref(p), _ptr(f), _ptr(rho), _ptr(U))
+    return rho, U
+
+
+def collide_stream(p, f, G=None):
+    lib = _load()
+    f = _f64(f)
+    out = np.zeros_like(f)
+    Gc = None if G is None else _f64(G)
+    lib.orc_collide_stream(ct.byref(p), _ptr(f), _ptr(Gc), _ptr(out))
+    return out
+
+
+def sums(p, f):
+    lib = _load()
+    f = _f64(f)
+    out = np.zeros(4)
+    lib.orc_sums(ct.byref(p), _ptr(f), _ptr(out))
+    return out
+
+
+def interpolate(p, x, U):
+    lib = _load()
+    x = _f64(x).reshape(-1, 3)
+    U = _f64(U)
+    u = np.zeros_like(x)
+    _check(lib.orc_interpolate(ct.byref(p), x.shape[0], _ptr(x), _ptr(U), _ptr(u)))
+    return u
+
+
+def spread(p, x, v, acc=None):
+    lib = _load()
+    x = _f64(x).reshape(-1, 3)
+    v = _f64(v).reshape(-1, 3)
+    acc = np.zeros((3,) + grid_shape(p)) if acc is None else _f64(acc).copy()
+    _check(lib.orc_spread(ct.byref(p), x.shape[0], _ptr(x), _ptr(v), _ptr(acc)))
+    return acc
+
+
+def kinematics(rest, body_off, bodies, step):
+    lib = _load()
+    rest = _f64(rest).reshape(-1, 3)
+    body_off = np.ascontiguousarray(body_off, dtype=np.int64)
+    bodies = _f64(bodies).reshape(-1, 8)
+    x = np.zeros_like(rest)
+    ub = np.zeros_like(rest)
+    lib.orc_kinematics(rest.shape[0], _ptr(rest), _ptr(body_off), bodies.shape[0],
+                       _ptr(bodies), int(step), _ptr(x), _ptr(ub))
+    return x, ub
+
+
+def ibm(p, x, ub, s, U0, n_iter=5, flags=0):
+    """Returns G [3,nz,ny,nx], du [n,3], g_last [n,3], resid [n_iter]."""
+    lib = _load()
+    x = _f64(x).reshape(-1, 3)
+    ub = _f64(ub).reshape(-1, 3)
+    s = _f64(s).reshape(-1)
+    U0 = _f64(U0)
+    n = x.shape[0]
+    G = np.zeros((3,) + grid_shape(p))
+    du = np.zeros((n, 3))
+    g = np.zeros((n, 3))
+    resid = np.zeros(max(int(n_iter), 1))
+    _check(lib.orc_ibm(ct.byref(p), n, _ptr(x), _ptr(ub), _ptr(s), _ptr(U0),
+                       int(n_iter), int(flags), _ptr(G), _ptr(du), _ptr(g), _ptr(resid)))
+    return G, du, g, resid[:n_iter]
+
+
+class Points:
+    """Lagrangian surface description handed to the step functions."""
+
+    def __init__(self, rest, area, body_off, bodies, n_iter=5, flags=0):
+        self.rest = _f64(rest).reshape(-1, 3)
+        self.area = _f64(area).reshape(-1)
+        self.body_off = np.ascontiguousarray(body_off, dtype=np.int64)
+        self.bodies = _f64(bodies).reshape(-1, 8)
+        self.n_iter = int(n_iter)
+        self.flags = int(flags)
+        self.c = _Points(self.rest.shape[0], _ptr(self.rest), _ptr(self.area),
+                         _ptr(self.body_off), self.bodies.shape[0], self.n_iter,
+                         self.flags, 0, _ptr(self.bodies))
+
+    @property
+    def n(self):
+        return self.rest.shape[0]
+
+
+def step(p, f, pts=None, step_index=0, outputs=True):
+    """One full time step in place on f (float64 [19,nz,ny,nx], C-contiguous).
+
+    Returns a dict with sums (before the step), G, x, ub, g, du, resid."""
+    lib = _load()
+    assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"]
+    o = _StepOut()
+    res = {}
+    if outputs:
+        res["sums"] = np.zeros(4)
+        res["G"] = np.zeros((3,) + grid_shape(p))
+        o.sums, o.G = _ptr(res["sums"]), _ptr(res["G"])
+        if pts is not None and pts.n > 0:
+            for k in ("x", "ub", "g", "du"):
+                res[k] = np.zeros((pts.n, 3))
+            res["resid"] = np.zeros(max(pts.n_iter, 1))
+            o.x, o.ub, o.g, o.du = (_ptr(res[k]) for k in ("x", "ub", "g", "du"))
+            o.resid = _ptr(res["resid"])
+    pc = ct.byref(pts.c) if pts is not None else None
+    _check(lib.orc_step(ct.byref(p), _ptr(f), pc, int(step_index), ct.byref(o)))
+    return res
+
+
+def run(p, f, pts=None, step0=0, n_steps=1):
+    """n_steps steps in place on f; returns the sums before each step."""
+    lib = _load()
+    assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"]
+    hist = np.zeros((int(n_steps), 4))
+    pc = ct.byref(pts.c) if pts is not None else None
+    _check(lib.orc_run(ct.byref(p), _ptr(f), pc, int(step0), int(n_steps), _ptr(hist)))
+    return hist

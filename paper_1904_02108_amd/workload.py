@@ -1,0 +1,221 @@
+"""Seeded synthetic inputs for the LBM-IBM path.
+
+This module only builds inputs: surface samplings of rotating propellers, the
+rigid-body descriptions that drive them, and random lattice states, force
+fields and point clouds for the parity tests.  It contains none of the
+method's arithmetic (no lattice constants, no kernels, no motion law); the
+GPU library and the oracle each apply the method to these inputs on their own.
+
+The propeller stands in for the paper's CAD propeller mesh, which is not
+available (§6 describes a Blender model of 3930 points): a hub cylinder with
+two end caps plus three flat single-sheet blades in planes through the axis,
+120 degrees apart.  Every surface is sampled at spacing about ``h`` and each
+point carries the area of its surface component divided by the component's
+point count (the s(k) of §3).
+
+All randomness uses numpy's PCG64 generator seeded explicitly.
+
+Array conventions:
+  rest   float32 [n, 3]  point positions relative to the body centre
+  area   float32 [n]     s(k)
+  body_off int64 [nb+1]  points of body b are rest[body_off[b]:body_off[b+1]]
+  bodies float64 [nb, 8] (cx, cy, cz, ax, ay, az, theta0, omega)
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BC_PERIODIC, BC_BOUNCEBACK = 0, 1
+FORCE_GUO, FORCE_SHIFT = 0, 1
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def propeller_surface(hub_radius, hub_length, blade_length, blade_chord, h,
+                      n_blades=3):
+    """Canonical propeller (axis = +z, centre at the origin).
+
+    Returns (points float64 [n,3], area float64 [n])."""
+    pts, area = [], []
+    # hub lateral surface: rings along z
+    n_theta = int(math.ceil(2.0 * math.pi * hub_radius / h))
+    n_z = int(math.floor(hub_length / h)) + 1
+    zs = np.linspace(-hub_length / 2.0, hub_length / 2.0, n_z)
+    th = 2.0 * math.pi * np.arange(n_theta) / n_theta
+    zz, tt = np.meshgrid(zs, th, indexing="ij")
+    lat = np.stack([hub_radius * np.cos(tt), hub_radius * np.sin(tt), zz], -1).reshape(-1, 3)
+    pts.append(lat)
+    area.append(np.full(len(lat), 2.0 * math.pi * hub_radius * hub_length / len(lat)))
+    # end caps: concentric rings inside the rim (the rim belongs to the lateral surface)
+    m = int(math.ceil(hub_radius / h))
+    for zc in (-hub_length / 2.0, hub_length / 2.0):
+        cap = []
+        for j in range(m):
+            rj = hub_radius * j / m
+            nj = max(1, int(math.ceil(2.0 * math.pi * rj / h)))
+            a = 2.0 * math.pi * np.arange(nj) / nj
+            cap.append(np.stack([rj * np.cos(a), rj * np.sin(a), np.full(nj, zc)], -1))
+        cap = np.concatenate(cap)
+        pts.append(cap)
+        area.append(np.full(len(cap), math.pi * hub_radius ** 2 / len(cap)))
+    # blades: flat sheets spanned by the radial direction and the axis
+    n_r = int(math.floor((blade_length - h) / h + 1e-9)) + 1
+    n_c = int(math.floor(blade_chord / h + 1e-9)) + 1
+    radii = hub_radius + h * (1 + np.arange(n_r))
+    chord = np.linspace(-blade_chord / 2.0, blade_chord / 2.0, n_c)
+    for b in range(n_blades):
+        phi = 2.0 * math.pi * b / n_blades
+        rr, cc = np.meshgrid(radii, chord, indexing="ij")
+        bl = np.stack([rr * math.cos(phi), rr * math.sin(phi), cc], -1).reshape(-1, 3)
+        pts.append(bl)
+        area.append(np.full(len(bl), blade_length * blade_chord / len(bl)))
+    return np.concatenate(pts), np.concatenate(area)
+
+
+def _frame_to_axis(axis):
+    """A rotation taking +z to the unit vector ``axis`` (input preparation)."""
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    z = np.array([0.0, 0.0, 1.0])
+    v = np.cross(z, a)
+    c = float(np.dot(z, a))
+    if np.linalg.norm(v) < 1e-12:
+        return np.eye(3) if c > 0 else np.diag([1.0, -1.0, -1.0])
+    vx = np.array([[0, -v[2], v[1]], [v[2], 0, -v[0]], [-v[1], v[0], 0]])
+    return np.eye(3) + vx + vx @ vx * (1.0 / (1.0 + c))
+
+
+@dataclass
+class Workload:
+    name: str
+    shape: tuple            # (nx, ny, nz)
+    tau: float
+    bc: tuple               # per axis
+    forcing: int = FORCE_GUO
+    rest: np.ndarray = None
+    area: np.ndarray = None
+    body_off: np.ndarray = None
+    bodies: np.ndarray = None
+    n_iter: int = 5
+    steps: int = 1
+    h: float = 1.0
+    notes: dict = field(default_factory=dict)
+
+    @property
+    def n_points(self):
+        return 0 if self.rest is None else int(self.rest.shape[0])
+
+    @property
+    def n_cells(self):
+        nx, ny, nz = self.shape
+        return nx * ny * nz
+
+
+def _assemble(props):
+    """props: list of (canonical points, area, centre, axis, theta0, omega)."""
+    rest, area, off, bodies = [], [], [0], []
+    for pts, ar, centre, axis, th0, om in props:
+        Qm = _frame_to_axis(axis)
+        rest.append(pts @ Qm.T)
+        area.append(ar)
+        off.append(off[-1] + len(pts))
+        a = np.asarray(axis, dtype=np.float64)
+        a = a / np.linalg.norm(a)
+        bodies.append([centre[0], centre[1], centre[2], a[0], a[1], a[2], th0, om])
+    return (np.concatenate(rest).astype(np.float32), np.concatenate(area).astype(np.float32),
+            np.asarray(off, dtype=np.int64), np.asarray(bodies, dtype=np.float64))
+
+
+def config(name, h=None, seed=0, forcing=FORCE_GUO):
+    """Workloads of the benchmark family.
+
+    c0  32^3 periodic, tau 0.6, one propeller (hub r 3, L 6, blades 10x3), h 1.0,
+        omega 0.01 about z, 5 iterations, 50 steps.
+    c1  128^3, x periodic, y/z bounce-back walls, tau 0.55, propeller x4
+        (hub r 12, L 24, blades 40x12) at the centre, h 0.7, omega 0.005,
+        5 iterations, 1000 steps.
+    c2  256^3 periodic, tau 0.55, 64 propellers of c1 size at 32 + 64 {0..3}^3,
+        axes uniform on the sphere, theta0 ~ U[0, 2 pi), omega ~ U[0.002, 0.008]
+        (seeded), 5 iterations, 500 steps.  h 0.7 gives the literal sampling
+        (about 0.55M points); c2_dense uses h 0.41 (about 25k points per
+        propeller, 1.6M in total).
+    """
+    if name == "c0":
+        hh = 1.0 if h is None else h
+        pts, ar = propeller_surface(3.0, 6.0, 10.0, 3.0, hh)
+        rest, area, off, bodies = _assemble([(pts, ar, (16.0, 16.0, 16.0), (0, 0, 1), 0.0, 0.01)])
+        return Workload("c0", (32, 32, 32), 0.6, (0, 0, 0), forcing, rest, area, off, bodies,
+                        5, 50, hh)
+    if name == "c1":
+        hh = 0.7 if h is None else h
+        pts, ar = propeller_surface(12.0, 24.0, 40.0, 12.0, hh)
+        rest, area, off, bodies = _assemble([(pts, ar, (64.0, 64.0, 64.0), (0, 0, 1), 0.0, 0.005)])
+        return Workload("c1", (128, 128, 128), 0.55, (0, 1, 1), forcing, rest, area, off, bodies,
+                        5, 1000, hh)
+    if name in ("c2", "c2_dense"):
+        hh = (0.7 if name == "c2" else 0.41) if h is None else h
+        rng = _rng(seed)
+        pts, ar = propeller_surface(12.0, 24.0, 40.0, 12.0, hh)
+        props = []
+        for k in range(4):
+            for j in range(4):
+                for i in range(4):
+                    v = rng.normal(size=3)
+                    axis = v / np.linalg.norm(v)
+                    th0 = rng.uniform(0.0, 2.0 * math.pi)
+                    om = rng.uniform(0.002, 0.008)
+                    props.append((pts, ar, (32.0 + 64 * i, 32.0 + 64 * j, 32.0 + 64 * k), axis, th0, om))
+        rest, area, off, bodies = _assemble(props)
+        return Workload(name, (256, 256, 256), 0.55, (0, 0, 0), forcing, rest, area, off, bodies,
+                        5, 500, hh, {"seed": seed})
+    raise KeyError(name)
+
+
+def tiny_propeller_case(shape=(24, 20, 28), bc=(0, 0, 0), h=1.0, omega=0.02, theta0=0.3,
+                        axis=(0.3, -0.2, 0.93), centre=None, tau=0.7, forcing=FORCE_GUO):
+    """A small, off-axis propeller on a box whose sides are not tile multiples."""
+    nx, ny, nz = shape
+    c = (nx / 2 + 0.37, ny / 2 - 0.21, nz / 2 + 0.13) if centre is None else centre
+    pts, ar = propeller_surface(2.0, 4.0, 5.0, 2.0, h)
+    rest, area, off, bodies = _assemble([(pts, ar, c, axis, theta0, omega)])
+    return Workload("tiny", tuple(shape), tau, tuple(bc), forcing, rest, area, off, bodies, 5, 1, h)
+
+
+def random_populations(shape, seed, amp=0.05, u_amp=0.05, weights=None):
+    """Populations near a random equilibrium-like state: w_i (1 + perturbation).
+
+    weights: the 19 lattice weights in the library's direction order must be
+    supplied by the caller (this module holds no lattice constants).
+    Returns float64 [19, nz, ny, nx]."""
+    nx, ny, nz = shape
+    rng = _rng(seed)
+    w = np.asarray(weights, dtype=np.float64).reshape(19, 1, 1, 1)
+    pert = amp * rng.uniform(-1.0, 1.0, size=(19, nz, ny, nx))
+    return w * (1.0 + pert)
+
+
+def random_field(shape, seed, amp=1e-3):
+    """Random vector field [3, nz, ny, nx] (e.g. a prescribed force G)."""
+    nx, ny, nz = shape
+    return amp * _rng(seed).uniform(-1.0, 1.0, size=(3, nz, ny, nx))
+
+
+def random_points(shape, n, seed, margin=0.0, special=True):
+    """n random points in the box (float64 [n,3]); with ``special`` some sit at
+    exact integer and half-integer coordinates and near the periodic seams."""
+    nx, ny, nz = shape
+    rng = _rng(seed)
+    lo = np.array([margin] * 3)
+    hi = np.array([nx, ny, nz], dtype=np.float64) - margin
+    x = lo + (hi - lo) * rng.uniform(size=(n, 3))
+    if special and n >= 8:
+        x[0] = np.floor(x[0])
+        x[1] = np.floor(x[1]) + 0.5
+        x[2] = [0.0, 0.0, 0.0] if margin == 0 else x[2]
+        x[3] = [nx - 1e-3, ny - 0.5, nz - 1.0] if margin == 0 else x[3]
+    return x

@@ -1,0 +1,257 @@
+"""Pins of the oracle's immersed-boundary part (§3, Algorithms 1-2): the delta
+kernel's identities, exact interpolation of linear fields, the adjoint
+identity between interpolation and spreading, conservation of spread totals,
+closed forms of the iteration (isolated point, lattice-aligned plane), a
+matrix formulation of the iteration on tiny grids, and rigid-motion facts.
+CPU only."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1904_02108_amd import workload as W
+
+
+# --------------------------------------------------------------- delta kernel
+def test_delta_values_and_continuity():
+    d = O.delta
+    assert d(0.0) == 0.5
+    assert abs(d(1.0) - 0.25) < 1e-16
+    assert d(2.0) == 0.0 and d(2.5) == 0.0 and d(-3.0) == 0.0
+    assert abs(d(0.5) - (2 + np.sqrt(2)) / 8) < 1e-16
+    eps = 1e-9
+    assert abs(d(1 - eps) - d(1 + eps)) < 1e-8     # fails with the "-6" reading
+    assert abs(d(2 - eps)) < 1e-4
+    r = np.linspace(-2.5, 2.5, 101)
+    np.testing.assert_array_equal(d(r), d(-r))
+
+
+@pytest.mark.parametrize("r", [0.0, 0.1, 0.25, 0.5, 0.77, 0.999999, np.pi - 3])
+def test_delta_moment_identities(r):
+    """sum_j phi(r-j) = 1, sum_j (r-j) phi(r-j) = 0, even and odd partial
+    sums 1/2, sum_j phi(r-j)^2 = 3/8 (Peskin's construction)."""
+    j = np.arange(-4, 6)
+    w = O.delta(r - j)
+    assert abs(w.sum() - 1) < 1e-15
+    assert abs(((r - j) * w).sum()) < 1e-15
+    assert abs(w[j % 2 == 0].sum() - 0.5) < 1e-15
+    assert abs((w ** 2).sum() - 3 / 8) < 1e-15
+    assert np.count_nonzero(w) <= 4
+
+
+# --------------------------------------------------- interpolation / spreading
+def _rand_pts(shape, n, seed, margin=0.0):
+    return W.random_points(shape, n, seed, margin=margin)
+
+
+def test_linear_field_exact():
+    shape = (12, 11, 13)
+    nx, ny, nz = shape
+    p = O.params(shape, 0.7)
+    rng = np.random.default_rng(0)
+    a = rng.normal(size=3)
+    B = rng.normal(size=(3, 3))
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    X = np.stack([xx, yy, zz])
+    U = a[:, None, None, None] + np.einsum("cd,dzyx->czyx", B, X)
+    x = _rand_pts(shape, 40, 1, margin=2.6)
+    u = O.interpolate(p, x, U)
+    np.testing.assert_allclose(u, a + x @ B.T, atol=1e-12)
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1)])
+def test_adjoint_and_conservation(bc):
+    shape = (9, 10, 8)
+    p = O.params(shape, 0.7, bc=bc)
+    margin = 0.0 if bc[0] == 0 else 2.0
+    x = _rand_pts(shape, 30, 2, margin=margin)
+    rng = np.random.default_rng(3)
+    U = rng.normal(size=(3, 8, 10, 9))
+    v = rng.normal(size=(30, 3))
+    Sv = O.spread(p, x, v)
+    lhs = (O.interpolate(p, x, U) * v).sum()
+    rhs = (U * Sv).sum()
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
+    np.testing.assert_allclose(Sv.sum(axis=(1, 2, 3)), v.sum(0), atol=1e-12)
+
+
+def test_wall_domain_error():
+    p = O.params((10, 10, 10), 0.7, bc=(0, 1, 0))
+    with pytest.raises(O.OracleError):
+        O.interpolate(p, np.array([[5.0, 0.4, 5.0]]), np.zeros((3, 10, 10, 10)))
+    # exactly 1 cell from the wall the outer tap has weight 0 and is allowed
+    O.interpolate(p, np.array([[5.0, 1.0, 5.0]]), np.zeros((3, 10, 10, 10)))
+
+
+# ------------------------------------------------------------- iteration
+@pytest.mark.parametrize("flags", [0, O.IBM_INNER_UNWEIGHTED])
+@pytest.mark.parametrize("frac", [(0.0, 0.0, 0.0), (0.5, 0.5, 0.5), (0.13, 0.71, 0.42)])
+@pytest.mark.parametrize("s", [1.0, 0.49])
+def test_isolated_point_closed_form(flags, frac, s):
+    """One point in fluid at rest: g_n = (1 - a)^n u_b with a = s (3/8)^3
+    (a = (3/8)^3 for the unweighted inner spread), because sum phi^2 = 3/8 at
+    any offset.  Then du = s u_b (1 - (1-a)^N) / a and G = du W."""
+    shape = (12, 12, 12)
+    p = O.params(shape, 0.7)
+    x = np.array([[5.0, 6.0, 4.0]]) + np.array(frac)
+    ub = np.array([[0.02, -0.01, 0.005]])
+    N = 5
+    G, du, g, res = O.ibm(p, x, ub, np.array([s]), np.zeros((3, 12, 12, 12)), N, flags)
+    a = (27 / 512) * (1.0 if flags else s)
+    np.testing.assert_allclose(g, (1 - a) ** (N - 1) * ub, rtol=1e-13)
+    np.testing.assert_allclose(du, s * ub * (1 - (1 - a) ** N) / a, rtol=1e-13)
+    np.testing.assert_allclose(res, s * (ub ** 2).sum() * (1 - a) ** (2 * np.arange(N)), rtol=1e-12)
+    np.testing.assert_allclose(G.sum(axis=(1, 2, 3)), du[0], rtol=1e-13)
+    # the tap weights are products of 1-D weights: check one tap
+    X = np.floor(x[0]).astype(int)
+    wt = np.prod(O.delta(x[0] - X))
+    np.testing.assert_allclose(G[:, X[2], X[1], X[0]], du[0] * wt, rtol=1e-13)
+
+
+def test_isolated_point_value_s1():
+    """For s = 1 and five sweeps du / u_b = (1 - (485/512)^5) / (27/512)."""
+    p = O.params((10, 10, 10), 0.7)
+    _, du, _, _ = O.ibm(p, np.array([[4.3, 5.6, 5.1]]), np.array([[1.0, 0, 0]]),
+                        np.array([1.0]), np.zeros((3, 10, 10, 10)), 5, 0)
+    assert abs(du[0, 0] - 4.49973988) < 1e-8
+
+
+@pytest.mark.parametrize("off", [(0.0, 0.0, 3.0), (0.3, 0.8, 3.4)])
+def test_plane_of_points(off):
+    """A lattice-aligned plane of points at unit spacing in a periodic box:
+    g_n = (5/8)^n u_b and G(X) = du phi(Z - z0)."""
+    shape = (6, 5, 8)
+    nx, ny, nz = shape
+    p = O.params(shape, 0.7)
+    ii, jj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    x = np.stack([ii.ravel() + off[0], jj.ravel() + off[1], np.full(ii.size, off[2])], -1)
+    ub = np.tile([0.01, 0.02, -0.03], (len(x), 1))
+    N = 5
+    G, du, g, _ = O.ibm(p, x, ub, np.ones(len(x)), np.zeros((3, nz, ny, nx)), N, 0)
+    np.testing.assert_allclose(g, (5 / 8) ** (N - 1) * ub, rtol=1e-12)
+    ref_du = ub * sum((5 / 8) ** n for n in range(N))
+    np.testing.assert_allclose(du, ref_du, rtol=1e-12)
+    phiz = O.delta(np.arange(nz) - off[2])
+    np.testing.assert_allclose(G, ref_du[0][:, None, None, None] * phiz[None, :, None, None]
+                               * np.ones((1, 1, ny, nx)), atol=1e-15)
+
+
+def _probe_matrix(p, x):
+    """D[k, X]: weight of cell X in the interpolation at point k, found by
+    interpolating unit fields (no weight formula is retyped here)."""
+    nz, ny, nx = p.nz, p.ny, p.nx
+    n = nx * ny * nz
+    D = np.zeros((len(x), n))
+    for c in range(n):
+        U = np.zeros((3, n))
+        U[0, c] = 1.0
+        D[:, c] = O.interpolate(p, x, U.reshape(3, nz, ny, nx))[:, 0]
+    return D
+
+
+@pytest.mark.parametrize("flags", [0, O.IBM_INNER_UNWEIGHTED])
+def test_iteration_matrix_form(flags):
+    """On a tiny periodic grid the sweep equals its closed matrix form:
+    with M = D D^T diag(s) (D^T for the unweighted inner spread),
+    g_n = (I - M)^n g_0, du = diag(s) sum_{n<N} g_n, G = D^T du."""
+    shape = (6, 5, 7)
+    nx, ny, nz = shape
+    p = O.params(shape, 0.7)
+    x = _rand_pts(shape, 12, 5)
+    rng = np.random.default_rng(6)
+    s = rng.uniform(0.3, 1.2, 12)
+    ub = rng.normal(scale=0.02, size=(12, 3))
+    U0 = rng.normal(scale=0.01, size=(3, nz, ny, nx))
+    D = _probe_matrix(p, x)
+    np.testing.assert_allclose(D.sum(1), 1.0, atol=1e-14)    # partition of unity in 3-D
+    # spreading is the transpose of interpolation
+    v = rng.normal(size=(12, 3))
+    np.testing.assert_allclose(O.spread(p, x, v).reshape(3, -1), (D.T @ v).T, atol=1e-14)
+    N = 5
+    G, du, g, res = O.ibm(p, x, ub, s, U0, N, flags)
+    S = np.eye(12) if flags else np.diag(s)
+    M = D @ D.T @ S
+    g0 = ub - D @ U0.reshape(3, -1).T
+    gn = [np.linalg.matrix_power(np.eye(12) - M, n) @ g0 for n in range(N)]
+    np.testing.assert_allclose(g, gn[-1], atol=1e-14)
+    np.testing.assert_allclose(du, s[:, None] * sum(gn), atol=1e-14)
+    np.testing.assert_allclose(G.reshape(3, -1), (D.T @ du).T, atol=1e-14)
+    np.testing.assert_allclose(res, [(s[:, None] * q ** 2).sum() for q in gn], rtol=1e-11)
+
+
+def test_iteration_converges_to_no_slip():
+    """Iterated to convergence, the corrected velocity U0 + G interpolates to
+    the prescribed point velocities, and du solves D D^T du = u_b - D U0."""
+    shape = (8, 7, 6)
+    nx, ny, nz = shape
+    p = O.params(shape, 0.7)
+    x = _rand_pts(shape, 8, 11)
+    D = _probe_matrix(p, x)
+    lam = np.linalg.eigvalsh(D @ D.T)
+    s = np.full(8, 1.0 / lam.max())      # (I - M) has spectral radius < 1
+    rng = np.random.default_rng(12)
+    ub = rng.normal(scale=0.02, size=(8, 3))
+    U0 = rng.normal(scale=0.01, size=(3, nz, ny, nx))
+    N = int(np.ceil(np.log(1e-15) / np.log(1 - lam.min() / lam.max()))) + 5
+    G, du, _, _ = O.ibm(p, x, ub, s, U0, N, 0)
+    ref = np.linalg.solve(D @ D.T, ub - D @ U0.reshape(3, -1).T)
+    np.testing.assert_allclose(du, ref, atol=1e-10)
+    np.testing.assert_allclose(O.interpolate(p, x, U0 + G), ub, atol=1e-10)
+
+
+# ------------------------------------------------------------ rigid motion
+def test_kinematics_rigid_rotation():
+    rng = np.random.default_rng(7)
+    rest = rng.normal(scale=10, size=(50, 3))
+    axis = np.array([0.3, -0.5, 0.81])
+    a = axis / np.linalg.norm(axis)
+    omega, th0 = 0.013, 0.4
+    bodies = np.array([[100.0, 50.0, 20.0, *axis, th0, omega]])
+    off = np.array([0, 50])
+    for step in (0, 1, 17):
+        x, ub = O.kinematics(rest, off, bodies, step)
+        r = x - bodies[0, :3]
+        np.testing.assert_allclose(np.linalg.norm(r, axis=1), np.linalg.norm(rest, axis=1), rtol=1e-13)
+        np.testing.assert_allclose(r @ a, rest @ a, atol=1e-12)
+        rperp = np.linalg.norm(rest - np.outer(rest @ a, a), axis=1)
+        np.testing.assert_allclose(np.linalg.norm(ub, axis=1), 2 * rperp * np.sin(omega / 2), rtol=1e-10)
+        np.testing.assert_allclose(ub @ a, 0, atol=1e-12)
+        xp, _ = O.kinematics(rest, off, bodies, step - 1)
+        np.testing.assert_allclose(ub, x - xp, atol=1e-12)
+    # right-handed: +x rotated by pi/2 about +z goes to +y
+    x, _ = O.kinematics(np.array([[1.0, 0, 0]]), np.array([0, 1]),
+                        np.array([[0, 0, 0, 0, 0, 1, np.pi / 2, 0.0]]), 0)
+    np.testing.assert_allclose(x[0], [0, 1, 0], atol=1e-15)
+
+
+def test_propeller_area_and_symmetry():
+    """Generator sanity (inputs, not the method): total area matches the
+    analytic surface and the three-fold blade pattern cancels the summed
+    point velocity."""
+    wl = W.config("c0")
+    area = 2 * np.pi * 3 * 6 + 2 * np.pi * 9 + 3 * 10 * 3
+    assert abs(wl.area.astype(np.float64).sum() - area) < 1e-3 * area
+    x, ub = O.kinematics(wl.rest, wl.body_off, wl.bodies, 3)
+    assert np.abs((wl.area[:, None] * ub).sum(0)).max() < 1e-6
+
+
+# ------------------------------------------------------------ whole step
+def test_step_with_ibm_invariants():
+    """A full step with a rotating body in a periodic box: mass unchanged and
+    momentum changed by exactly sum rho G with the step's own G."""
+    wl = W.tiny_propeller_case(shape=(20, 18, 22))
+    p = O.params(wl.shape, wl.tau, forcing=O.FORCE_GUO)
+    pts = O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, 5, 0)
+    f = O.init_equilibrium(p)
+    O.run(p, f, pts, 0, 3)
+    import math
+    e, _, _ = O.d3q19()
+    rho, _ = O.moments(p, f)
+    m0 = math.fsum(f.ravel())
+    p0 = [math.fsum((e[:, a, None, None, None] * f).ravel()) for a in range(3)]
+    r = O.step(p, f, pts, 3)
+    m1 = math.fsum(f.ravel())
+    p1 = [math.fsum((e[:, a, None, None, None] * f).ravel()) for a in range(3)]
+    assert abs(m1 - m0) < 1e-14 * m0
+    dp = [math.fsum((rho * r["G"][a]).ravel()) for a in range(3)]
+    np.testing.assert_allclose(np.subtract(p1, p0), dp, rtol=1e-10, atol=1e-15)
+    assert np.abs(r["G"]).max() > 1e-4

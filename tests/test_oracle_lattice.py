@@ -1,0 +1,209 @@
+"""Pins of the oracle's lattice part: D3Q19 set, equilibrium, collision,
+streaming and walls, checked against facts fixed by the mathematics (moment
+identities, conservation, closed-form flows) rather than against the oracle's
+own formulas.  CPU only."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+@pytest.fixture(scope="module")
+def lat():
+    e, w, opp = O.d3q19()
+    return e.astype(np.float64), w, opp
+
+
+def test_velocity_set(lat):
+    e, w, opp = lat
+    # 19 distinct integer vectors: 1 rest, 6 of length 1, 12 of length sqrt 2
+    assert len({tuple(v) for v in e.astype(int)}) == 19
+    n2 = (e ** 2).sum(1)
+    assert sorted(n2.tolist()) == [0] + [1] * 6 + [2] * 12
+    assert np.all(np.abs(e) <= 1)
+    for i in range(19):
+        np.testing.assert_array_equal(e[opp[i]], -e[i])
+    # weights depend on length only
+    for i in range(19):
+        assert w[i] == w[int(np.argmax(n2 == n2[i]))]
+
+
+def test_isotropy(lat):
+    """sum t = 1, sum t e = 0, sum t e e = I/3, odd moments 0, 4th moment
+    (delta delta + delta delta + delta delta)/9 (c_s^2 = 1/3)."""
+    e, w, _ = lat
+    d = np.eye(3)
+    assert abs(w.sum() - 1) < 1e-15
+    np.testing.assert_allclose(np.einsum("i,ia->a", w, e), 0, atol=1e-16)
+    np.testing.assert_allclose(np.einsum("i,ia,ib->ab", w, e, e), d / 3, atol=1e-16)
+    np.testing.assert_allclose(np.einsum("i,ia,ib,ic->abc", w, e, e, e), 0, atol=1e-16)
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", w, e, e, e, e)
+    ref = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+           + np.einsum("ad,bc->abcd", d, d)) / 9
+    np.testing.assert_allclose(m4, ref, atol=1e-16)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_equilibrium_moments(lat, seed):
+    """sum Eq = rho, sum e Eq = rho u, sum e e Eq = rho (u u + I/3): pins the
+    density factor and the coefficients 3, 9/2, 3/2 of eq. (3)."""
+    e, _, _ = lat
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.5, 2.0)
+    u = rng.uniform(-0.2, 0.2, 3)
+    eq = O.equilibrium(rho, u)
+    assert abs(eq.sum() - rho) < 1e-14
+    np.testing.assert_allclose(e.T @ eq, rho * u, atol=1e-14)
+    np.testing.assert_allclose(np.einsum("i,ia,ib->ab", eq, e, e),
+                               rho * (np.outer(u, u) + np.eye(3) / 3), atol=1e-14)
+
+
+def _rand_state(shape, seed, amp=0.02):
+    e, w, _ = O.d3q19()
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(w.reshape(19, 1, 1, 1) * (1 + amp * rng.uniform(-1, 1, (19, nz, ny, nx))))
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (0, 1, 1), (1, 1, 1)])
+@pytest.mark.parametrize("forcing", [O.FORCE_GUO, O.FORCE_SHIFT])
+def test_rest_state_stays_at_rest(bc, forcing):
+    p = O.params((6, 5, 7), 0.8, bc=bc, forcing=forcing)
+    f = O.init_equilibrium(p)
+    f0 = f.copy()
+    O.run(p, f, None, 0, 10)
+    _, U = O.moments(p, f)
+    assert np.all(U == 0.0)          # velocity stays exactly zero
+    np.testing.assert_allclose(f, f0, rtol=0, atol=1e-15)
+
+
+def test_pure_streaming_direction():
+    """With 1/tau -> 0 collision is the identity, so one step must move f_i by
+    +e_i (eq. 4); checked with numpy's roll as an independent shift."""
+    e, _, _ = O.d3q19()
+    shape = (5, 6, 7)
+    p = O.params(shape, 1e300)
+    f = _rand_state(shape, 1)
+    g = O.collide_stream(p, f)
+    for i in range(19):
+        ref = np.roll(f[i], shift=(e[i][2], e[i][1], e[i][0]), axis=(0, 1, 2))
+        np.testing.assert_allclose(g[i], ref, rtol=0, atol=1e-15)
+
+
+def test_pure_streaming_bounce_back():
+    """Halfway bounce-back: a population that would leave through a wall comes
+    back to its own cell in the opposite direction; a moving wall adds
+    6 t_i rho_w e_i.u_w to the returning population."""
+    e, w, opp = O.d3q19()
+    shape = (4, 5, 3)
+    uw = np.zeros((3, 2, 3))
+    uw[1, 1] = [0.03, 0.0, 0.01]   # top y wall moves
+    p = O.params(shape, 1e300, bc=(0, 1, 0), wall_u=uw, rho_wall=1.3)
+    f = _rand_state(shape, 2)
+    g = O.collide_stream(p, f)
+    nx, ny, nz = shape
+    for i in range(19):
+        for (z, y, x) in itertools.product(range(nz), range(ny), range(nx)):
+            src_y = y - int(e[i][1])
+            if 0 <= src_y < ny:
+                sx, sz = (x - int(e[i][0])) % nx, (z - int(e[i][2])) % nz
+                assert abs(g[i, z, y, x] - f[i, sz, src_y, sx]) < 1e-15
+            else:
+                face = 0 if src_y < 0 else 1
+                extra = 6 * w[i] * 1.3 * float(e[i] @ uw[1, face])
+                assert abs(g[i, z, y, x] - (f[opp[i], z, y, x] + extra)) < 1e-15
+
+
+@pytest.mark.parametrize("forcing", [O.FORCE_GUO, O.FORCE_SHIFT])
+def test_conservation_no_force(forcing):
+    shape = (7, 6, 5)
+    p = O.params(shape, 0.57, forcing=forcing)
+    f = _rand_state(shape, 3)
+    hist = O.run(p, f, None, 0, 20)
+    np.testing.assert_allclose(hist[:, 0], hist[0, 0], rtol=1e-14)
+    np.testing.assert_allclose(hist[:, 1:] - hist[0, 1:], 0, atol=1e-13)
+
+
+@pytest.mark.parametrize("forcing", [O.FORCE_GUO, O.FORCE_SHIFT])
+def test_momentum_change_equals_force(forcing):
+    """Both forcing schemes impart exactly sum_X rho G to the momentum per step
+    and leave the mass unchanged (periodic box)."""
+    shape = (6, 7, 5)
+    p = O.params(shape, 0.66, forcing=forcing)
+    f = _rand_state(shape, 4)
+    rng = np.random.default_rng(9)
+    G = 1e-3 * rng.uniform(-1, 1, (3, 5, 7, 6))
+    rho, _ = O.moments(p, f)
+    s0 = O.sums(p, f)
+    f1 = O.collide_stream(p, f, G)
+    s1 = O.sums(p, f1)
+    assert abs(s1[0] - s0[0]) < 1e-14 * s0[0]
+    np.testing.assert_allclose(s1[1:] - s0[1:], (rho[None] * G).sum(axis=(1, 2, 3)), atol=1e-14)
+
+
+def test_shear_wave_decay():
+    """u_x = A sin(k y) decays as exp(-nu k^2 t), nu = (tau - 1/2)/3."""
+    ny, tau, A = 64, 0.8, 1e-4
+    p = O.params((1, ny, 1), tau)
+    e, w, _ = O.d3q19()
+    k = 2 * np.pi / ny
+    y = np.arange(ny)
+    f = np.zeros((19, 1, ny, 1))
+    for j in range(ny):
+        f[:, 0, j, 0] = O.equilibrium(1.0, [A * np.sin(k * y[j]), 0, 0])
+    f = np.ascontiguousarray(f)
+    amps = []
+    for t in range(400):
+        if t in (100, 300):
+            _, U = O.moments(p, f)
+            amps.append(2 / ny * np.sum(U[0, 0, :, 0] * np.sin(k * y)))
+        O.run(p, f, None, t, 1)
+    nu = (tau - 0.5) / 3
+    rate = -np.log(amps[1] / amps[0]) / 200
+    assert abs(rate / (nu * k * k) - 1) < 2e-3
+
+
+def _steady(p, f, max_steps, tol):
+    last = None
+    for _ in range(max_steps // 200):
+        O.run(p, f, None, 0, 200)
+        _, U = O.moments(p, f)
+        if last is not None and np.abs(U - last).max() < tol:
+            return U
+        last = U
+    return U
+
+
+def test_poiseuille_guo():
+    """Body-force channel between halfway bounce-back walls (Guo forcing): in
+    the bulk the physical velocity U + G/2 has second difference -g/nu, and
+    the profile is symmetric about the centre line."""
+    ny, tau, gx = 16, 0.9, 1e-6
+    p = O.params((1, ny, 1), tau, bc=(0, 1, 0), forcing=O.FORCE_GUO, g_ext=(gx, 0, 0))
+    f = O.init_equilibrium(p)
+    U = _steady(p, f, 40000, 1e-15)
+    u = U[0, 0, :, 0] + gx / 2
+    nu = (tau - 0.5) / 3
+    d2 = u[2:] - 2 * u[1:-1] + u[:-2]
+    np.testing.assert_allclose(d2, -gx / nu, rtol=1e-6)
+    np.testing.assert_allclose(u, u[::-1], rtol=1e-10)
+    # close to the no-slip parabola with walls half a cell outside
+    y = np.arange(ny)
+    ref = gx / (2 * nu) * (y + 0.5) * (ny - 0.5 - y)
+    assert np.abs(u - ref).max() / ref.max() < 0.05
+
+
+def test_couette_linear():
+    """Moving top wall, resting bottom wall: the steady profile is exactly
+    linear, u(y) = U_w (y + 1/2) / N (halfway bounce-back with Ladd's term)."""
+    ny, tau, Uw = 12, 0.75, 0.01
+    uw = np.zeros((3, 2, 3))
+    uw[1, 1, 0] = Uw
+    p = O.params((1, ny, 1), tau, bc=(0, 1, 0), wall_u=uw)
+    f = O.init_equilibrium(p)
+    U = _steady(p, f, 60000, 1e-16)
+    u = U[0, 0, :, 0]
+    y = np.arange(ny)
+    np.testing.assert_allclose(u, Uw * (y + 0.5) / ny, rtol=1e-9, atol=1e-14)
