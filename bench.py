@@ -1,0 +1,175 @@
+"""Benchmark of the LBM-IBM hot path on one MI355X.
+
+A step is one pass of the whole path: rigid motion and binning of the
+Lagrangian points, velocity near the surface, the multi-direct-forcing
+sweeps (interpolation, correction, spreading) and the fused D3Q19
+stream-collide, on synthetic inputs resident in HBM.
+
+Default workload: the dense case, a 256^3 periodic lattice (tau 0.55, FP32)
+with 64 rotating propellers (h 0.41, about 1.6M Lagrangian points, seed 0),
+5 sweeps per step.
+
+Prints ONE JSON line: MLUPS including the forcing (value), point-updates/s,
+the fraction of the HBM roofline, the stream-collide kernel's roofline entry
+(bytes per launch / measured launch time) and the FP64 oracle timed on the
+host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+BYTES_PER_CELL = {0: 152, 1: 76, 2: 76}    # 19 populations read + written
+KERNEL_SOURCES = ["paper_1904_02108_amd/csrc/lbm_kernels.hip",
+                  "paper_1904_02108_amd/csrc/device_common.h"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(storage):
+    """HBM bytes per stream-collide launch from the committed rocprofv3 PMC
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "stream_collide_c2_dense_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get("bytes_per_launch", {}).get(str(storage))
+
+
+def cpu_baseline(wl, n_steps):
+    """The FP64 oracle on the host cores: n_steps steps of the same workload."""
+    import numpy as np  # noqa: F401
+
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    p = O.params(wl.shape, wl.tau, bc=wl.bc, forcing=wl.forcing)
+    pts = O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter)
+    f = O.init_equilibrium(p)
+    t0 = time.perf_counter()
+    O.run(p, f, pts, 0, n_steps)
+    dt = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": round(wl.n_cells * n_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d step(s) of the same workload from rest (FP64, OpenMP), %.1f s wall, %s"
+                      % (n_steps, dt, cpu)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c2_dense", choices=["c0", "c1", "c2", "c2_dense"])
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--forcing", default="guo", choices=["guo", "shift"])
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU; this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1904_02108_amd import lbmibm as L
+    from paper_1904_02108_amd import workload as W
+
+    storage = {"f32": L.LBM_STORE_F32, "f16": L.LBM_STORE_F16, "bf16": L.LBM_STORE_BF16}[args.storage]
+    forcing = {"guo": L.LBM_FORCE_GUO, "shift": L.LBM_FORCE_SHIFT}[args.forcing]
+    wl = W.config(args.workload, forcing=forcing)
+    torch.cuda.set_device(0)
+    sim = L.Simulation(wl.shape, wl.tau, bc=wl.bc, storage=storage, forcing=forcing,
+                       max_points=wl.n_points, max_iter=wl.n_iter, device="cuda:0")
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter)
+    stream = torch.cuda.current_stream()
+
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    L.lbm_set_timing(sim.ctx, 1)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    sim.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    tm = L.lbm_get_timing(sim.ctx)
+    L.lbm_set_timing(sim.ctx, 0)
+    sums = sim.read("sums")["sums"].cpu().numpy()
+
+    K = args.steps
+    ms_step = ms / K
+    mlups = wl.n_cells * K / (ms * 1e-3) / 1e6
+    bpc = BYTES_PER_CELL[storage]
+    fluid_ms = tm["ms_fluid"] / max(tm["n_fluid"], 1)
+    forcing_ms = tm["ms_forcing"] / max(tm["n_forcing"], 1)
+    achieved = bpc * wl.n_cells / (fluid_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(storage)
+    out = {
+        "metric": "MLUPS incl. IBM + Lagrangian pt-updates/s, %HBM roofline",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {0: "f32", 1: "f16-storage/f32", 2: "bf16-storage/f32"}[storage],
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": list(wl.shape), "bc": list(wl.bc), "tau": wl.tau,
+                   "n_points": wl.n_points, "n_bodies": int(len(wl.bodies)), "h": wl.h,
+                   "sweeps": wl.n_iter, "forcing": args.forcing, "storage": args.storage,
+                   "parallelism": "single GPU"},
+        "point_updates_per_s": round(wl.n_points * K / (ms * 1e-3), 1),
+        "hbm_frac_full_step": round(mlups * 1e6 * bpc / (HBM_PEAK_GBS * 1e9), 4),
+        "ms_fluid": round(fluid_ms, 4),
+        "ms_forcing": round(forcing_ms, 4),
+        "forcing_over_fluid": round(forcing_ms / fluid_ms, 3),
+        "mass_sum": float(sums[0]),
+        "finite": bool(all(map(lambda v: v == v and abs(v) != float("inf"), sums))),
+        "roofline": {"bound": "hbm", "kernel": "k_stream_collide",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "bytes_per_launch": bpc * wl.n_cells},
+        "cpu_baseline": None,
+    }
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline and args.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * lbmibm.h -- C ABI of the MI355X (gfx950) LBM-IBM library.
+ *
+ * The library advances a D3Q19 BGK lattice-Boltzmann fluid with a body-force
+ * term (Beny & Latt, arXiv 1904.02108, §2: eqs. (1)-(4) and the six-step
+ * time loop) and computes that force with the multi-direct-forcing immersed
+ * boundary method of Ota, Suzuki and Inamuro (§3: interpolation through
+ * Peskin's 4-point delta, deficit g(k), accumulated correction du(k),
+ * intermediate spreading, final spreading into G; §4.2-4.3: Algorithms 1
+ * and 2) for rigidly rotating Lagrangian surfaces.
+ *
+ * Conventions shared by every call
+ *   - Every function returns lbm_status (0 = LBM_OK, < 0 = error).  No C++
+ *     exception crosses the ABI.  After an error, lbm_last_error(ctx) holds a
+ *     message; the context is unchanged except after LBM_ERR_HIP, after which
+ *     it must be destroyed.
+ *   - Work is enqueued on the stream given in lbm_params (a hipStream_t,
+ *     borrowed, never destroyed by the library; NULL = the null stream).
+ *     Calls return before the GPU finishes unless a host pointer is read or
+ *     written, or a stats/residual result is requested.
+ *   - Large device memory is owned by the caller: lbm_buffer_sizes() gives
+ *     the byte size of each buffer, the caller allocates them (any device
+ *     allocator; 256-byte alignment) and passes them to lbm_create(); they
+ *     must outlive the context.  The library owns only host metadata.
+ *   - A context is not thread-safe; calls on one context must be serialised.
+ *   - Lattice units: cell X sits at integer coordinates 0..n-1 on each axis;
+ *     dx = dt = 1.  Fields are exported x-fastest: index x + nx*(y + ny*z).
+ *   - D3Q19 direction order (POPS export): 0 rest; 1..6 = +x,-x,+y,-y,+z,-z;
+ *     7..18 = (1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),
+ *     (1,0,-1),(-1,0,1),(0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1).
+ */
+#ifndef LBMIBM_H
+#define LBMIBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque context: one simulation on one device. */
+typedef struct lbm_ctx lbm_ctx;
+
+typedef int32_t lbm_status;
+enum {
+  LBM_OK = 0,
+  LBM_ERR_ARG = -1,       /* invalid argument (sizes, pointers, enums)        */
+  LBM_ERR_OOM = -2,       /* a caller buffer is missing or too small          */
+  LBM_ERR_HIP = -3,       /* a HIP runtime call or launch failed              */
+  LBM_ERR_STATE = -4,     /* call not valid in the current state              */
+  LBM_ERR_DOMAIN = -5,    /* a point's kernel support leaves a walled box     */
+  LBM_ERR_NONFINITE = -6  /* non-finite mass or momentum detected             */
+};
+
+/* Boundary condition per axis (both faces).  Bounce-back is the halfway
+ * rule: walls half a cell outside the first and last cell. */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_BOUNCEBACK = 1 };
+
+/* Population storage in HBM.  All arithmetic is FP32; the 16-bit forms store
+ * f_i - t_i (offset from the lattice weight), rounded to nearest even. */
+enum { LBM_STORE_F32 = 0, LBM_STORE_F16 = 1, LBM_STORE_BF16 = 2 };
+
+/* Forcing scheme for the force G (an acceleration) in the collision:
+ *   GUO:   F = rho G, equilibrium at U + G/2, plus Guo's source term;
+ *   SHIFT: the paper's velocity shift, equilibrium at U + tau G (§2, step 3).
+ * Both change the momentum by exactly rho G per step. */
+enum { LBM_FORCE_GUO = 0, LBM_FORCE_SHIFT = 1 };
+
+typedef struct {
+  int32_t nx, ny, nz;      /* lattice size, each >= 1                          */
+  int32_t bc[3];           /* LBM_BC_* per axis                                */
+  int32_t storage;         /* LBM_STORE_*                                      */
+  int32_t forcing;         /* LBM_FORCE_*                                      */
+  double tau;              /* BGK relaxation time, > 0.5                       */
+  double rho_wall;         /* density in the moving-wall correction (Ladd)     */
+  double wall_u[3][2][3];  /* wall velocity [axis][0 = low, 1 = high face][c]  */
+  double g_ext[3];         /* uniform acceleration added to G in every cell    */
+  double rho0;             /* initial uniform density                          */
+  double u0[3];            /* initial uniform velocity                         */
+  int64_t max_points;      /* capacity for Lagrangian points (>= 0)            */
+  int32_t max_iter;        /* capacity for forcing sweeps per step (1..64)     */
+  int32_t reserved_;       /* must be 0                                        */
+  void* stream;            /* hipStream_t, borrowed                            */
+} lbm_params;
+
+/* Caller-owned device buffers. */
+enum {
+  LBM_BUF_LATTICE = 0,  /* two population lattices                        */
+  LBM_BUF_FIELDS = 1,   /* velocity scratch U and force G, 3 x FP32 each  */
+  LBM_BUF_POINTS = 2,   /* Lagrangian point arrays                        */
+  LBM_BUF_TILES = 3,    /* tile counts, offsets, flags                    */
+  LBM_BUF_SCRATCH = 4,  /* reduction partials and small results           */
+  LBM_NBUF = 5
+};
+
+/* Rigid body: rotation about `axis` (normalised by the library) through
+ * `center`, by theta_n = theta0 + omega * n at time step n (§4.2: the motion
+ * M(t) is applied to the rest positions at the first sweep). */
+typedef struct {
+  double center[3];
+  double axis[3];
+  double theta0;
+  double omega;
+} ibm_body;
+
+/* ibm_set_points flags */
+enum {
+  IBM_INNER_UNWEIGHTED = 1u  /* spread g(k) (not s(k) g(k)) inside the sweep,
+                                the paper-literal reading of §3             */
+};
+
+#define LBM_MAX_ITER 64
+
+/* Per-step forcing statistics (FP64 sums over points). */
+typedef struct {
+  int32_t n_iter;                /* sweeps executed                         */
+  int32_t pad_;
+  double sum_s;                  /* sum_k s(k)                              */
+  double sum_s_ub2;              /* sum_k s(k) |u_b(k)|^2                   */
+  double resid[LBM_MAX_ITER];    /* sum_k s(k) |g_it(k)|^2 for each sweep   */
+} ibm_stats;
+
+/* lbm_read_fields / lbm_write_fields masks */
+enum {
+  LBM_F_RHO = 1u << 0,   /* float [nz][ny][nx]      density (read)            */
+  LBM_F_VEL = 1u << 1,   /* float [3][nz][ny][nx]   U = sum e f / rho (read)  */
+  LBM_F_FORCE = 1u << 2, /* float [3][nz][ny][nx]   G of the last forcing;
+                            write: prescribes G (only without points)        */
+  LBM_F_POPS = 1u << 3,  /* float or double [19][nz][ny][nx] populations f
+                            at the start of the current step (after stream)  */
+  LBM_F_PT_X = 1u << 4,  /* double [n][3] point positions of the last forcing */
+  LBM_F_PT_UB = 1u << 5, /* float  [n][3] point velocities u_b                */
+  LBM_F_PT_G = 1u << 6,  /* float  [n][3] last deficit g                      */
+  LBM_F_PT_DU = 1u << 7, /* float  [n][3] accumulated correction du           */
+  LBM_F_SUMS = 1u << 8,  /* double [4]   sum rho, sum rho U over the box at the
+                            start of the last completed step                 */
+  LBM_F_STEP = 1u << 9   /* int64  [1]   current time step index              */
+};
+
+typedef struct {
+  int32_t on_device;   /* 1: device pointers (async on the stream);
+                          0: host pointers (the call synchronises)          */
+  int32_t pops_f64;    /* POPS as double (1) or float (0)                     */
+  float* rho;
+  float* vel;
+  float* force;
+  void* pops;
+  double* pt_x;        /* point arrays are in the order given to ibm_set_points */
+  float* pt_ub;
+  float* pt_g;
+  float* pt_du;
+  double* sums;
+  int64_t* step;
+} lbm_fields;
+
+/* Byte sizes of the LBM_NBUF caller buffers for these parameters. */
+lbm_status lbm_buffer_sizes(const lbm_params* p, size_t sizes_out[LBM_NBUF]);
+
+/* Creates a context on the current HIP device, binds the caller buffers and
+ * enqueues the initial state f = Eq(rho0, u0) at step 0.  The buffers are
+ * not read before this call and need no initialisation. */
+lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx** out);
+
+/* Destroys the context (host memory only; the caller frees its buffers). */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Last error message of ctx, or of the last failed lbm_create on this thread
+ * when ctx is NULL.  Valid until the next call on the context. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+/* Sets the immersed surface (§3, §4.2): n points with rest positions
+ * relative to their body's centre (host float [n][3]), areas s(k) (host
+ * float [n]), body ranges body_off[0..nbodies] (host, body b owns points
+ * body_off[b] .. body_off[b+1]-1, body_off[0] = 0, body_off[nbodies] = n),
+ * bodies (host [nbodies]), n_iter sweeps per step (1..max_iter), flags
+ * (IBM_*), eps (reserved, 0).  Host arrays are copied before return.
+ * n = 0 removes the surface.  Returns LBM_ERR_DOMAIN if for some rotation
+ * angle a support could leave a walled axis (bounding-sphere test: on a
+ * bounce-back axis every point must keep 1 <= x < n - 2). */
+lbm_status ibm_set_points(lbm_ctx* ctx, int64_t n, const float* rest_xyz, const float* area,
+                          const int64_t* body_off, int32_t nbodies, const ibm_body* bodies,
+                          int32_t n_iter, uint32_t flags, float eps);
+
+/* Computes the force G for the current step (§2 step 2, §3): moves the
+ * points (Algorithm 1), computes U near them, runs the sweeps and spreads
+ * du into G.  A following lbm_step uses this G instead of recomputing it.
+ * stats (nullable; non-NULL synchronises the stream) receives the sums. */
+lbm_status ibm_force_iterate(lbm_ctx* ctx, ibm_stats* stats);
+
+/* Advances n_steps >= 0 time steps: per step, the forcing (if a surface is
+ * set) followed by the fused stream-collide (§2 steps 1, 3-6). */
+lbm_status lbm_step(lbm_ctx* ctx, int32_t n_steps);
+
+/* Reads fields selected by mask into caller memory (see LBM_F_*). */
+lbm_status lbm_read_fields(lbm_ctx* ctx, uint32_t mask, const lbm_fields* dst);
+
+/* Writes LBM_F_POPS (f at the start of the current step), LBM_F_FORCE
+ * (prescribed G, kept until the next write, only without points) and
+ * LBM_F_STEP.  Other bits are rejected with LBM_ERR_ARG. */
+lbm_status lbm_write_fields(lbm_ctx* ctx, uint32_t mask, const lbm_fields* src);
+
+/* Optional per-phase timing with HIP events on the context's stream.
+ * lbm_get_timing returns {ms forcing, ms stream-collide, forcing calls,
+ * stream-collide calls} accumulated since enabling, and synchronises. */
+lbm_status lbm_set_timing(lbm_ctx* ctx, int32_t enable);
+lbm_status lbm_get_timing(lbm_ctx* ctx, double out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBMIBM_H */

@@ -340,18 +340,28 @@ int orc_interpolate(const orc_params* p, int64_t npts, const double* x,
 }
 
 /* Spreading (§3): acc(X) += sum_k v(k) w(x-X) w(y-Y) w(z-Z).
- * v: [n][3]; acc: [3][ncell], accumulated in place.  Serial over points. */
+ * v: [n][3]; acc: [3][ncell], accumulated in place.  Points run in parallel;
+ * concurrent additions to one cell are atomic (FP64, so the order only
+ * changes the last bits). */
 int orc_spread(const orc_params* p, int64_t npts, const double* x,
                const double* v, double* acc) {
   const int64_t n = ncells(p);
-  orc_window win;
+  int err = ORC_OK;
+#pragma omp parallel for schedule(static)
   for (int64_t k = 0; k < npts; ++k) {
-    if (point_window(p, x + 3 * k, &win) != ORC_OK) return ORC_ERR_DOMAIN;
+    orc_window win;
+    if (point_window(p, x + 3 * k, &win) != ORC_OK) {
+#pragma omp atomic write
+      err = ORC_ERR_DOMAIN;
+      continue;
+    }
     for (int t = 0; t < win.count; ++t)
-      for (int a = 0; a < 3; ++a)
+      for (int a = 0; a < 3; ++a) {
+#pragma omp atomic
         acc[(int64_t)a * n + win.cell[t]] += v[3 * k + a] * win.w[t];
+      }
   }
-  return ORC_OK;
+  return err;
 }
 
 /* ---------------------------------------------------------------------------
@@ -405,30 +415,29 @@ void orc_kinematics(int64_t npts, const double* rest, const int64_t* body_off,
  * U0 is not modified.  resid[it] = sum_k s(k) |g_it(k)|^2.
  * G_out: [3][ncell] overwritten.  du_out, g_out: [n][3] (nullable).
  * ------------------------------------------------------------------------- */
-int orc_ibm(const orc_params* p, int64_t npts, const double* x,
-            const double* ub, const double* s, const double* U0,
-            int32_t n_iter, int32_t flags, double* G_out, double* du_out,
-            double* g_out, double* resid) {
+static int ibm_core(const orc_params* p, int64_t npts, const double* x,
+                    const double* ub, const double* s, double* U, int32_t n_iter,
+                    int32_t flags, double* G_out, double* du_out, double* g_out,
+                    double* resid) {
   const int64_t n = ncells(p);
-  double* U = (double*)malloc(sizeof(double) * 3 * n);
-  double* u = (double*)malloc(sizeof(double) * 3 * (npts > 0 ? npts : 1));
-  double* g = (double*)malloc(sizeof(double) * 3 * (npts > 0 ? npts : 1));
-  double* v = (double*)malloc(sizeof(double) * 3 * (npts > 0 ? npts : 1));
-  double* du = (double*)calloc(3 * (npts > 0 ? npts : 1), sizeof(double));
+  const int64_t m = npts > 0 ? npts : 1;
+  double* u = (double*)malloc(sizeof(double) * 3 * m);
+  double* g = (double*)malloc(sizeof(double) * 3 * m);
+  double* v = (double*)malloc(sizeof(double) * 3 * m);
+  double* du = (double*)calloc(3 * m, sizeof(double));
   int err = ORC_OK;
-  memcpy(U, U0, sizeof(double) * 3 * n);
   for (int it = 0; it < n_iter && err == ORC_OK; ++it) {
     err = orc_interpolate(p, npts, x, U, u);
     if (err != ORC_OK) break;
     double r = 0.0;
     for (int64_t k = 0; k < npts; ++k) {
-      double m = 0.0;
+      double sq = 0.0;
       for (int a = 0; a < 3; ++a) {
         g[3 * k + a] = ub[3 * k + a] - u[3 * k + a];
         du[3 * k + a] += s[k] * g[3 * k + a];
-        m += g[3 * k + a] * g[3 * k + a];
+        sq += g[3 * k + a] * g[3 * k + a];
       }
-      r += s[k] * m;
+      r += s[k] * sq;
     }
     if (resid) resid[it] = r;
     if (it < n_iter - 1) {
@@ -448,11 +457,23 @@ int orc_ibm(const orc_params* p, int64_t npts, const double* x,
     if (du_out) memcpy(du_out, du, sizeof(double) * 3 * npts);
     if (g_out) memcpy(g_out, g, sizeof(double) * 3 * npts);
   }
-  free(U);
   free(u);
   free(g);
   free(v);
   free(du);
+  return err;
+}
+
+int orc_ibm(const orc_params* p, int64_t npts, const double* x,
+            const double* ub, const double* s, const double* U0,
+            int32_t n_iter, int32_t flags, double* G_out, double* du_out,
+            double* g_out, double* resid) {
+  const int64_t n = ncells(p);
+  double* U = (double*)malloc(sizeof(double) * 3 * n);
+  memcpy(U, U0, sizeof(double) * 3 * n);
+  int err = ibm_core(p, npts, x, ub, s, U, n_iter, flags, G_out, du_out, g_out,
+                     resid);
+  free(U);
   return err;
 }
 
@@ -488,45 +509,67 @@ typedef struct {
   double* resid; /* [n_iter] */
 } orc_step_out;
 
-int orc_step(const orc_params* p, double* f, const orc_points* pts,
-             int64_t step, const orc_step_out* out) {
+/* Buffers reused across the steps of one run. */
+typedef struct {
+  double *fn, *rho, *U, *G, *x, *ub;
+} orc_ws;
+
+static void ws_alloc(orc_ws* w, int64_t n, int64_t m) {
+  if (m < 1) m = 1;
+  w->fn = (double*)malloc(sizeof(double) * Q * n);
+  w->rho = (double*)malloc(sizeof(double) * n);
+  w->U = (double*)malloc(sizeof(double) * 3 * n);
+  w->G = (double*)malloc(sizeof(double) * 3 * n);
+  w->x = (double*)malloc(sizeof(double) * 3 * m);
+  w->ub = (double*)malloc(sizeof(double) * 3 * m);
+}
+
+static void ws_free(orc_ws* w) {
+  free(w->fn);
+  free(w->rho);
+  free(w->U);
+  free(w->G);
+  free(w->x);
+  free(w->ub);
+}
+
+/* One step from f into w->fn (f is left unchanged). */
+static int step_into(const orc_params* p, const double* f, const orc_points* pts,
+                     int64_t step, const orc_step_out* out, orc_ws* w) {
   const int64_t n = ncells(p);
-  double* fn = (double*)malloc(sizeof(double) * Q * n);
-  double* G = NULL;
+  const double* G = NULL;
   int err = ORC_OK;
   if (out && out->sums) orc_sums(p, f, out->sums);
   if (pts && pts->npts > 0) {
     int64_t m = pts->npts;
-    double* rho = (double*)malloc(sizeof(double) * n);
-    double* U = (double*)malloc(sizeof(double) * 3 * n);
-    double* x = (double*)malloc(sizeof(double) * 3 * m);
-    double* ub = (double*)malloc(sizeof(double) * 3 * m);
-    G = (double*)malloc(sizeof(double) * 3 * n);
-    orc_moments(p, f, rho, U);
+    orc_moments(p, f, w->rho, w->U);
     orc_kinematics(m, pts->rest, pts->body_off, pts->nbodies, pts->bodies,
-                   step, x, ub);
-    err = orc_ibm(p, m, x, ub, pts->area, U, pts->n_iter, pts->flags, G,
-                  out ? out->du : NULL, out ? out->g : NULL,
-                  out ? out->resid : NULL);
-    if (out && out->x) memcpy(out->x, x, sizeof(double) * 3 * m);
-    if (out && out->ub) memcpy(out->ub, ub, sizeof(double) * 3 * m);
-    free(rho);
-    free(U);
-    free(x);
-    free(ub);
+                   step, w->x, w->ub);
+    err = ibm_core(p, m, w->x, w->ub, pts->area, w->U, pts->n_iter, pts->flags,
+                   w->G, out ? out->du : NULL, out ? out->g : NULL,
+                   out ? out->resid : NULL);
+    if (out && out->x) memcpy(out->x, w->x, sizeof(double) * 3 * m);
+    if (out && out->ub) memcpy(out->ub, w->ub, sizeof(double) * 3 * m);
+    G = w->G;
   }
-  if (err == ORC_OK) {
-    if (out && out->G) {
-      if (G)
-        memcpy(out->G, G, sizeof(double) * 3 * n);
-      else
-        memset(out->G, 0, sizeof(double) * 3 * n);
-    }
-    orc_collide_stream(p, f, G, fn);
-    memcpy(f, fn, sizeof(double) * Q * n);
+  if (err != ORC_OK) return err;
+  if (out && out->G) {
+    if (G)
+      memcpy(out->G, G, sizeof(double) * 3 * n);
+    else
+      memset(out->G, 0, sizeof(double) * 3 * n);
   }
-  free(G);
-  free(fn);
+  orc_collide_stream(p, f, G, w->fn);
+  return ORC_OK;
+}
+
+int orc_step(const orc_params* p, double* f, const orc_points* pts,
+             int64_t step, const orc_step_out* out) {
+  orc_ws w;
+  ws_alloc(&w, ncells(p), pts ? pts->npts : 0);
+  int err = step_into(p, f, pts, step, out, &w);
+  if (err == ORC_OK) memcpy(f, w.fn, sizeof(double) * Q * ncells(p));
+  ws_free(&w);
   return err;
 }
 
@@ -534,12 +577,26 @@ int orc_step(const orc_params* p, double* f, const orc_points* pts,
  * the sums before each step, [n_steps][4]. */
 int orc_run(const orc_params* p, double* f, const orc_points* pts,
             int64_t step0, int64_t n_steps, double* sums_hist) {
-  for (int64_t s = 0; s < n_steps; ++s) {
+  const int64_t n = ncells(p);
+  orc_ws w;
+  ws_alloc(&w, n, pts ? pts->npts : 0);
+  double* cur = f;
+  int err = ORC_OK;
+  for (int64_t s = 0; s < n_steps && err == ORC_OK; ++s) {
     orc_step_out o;
     memset(&o, 0, sizeof(o));
     o.sums = sums_hist ? sums_hist + 4 * s : NULL;
-    int err = orc_step(p, f, pts, step0 + s, &o);
-    if (err != ORC_OK) return err;
+    err = step_into(p, cur, pts, step0 + s, &o, &w);
+    if (err == ORC_OK) { /* swap the state and the work lattice */
+      double* t = w.fn;
+      w.fn = cur;
+      cur = t;
+    }
   }
-  return ORC_OK;
+  if (cur != f) { /* final state lives in the work buffer */
+    memcpy(f, cur, sizeof(double) * Q * n);
+    w.fn = cur;
+  }
+  ws_free(&w);
+  return err;
 }

@@ -1,0 +1,146 @@
+// Device-side building blocks shared by the HIP kernels of the library:
+// the D3Q19 velocity set, population storage formats and the pull-stream
+// gather with periodic or halfway bounce-back boundaries.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbmibm.h"
+
+namespace lbmd {
+
+// D3Q19 velocity set in the export order documented in lbmibm.h.
+constexpr int Q = 19;
+constexpr int EX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int EY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int EZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+// Lattice weights: 1/3 rest, 1/18 axis links, 1/36 diagonal links.
+__host__ __device__ constexpr float wgt(int i) {
+  return i == 0 ? 1.0f / 3.0f : (i <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f);
+}
+__host__ __device__ constexpr double wgt_d(int i) {
+  return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// ---------------------------------------------------------------------------
+// Population storage.  Every format holds the offset f_i - t_i; arithmetic is
+// FP32.  16-bit formats round to nearest even on store.
+// ---------------------------------------------------------------------------
+template <int S>
+struct Store;
+
+template <>
+struct Store<LBM_STORE_F32> {
+  using T = float;
+  static __device__ __forceinline__ float load(const T* p) { return *p; }
+  static __device__ __forceinline__ void store(T* p, float v) { *p = v; }
+};
+
+template <>
+struct Store<LBM_STORE_F16> {
+  using T = _Float16;
+  static __device__ __forceinline__ float load(const T* p) { return (float)*p; }
+  static __device__ __forceinline__ void store(T* p, float v) { *p = (_Float16)v; }
+};
+
+template <>
+struct Store<LBM_STORE_BF16> {
+  using T = uint16_t;
+  static __device__ __forceinline__ float load(const T* p) {
+    return __uint_as_float(((uint32_t)*p) << 16);
+  }
+  static __device__ __forceinline__ void store(T* p, float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
+      *p = (uint16_t)((u >> 16) | 0x40u);  // keep NaN quiet
+      return;
+    }
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    *p = (uint16_t)(u >> 16);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Lattice geometry passed by value to the lattice kernels.
+// bb_add[a][face][i]: term added to population i when it is reflected at the
+// wall of axis a (face 0 = low, 1 = high): 6 t_i rho_w e_i . u_w.
+// ---------------------------------------------------------------------------
+struct LatticeGeom {
+  int nx, ny, nz;
+  int bc[3];
+  int64_t ncell;
+  int64_t stride;  // elements between consecutive population arrays
+  float bb_add[3][2][Q];
+  float tau, omega;   // omega = 1 / tau
+  float g_ext[3];
+  int fblk_x, fblk_y;  // grid of 4^3 force blocks (x, y extent) for flag lookups
+};
+
+constexpr int TILE = 8;       // edge of the cubic tiles the forcing works on
+constexpr int TILE_SHIFT = 3;
+constexpr int FBLK = 4;       // edge of the cubic blocks flagged as touched by a support
+constexpr int FBLK_SHIFT = 2;
+
+// Pull-stream gather of the 19 post-stream offsets at cell (x, y, z) from the
+// post-collision lattice `lat` (eq. (4) read backwards: f_i(X) = f*_i(X - e_i);
+// at a wall the reflected population of the same cell, plus bb_add).
+template <int S>
+__device__ __forceinline__ void gather_pull(const typename Store<S>::T* __restrict__ lat,
+                                            const LatticeGeom& g, int x, int y, int z,
+                                            float f[Q]) {
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int64_t here = (int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int sx = x - EX[i], sy = y - EY[i], sz = z - EZ[i];
+    int wall_axis = -1, wall_face = 0;
+    if (EX[i] != 0 && (sx < 0 || sx >= nx)) {
+      if (g.bc[0] == LBM_BC_PERIODIC) {
+        sx = sx < 0 ? sx + nx : sx - nx;
+      } else {
+        wall_axis = 0;
+        wall_face = sx < 0 ? 0 : 1;
+      }
+    }
+    if (EY[i] != 0 && (sy < 0 || sy >= ny)) {
+      if (g.bc[1] == LBM_BC_PERIODIC) {
+        sy = sy < 0 ? sy + ny : sy - ny;
+      } else if (wall_axis < 0) {
+        wall_axis = 1;
+        wall_face = sy < 0 ? 0 : 1;
+      }
+    }
+    if (EZ[i] != 0 && (sz < 0 || sz >= nz)) {
+      if (g.bc[2] == LBM_BC_PERIODIC) {
+        sz = sz < 0 ? sz + nz : sz - nz;
+      } else if (wall_axis < 0) {
+        wall_axis = 2;
+        wall_face = sz < 0 ? 0 : 1;
+      }
+    }
+    if (wall_axis < 0) {
+      const int64_t src = (int64_t)sx + (int64_t)nx * ((int64_t)sy + (int64_t)ny * sz);
+      f[i] = Store<S>::load(lat + (int64_t)i * g.stride + src);
+    } else {
+      f[i] = Store<S>::load(lat + (int64_t)OPP[i] * g.stride + here) +
+             g.bb_add[wall_axis][wall_face][i];
+    }
+  }
+}
+
+// Index of the 4^3 force block holding cell (x, y, z).
+__device__ __forceinline__ int64_t fblock_of(const LatticeGeom& g, int x, int y, int z) {
+  return (int64_t)(x >> FBLK_SHIFT) +
+         (int64_t)g.fblk_x * ((int64_t)(y >> FBLK_SHIFT) + (int64_t)g.fblk_y * (z >> FBLK_SHIFT));
+}
+
+// 64-lane FP64 sum across a wavefront.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace lbmd

@@ -1,0 +1,110 @@
+// Host-side internals: the context and the kernel launchers that the C ABI
+// in lbmibm.cpp drives.  Launchers enqueue on ctx->stream and return
+// hipError_t from the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "device_common.h"
+#include "lbmibm.h"
+
+constexpr int LBM_MAX_BODIES = 65536;
+constexpr int LBM_BLOCK = 256;  // threads per workgroup of the cell and point kernels
+
+// Per-body motion coefficients computed on the device each step:
+// normalised axis, centre, cos/sin of theta_n, and the differences of cos and
+// sin between steps n and n-1.
+struct BodyMotion {
+  double center[3];
+  double axis[3];
+  double c, s, dc, ds;
+};
+
+struct lbm_ctx {
+  lbm_params p{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  lbmd::LatticeGeom geom{};
+  int64_t ncell = 0;
+  int tiles[3] = {0, 0, 0};
+  int64_t ntiles = 0;
+  size_t elem = 4;  // bytes per stored population
+
+  // caller buffers, carved
+  void* lat[2] = {nullptr, nullptr};
+  int cur = 0;  // lattice holding the post-collision state of the previous step
+  float* U = nullptr;  // [3][ncell] velocity scratch for the forcing
+  float* G = nullptr;  // [3][ncell] force
+  // points (capacity max_points)
+  float4* rest = nullptr;     // (x, y, z, s) relative to the body centre
+  int32_t* body_of = nullptr;
+  uint32_t* key = nullptr;
+  uint32_t* rank = nullptr;
+  int4* sp_base = nullptr;    // sorted: base cell (x, y, z), original index
+  float4* sp_frac = nullptr;  // sorted: fractional position (x, y, z), s
+  float4* sp_ub = nullptr;    // sorted: point velocity u_b
+  float4* sp_g = nullptr;     // sorted: deficit g
+  float4* sp_du = nullptr;    // sorted: accumulated correction du
+  double* bodies = nullptr;   // [LBM_MAX_BODIES][8] as given
+  BodyMotion* motion = nullptr;
+  // tiles (8^3) and force blocks (4^3)
+  int fblk[3] = {0, 0, 0};
+  int64_t nblocks4 = 0;        // number of 4^3 force blocks
+  int64_t nbflag_words = 0;    // bflag size in 32-bit words
+  uint32_t* cnt_own = nullptr;     // [ntiles] points owned per tile (pass 1)
+  uint32_t* cnt_touch = nullptr;   // [ntiles] points touching each tile (pass 1)
+  uint32_t* fill = nullptr;        // [ntiles] touch-list fill counters (pass 3)
+  uint32_t* start_own = nullptr;   // [ntiles + 1]
+  uint32_t* start_touch = nullptr; // [ntiles + 1]
+  uint32_t* own_tiles = nullptr;   // compact list of tiles owning points
+  uint32_t* touch_tiles = nullptr; // compact list of touched tiles
+  uint32_t* meta = nullptr;        // [4]: list lengths
+  uint8_t* bflag = nullptr;        // [nbflag_words * 4] force-block flags
+  uint32_t* tlist = nullptr;       // touch lists: sorted point slots per tile
+  // scratch
+  double* sum_partials = nullptr;   // [n_cell_blocks][4]
+  int64_t n_cell_blocks = 0;
+  double* pt_partials = nullptr;    // [max_iter + 2][part_row]
+  int64_t part_row = 0;
+  double* small = nullptr;          // [256] reduced results
+
+  // state
+  int64_t npts = 0;
+  int32_t nbodies = 0;
+  int32_t n_iter = 5;
+  uint32_t flags = 0;
+  int64_t step = 0;
+  int64_t g_valid_step = -1;
+  bool g_prescribed = false;
+  bool have_sums = false;  // a stream-collide has written the sum partials
+
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;  // per recorded interval: 0 forcing, 1 stream-collide
+  size_t ev_used = 0;
+  double t_acc[4] = {0, 0, 0, 0};
+
+  std::string err;
+};
+
+// lattice kernels (lbm_kernels.hip)
+hipError_t launch_init_equilibrium(lbm_ctx* c);
+hipError_t launch_unstream_from(lbm_ctx* c, const void* pops, int f64);
+hipError_t launch_stream_collide(lbm_ctx* c);
+hipError_t launch_readout(lbm_ctx* c, float* rho, float* vel, void* pops, int pops_f64);
+hipError_t launch_reduce_sums(lbm_ctx* c, double* out4);
+hipError_t launch_fill_u8(lbm_ctx* c, uint8_t* p, uint8_t v, int64_t n);
+hipError_t launch_fill_u32(lbm_ctx* c, uint32_t* p, uint32_t v, int64_t n);
+hipError_t launch_copy_f32(lbm_ctx* c, float* dst, const float* src, int64_t n);
+hipError_t launch_export_force(lbm_ctx* c, float* out);
+
+// forcing kernels (ibm_kernels.hip)
+hipError_t launch_forcing(lbm_ctx* c);
+int64_t forcing_list_grid(const lbm_ctx* c);
+hipError_t launch_reduce_point_stats(lbm_ctx* c, double* out /* [n_iter + 2] */);
+hipError_t launch_export_points(lbm_ctx* c, double* x, float* ub, float* g, float* du);

@@ -1,0 +1,347 @@
+// Lattice kernels: fused pull stream-collide with forcing (§2, eqs. (1)-(4)
+// and the six-step loop), initial state, checkpoint load, field export and
+// the FP64 mass/momentum reduction.
+#include "internal.h"
+
+using namespace lbmd;
+
+namespace {
+
+// Cell coordinates of a linear cell index (x fastest).
+__device__ __forceinline__ void cell_xyz(const LatticeGeom& g, int64_t cell, int& x, int& y,
+                                         int& z) {
+  const int64_t row = cell / g.nx;
+  x = (int)(cell - row * g.nx);
+  z = (int)(row / g.ny);
+  y = (int)(row - (int64_t)z * g.ny);
+}
+
+// ---------------------------------------------------------------------------
+// Fused stream-collide.  One thread per cell: gather the post-stream offsets
+// (pull), form rho and U (eq. 1), add the force of flagged tiles and the
+// uniform acceleration, relax towards the equilibrium (eqs. 2-3) with the
+// velocity-shift or Guo forcing, store the post-collision offsets.  Each
+// workgroup also writes FP64 partial sums of (rho - 1, rho U).
+// ---------------------------------------------------------------------------
+template <int S, int FORCING>
+__global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
+    const typename Store<S>::T* __restrict__ src, typename Store<S>::T* __restrict__ dst,
+    const LatticeGeom g, const float* __restrict__ G, const uint8_t* __restrict__ flags,
+    double* __restrict__ partials) {
+  const int64_t cell = (int64_t)blockIdx.x * LBM_BLOCK + threadIdx.x;
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+  if (cell < g.ncell) {
+    int x, y, z;
+    cell_xyz(g, cell, x, y, z);
+    float f[Q];
+    gather_pull<S>(src, g, x, y, z, f);
+
+    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      drho += f[i];
+      if (EX[i]) jx += EX[i] * f[i];
+      if (EY[i]) jy += EY[i] * f[i];
+      if (EZ[i]) jz += EZ[i] * f[i];
+    }
+    const float rho = 1.0f + drho;
+    const float inv = 1.0f / rho;
+    float gx = g.g_ext[0], gy = g.g_ext[1], gz = g.g_ext[2];
+    if (flags[fblock_of(g, x, y, z)]) {
+      gx += G[cell];
+      gy += G[g.ncell + cell];
+      gz += G[2 * g.ncell + cell];
+    }
+    float ux, uy, uz;
+    if (FORCING == LBM_FORCE_SHIFT) {
+      ux = jx * inv + g.tau * gx;
+      uy = jy * inv + g.tau * gy;
+      uz = jz * inv + g.tau * gz;
+    } else {
+      ux = jx * inv + 0.5f * gx;
+      uy = jy * inv + 0.5f * gy;
+      uz = jz * inv + 0.5f * gz;
+    }
+    const float uu = ux * ux + uy * uy + uz * uz;
+    const float om = g.omega;
+    const float fx = rho * gx, fy = rho * gy, fz = rho * gz;
+    const float uF = ux * fx + uy * fy + uz * fz;
+    const float guo = 1.0f - 0.5f * om;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const float eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
+      const float feq = wgt(i) * (drho + rho * (3.0f * eu + 4.5f * eu * eu - 1.5f * uu));
+      float post = f[i] + om * (feq - f[i]);
+      if (FORCING == LBM_FORCE_GUO) {
+        const float eF = EX[i] * fx + EY[i] * fy + EZ[i] * fz;
+        post += guo * wgt(i) * (3.0f * (eF - uF) + 9.0f * eu * eF);
+      }
+      Store<S>::store(dst + (int64_t)i * g.stride + cell, post);
+    }
+    part[0] = drho;
+    part[1] = jx;
+    part[2] = jy;
+    part[3] = jz;
+  }
+  __shared__ double red[4][LBM_BLOCK / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double v = wave_sum(part[k]);
+    if (lane == 0) red[k][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < LBM_BLOCK / 64; ++w) s += red[threadIdx.x][w];
+    partials[(int64_t)blockIdx.x * 4 + threadIdx.x] = s;
+  }
+}
+
+// Loads post-stream populations f (full values, float or double) as the
+// state at the start of a step: the post-collision lattice is their inverse
+// stream, f*_i(Y) = f_i(Y + e_i), or at a wall f*_i(Y) = f_opp(i)(Y) + bb_add.
+struct SrcPops {
+  const void* p;
+  int f64;
+  int64_t n;
+  __device__ double get(int i, int64_t cell) const {
+    const int64_t k = (int64_t)i * n + cell;
+    return f64 ? ((const double*)p)[k] - wgt_d(i) : (double)((const float*)p)[k] - wgt_d(i);
+  }
+};
+// Uniform equilibrium offsets Eq_i(rho0, u0) - t_i (eq. 3 with density).
+struct SrcUniform {
+  double feq[Q];
+  __device__ double get(int i, int64_t) const { return feq[i]; }
+};
+
+template <int S, class Src>
+__global__ __launch_bounds__(LBM_BLOCK) void k_unstream(typename Store<S>::T* __restrict__ dst,
+                                                        const LatticeGeom g, const Src src) {
+  const int64_t cell = (int64_t)blockIdx.x * LBM_BLOCK + threadIdx.x;
+  if (cell >= g.ncell) return;
+  int x, y, z;
+  cell_xyz(g, cell, x, y, z);
+  const int n[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int d[3] = {x + EX[i], y + EY[i], z + EZ[i]};
+    const int e[3] = {EX[i], EY[i], EZ[i]};
+    int wall_axis = -1, wall_face = 0;
+    for (int a = 0; a < 3; ++a) {
+      if (e[a] != 0 && (d[a] < 0 || d[a] >= n[a])) {
+        if (g.bc[a] == LBM_BC_PERIODIC) {
+          d[a] = d[a] < 0 ? d[a] + n[a] : d[a] - n[a];
+        } else if (wall_axis < 0) {
+          wall_axis = a;
+          wall_face = d[a] < 0 ? 0 : 1;
+        }
+      }
+    }
+    double v;
+    if (wall_axis < 0)
+      v = src.get(i, (int64_t)d[0] + (int64_t)g.nx * ((int64_t)d[1] + (int64_t)g.ny * d[2]));
+    else
+      v = src.get(OPP[i], cell) + (double)g.bb_add[wall_axis][wall_face][i];
+    Store<S>::store(dst + (int64_t)i * g.stride + cell, (float)v);
+  }
+}
+
+// Export: density, velocity and post-stream populations of every cell.
+template <int S>
+__global__ __launch_bounds__(LBM_BLOCK) void k_readout(const typename Store<S>::T* __restrict__ lat,
+                                                       const LatticeGeom g, float* rho_out,
+                                                       float* vel_out, void* pops_out,
+                                                       int pops_f64) {
+  const int64_t cell = (int64_t)blockIdx.x * LBM_BLOCK + threadIdx.x;
+  if (cell >= g.ncell) return;
+  int x, y, z;
+  cell_xyz(g, cell, x, y, z);
+  float f[Q];
+  gather_pull<S>(lat, g, x, y, z, f);
+  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += f[i];
+    jx += EX[i] * f[i];
+    jy += EY[i] * f[i];
+    jz += EZ[i] * f[i];
+  }
+  const float rho = 1.0f + drho;
+  if (rho_out) rho_out[cell] = rho;
+  if (vel_out) {
+    vel_out[cell] = jx / rho;
+    vel_out[g.ncell + cell] = jy / rho;
+    vel_out[2 * g.ncell + cell] = jz / rho;
+  }
+  if (pops_out) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (pops_f64)
+        ((double*)pops_out)[(int64_t)i * g.ncell + cell] = wgt_d(i) + (double)f[i];
+      else
+        ((float*)pops_out)[(int64_t)i * g.ncell + cell] = wgt(i) + f[i];
+    }
+  }
+}
+
+// Sum of the per-workgroup partials (single workgroup, fixed order).
+__global__ __launch_bounds__(LBM_BLOCK) void k_reduce_sums(const double* __restrict__ partials,
+                                                           int64_t nblocks, double ncell,
+                                                           double* out) {
+  double s[4] = {0, 0, 0, 0};
+  for (int64_t b = threadIdx.x; b < nblocks; b += LBM_BLOCK)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[k] += partials[b * 4 + k];
+  __shared__ double red[4][LBM_BLOCK / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double v = wave_sum(s[k]);
+    if (lane == 0) red[k][wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double v = 0.0;
+    for (int w = 0; w < LBM_BLOCK / 64; ++w) v += red[threadIdx.x][w];
+    out[threadIdx.x] = threadIdx.x == 0 ? ncell + v : v;
+  }
+}
+
+template <class T>
+__global__ void k_fill(T* p, T v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_copy_f32(float* __restrict__ d, const float* __restrict__ s, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+
+// G of flagged blocks, zero elsewhere (G is only maintained where supports reach).
+__global__ __launch_bounds__(LBM_BLOCK) void k_export_force(const float* __restrict__ G,
+                                                            const uint8_t* __restrict__ flags,
+                                                            const LatticeGeom g, float* out) {
+  const int64_t cell = (int64_t)blockIdx.x * LBM_BLOCK + threadIdx.x;
+  if (cell >= g.ncell) return;
+  int x, y, z;
+  cell_xyz(g, cell, x, y, z);
+  const bool on = flags[fblock_of(g, x, y, z)] != 0;
+  for (int c = 0; c < 3; ++c) out[c * g.ncell + cell] = on ? G[c * g.ncell + cell] : 0.0f;
+}
+
+int64_t cell_blocks(const lbm_ctx* c) { return (c->ncell + LBM_BLOCK - 1) / LBM_BLOCK; }
+
+template <int S>
+hipError_t stream_collide_s(lbm_ctx* c) {
+  using T = typename Store<S>::T;
+  const T* src = (const T*)c->lat[c->cur];
+  T* dst = (T*)c->lat[c->cur ^ 1];
+  dim3 grid((unsigned)cell_blocks(c));
+  if (c->p.forcing == LBM_FORCE_SHIFT)
+    k_stream_collide<S, LBM_FORCE_SHIFT><<<grid, LBM_BLOCK, 0, c->stream>>>(
+        src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+  else
+    k_stream_collide<S, LBM_FORCE_GUO><<<grid, LBM_BLOCK, 0, c->stream>>>(
+        src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+  return hipGetLastError();
+}
+
+template <int S, class Src>
+hipError_t unstream_s(lbm_ctx* c, const Src& src) {
+  using T = typename Store<S>::T;
+  k_unstream<S, Src><<<(unsigned)cell_blocks(c), LBM_BLOCK, 0, c->stream>>>(
+      (T*)c->lat[c->cur], c->geom, src);
+  return hipGetLastError();
+}
+
+template <class Src>
+hipError_t unstream_any(lbm_ctx* c, const Src& src) {
+  switch (c->p.storage) {
+    case LBM_STORE_F16: return unstream_s<LBM_STORE_F16>(c, src);
+    case LBM_STORE_BF16: return unstream_s<LBM_STORE_BF16>(c, src);
+    default: return unstream_s<LBM_STORE_F32>(c, src);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_stream_collide(lbm_ctx* c) {
+  hipError_t e;
+  switch (c->p.storage) {
+    case LBM_STORE_F16: e = stream_collide_s<LBM_STORE_F16>(c); break;
+    case LBM_STORE_BF16: e = stream_collide_s<LBM_STORE_BF16>(c); break;
+    default: e = stream_collide_s<LBM_STORE_F32>(c); break;
+  }
+  if (e == hipSuccess) c->cur ^= 1;
+  return e;
+}
+
+hipError_t launch_init_equilibrium(lbm_ctx* c) {
+  SrcUniform s;
+  const double rho = c->p.rho0;
+  const double* u = c->p.u0;
+  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  for (int i = 0; i < Q; ++i) {
+    const double eu = EX[i] * u[0] + EY[i] * u[1] + EZ[i] * u[2];
+    s.feq[i] = wgt_d(i) * (rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu) - 1.0);
+  }
+  return unstream_any(c, s);
+}
+
+hipError_t launch_unstream_from(lbm_ctx* c, const void* pops, int f64) {
+  SrcPops s{pops, f64, c->ncell};
+  return unstream_any(c, s);
+}
+
+hipError_t launch_readout(lbm_ctx* c, float* rho, float* vel, void* pops, int pops_f64) {
+  const unsigned nb = (unsigned)cell_blocks(c);
+  switch (c->p.storage) {
+    case LBM_STORE_F16:
+      k_readout<LBM_STORE_F16><<<nb, LBM_BLOCK, 0, c->stream>>>(
+          (const _Float16*)c->lat[c->cur], c->geom, rho, vel, pops, pops_f64);
+      break;
+    case LBM_STORE_BF16:
+      k_readout<LBM_STORE_BF16><<<nb, LBM_BLOCK, 0, c->stream>>>(
+          (const uint16_t*)c->lat[c->cur], c->geom, rho, vel, pops, pops_f64);
+      break;
+    default:
+      k_readout<LBM_STORE_F32><<<nb, LBM_BLOCK, 0, c->stream>>>(
+          (const float*)c->lat[c->cur], c->geom, rho, vel, pops, pops_f64);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_sums(lbm_ctx* c, double* out4) {
+  k_reduce_sums<<<1, LBM_BLOCK, 0, c->stream>>>(c->sum_partials, cell_blocks(c),
+                                                (double)c->ncell, out4);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(lbm_ctx* c, uint8_t* p, uint8_t v, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  k_fill<uint8_t><<<(unsigned)std::min<int64_t>((n + 255) / 256, 4096), 256, 0, c->stream>>>(p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(lbm_ctx* c, uint32_t* p, uint32_t v, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  k_fill<uint32_t><<<(unsigned)std::min<int64_t>((n + 255) / 256, 4096), 256, 0, c->stream>>>(p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f32(lbm_ctx* c, float* dst, const float* src, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  k_copy_f32<<<(unsigned)std::min<int64_t>((n + 255) / 256, 8192), 256, 0, c->stream>>>(dst, src, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_force(lbm_ctx* c, float* out) {
+  k_export_force<<<(unsigned)cell_blocks(c), LBM_BLOCK, 0, c->stream>>>(c->G, c->bflag, c->geom, out);
+  return hipGetLastError();
+}

@@ -1,0 +1,666 @@
+// C ABI of the LBM-IBM library (declared in include/lbmibm.h): argument
+// checks, carving of the caller buffers, the per-step kernel sequence and
+// field import/export.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Byte offsets of every array inside the caller buffers.
+struct Plan {
+  size_t size[LBM_NBUF];
+  // lattice
+  size_t elem, pop_stride, lat_bytes;
+  // points
+  size_t o_rest, o_body_of, o_key, o_rank, o_base, o_frac, o_ub, o_g, o_du, o_tlist, o_bodies,
+      o_motion;
+  // tiles
+  size_t o_cnt_own, o_cnt_touch, o_fill, o_start_own, o_start_touch, o_own_tiles, o_touch_tiles,
+      o_meta, o_bflag;
+  int64_t nblocks4, nbflag_words;
+  int fblk[3];
+  size_t tlist_mult;
+  // scratch
+  size_t o_sum_part, o_pt_part, o_small;
+  int64_t part_row;
+  int64_t n_cell_blocks, n_pt_blocks;
+  int64_t ncell, ntiles;
+  int tiles[3];
+};
+
+struct Cursor {
+  size_t at = 0;
+  size_t take(size_t bytes) {
+    size_t o = at;
+    at = align_up(at + bytes);
+    return o;
+  }
+};
+
+lbm_status check_params(const lbm_params* p, std::string& msg) {
+  if (!p) {
+    msg = "params is NULL";
+    return LBM_ERR_ARG;
+  }
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) {
+    msg = "lattice sizes must be >= 1";
+    return LBM_ERR_ARG;
+  }
+  const int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
+  if (ncell > ((int64_t)1 << 31) - 1) {
+    msg = "lattice larger than 2^31 - 1 cells";
+    return LBM_ERR_ARG;
+  }
+  for (int a = 0; a < 3; ++a)
+    if (p->bc[a] != LBM_BC_PERIODIC && p->bc[a] != LBM_BC_BOUNCEBACK) {
+      msg = "bc must be LBM_BC_PERIODIC or LBM_BC_BOUNCEBACK";
+      return LBM_ERR_ARG;
+    }
+  if (p->storage < LBM_STORE_F32 || p->storage > LBM_STORE_BF16) {
+    msg = "unknown storage";
+    return LBM_ERR_ARG;
+  }
+  if (p->forcing != LBM_FORCE_GUO && p->forcing != LBM_FORCE_SHIFT) {
+    msg = "unknown forcing";
+    return LBM_ERR_ARG;
+  }
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) {
+    msg = "tau must be finite and > 0.5";
+    return LBM_ERR_ARG;
+  }
+  if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0) || !std::isfinite(p->rho_wall)) {
+    msg = "rho0 must be > 0 and rho_wall finite";
+    return LBM_ERR_ARG;
+  }
+  const double* d = &p->wall_u[0][0][0];
+  for (int k = 0; k < 18; ++k)
+    if (!std::isfinite(d[k])) {
+      msg = "wall_u must be finite";
+      return LBM_ERR_ARG;
+    }
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p->g_ext[a]) || !std::isfinite(p->u0[a])) {
+      msg = "g_ext and u0 must be finite";
+      return LBM_ERR_ARG;
+    }
+  if (p->max_points < 0 || p->max_points > ((int64_t)1 << 31) - 1) {
+    msg = "max_points must be in [0, 2^31 - 1]";
+    return LBM_ERR_ARG;
+  }
+  if (p->max_iter < 1 || p->max_iter > LBM_MAX_ITER) {
+    msg = "max_iter must be in [1, 64]";
+    return LBM_ERR_ARG;
+  }
+  if (p->reserved_ != 0) {
+    msg = "reserved_ must be 0";
+    return LBM_ERR_ARG;
+  }
+  return LBM_OK;
+}
+
+void make_plan(const lbm_params* p, Plan& pl) {
+  pl.ncell = (int64_t)p->nx * p->ny * p->nz;
+  pl.elem = p->storage == LBM_STORE_F32 ? 4 : 2;
+  pl.pop_stride = align_up((size_t)pl.ncell * pl.elem) / pl.elem;
+  pl.lat_bytes = pl.pop_stride * pl.elem * lbmd::Q;
+  pl.size[LBM_BUF_LATTICE] = 2 * pl.lat_bytes;
+  pl.size[LBM_BUF_FIELDS] = 2 * align_up(3 * (size_t)pl.ncell * sizeof(float));
+
+  const size_t M = (size_t)std::max<int64_t>(p->max_points, 1);
+  const int dims[3] = {p->nx, p->ny, p->nz};
+  pl.tlist_mult = 1;
+  for (int a = 0; a < 3; ++a) {
+    pl.tiles[a] = (dims[a] + lbmd::TILE - 1) / lbmd::TILE;
+    pl.fblk[a] = (dims[a] + lbmd::FBLK - 1) / lbmd::FBLK;
+    // distinct tiles among 4 consecutive (wrapped) cells: 3 only when a last
+    // tile of 1 or 2 cells can be crossed
+    const int r = dims[a] % lbmd::TILE;
+    const int m = (r == 1 || r == 2) ? 3 : 2;
+    pl.tlist_mult *= (size_t)std::min(pl.tiles[a], m);
+  }
+  pl.ntiles = (int64_t)pl.tiles[0] * pl.tiles[1] * pl.tiles[2];
+  pl.nblocks4 = (int64_t)pl.fblk[0] * pl.fblk[1] * pl.fblk[2];
+  pl.nbflag_words = (pl.nblocks4 + 3) / 4;
+
+  Cursor pc;
+  pl.o_rest = pc.take(M * sizeof(float4));
+  pl.o_body_of = pc.take(M * sizeof(int32_t));
+  pl.o_key = pc.take(M * sizeof(uint32_t));
+  pl.o_rank = pc.take(M * sizeof(uint32_t));
+  pl.o_base = pc.take(M * sizeof(int4));
+  pl.o_frac = pc.take(M * sizeof(float4));
+  pl.o_ub = pc.take(M * sizeof(float4));
+  pl.o_g = pc.take(M * sizeof(float4));
+  pl.o_du = pc.take(M * sizeof(float4));
+  pl.o_tlist = pc.take(M * pl.tlist_mult * sizeof(uint32_t));
+  pl.o_bodies = pc.take((size_t)LBM_MAX_BODIES * 8 * sizeof(double));
+  pl.o_motion = pc.take((size_t)LBM_MAX_BODIES * sizeof(BodyMotion));
+  pl.size[LBM_BUF_POINTS] = pc.at;
+
+  const size_t NT = (size_t)pl.ntiles;
+  Cursor tc;
+  pl.o_cnt_own = tc.take(NT * 4);
+  pl.o_cnt_touch = tc.take(NT * 4);
+  pl.o_fill = tc.take(NT * 4);
+  pl.o_start_own = tc.take((NT + 1) * 4);
+  pl.o_start_touch = tc.take((NT + 1) * 4);
+  pl.o_own_tiles = tc.take(NT * 4);
+  pl.o_touch_tiles = tc.take(NT * 4);
+  pl.o_meta = tc.take(4 * 4);
+  pl.o_bflag = tc.take((size_t)pl.nbflag_words * 4);
+  pl.size[LBM_BUF_TILES] = tc.at;
+
+  pl.n_cell_blocks = (pl.ncell + LBM_BLOCK - 1) / LBM_BLOCK;
+  pl.n_pt_blocks = ((int64_t)M + LBM_BLOCK - 1) / LBM_BLOCK;
+  pl.part_row = std::max<int64_t>(pl.n_pt_blocks, (pl.ntiles + 7) / 8 * 8);
+  Cursor sc;
+  pl.o_sum_part = sc.take((size_t)pl.n_cell_blocks * 4 * sizeof(double));
+  pl.o_pt_part = sc.take((size_t)(p->max_iter + 2) * pl.part_row * sizeof(double));
+  pl.o_small = sc.take(256 * sizeof(double));
+  pl.size[LBM_BUF_SCRATCH] = sc.at;
+}
+
+lbm_status fail(lbm_ctx* c, lbm_status st, const std::string& msg) {
+  c->err = msg;
+  return st;
+}
+
+lbm_status hip_fail(lbm_ctx* c, hipError_t e, const char* where) {
+  c->err = std::string(where) + ": " + hipGetErrorString(e);
+  return LBM_ERR_HIP;
+}
+
+#define HIP_TRY(ctx, expr)                                    \
+  do {                                                        \
+    hipError_t e_ = (expr);                                   \
+    if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr);  \
+  } while (0)
+
+void fill_geom(lbm_ctx* c, const Plan& pl) {
+  lbmd::LatticeGeom& g = c->geom;
+  const lbm_params& p = c->p;
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.nz = p.nz;
+  for (int a = 0; a < 3; ++a) g.bc[a] = p.bc[a];
+  g.ncell = pl.ncell;
+  g.stride = (int64_t)pl.pop_stride;
+  for (int a = 0; a < 3; ++a)
+    for (int f = 0; f < 2; ++f)
+      for (int i = 0; i < lbmd::Q; ++i) {
+        const double* u = p.wall_u[a][f];
+        const double eu = lbmd::EX[i] * u[0] + lbmd::EY[i] * u[1] + lbmd::EZ[i] * u[2];
+        g.bb_add[a][f][i] = (float)(6.0 * lbmd::wgt_d(i) * p.rho_wall * eu);
+      }
+  g.tau = (float)p.tau;
+  g.omega = (float)(1.0 / p.tau);
+  for (int a = 0; a < 3; ++a) g.g_ext[a] = (float)p.g_ext[a];
+  g.fblk_x = pl.fblk[0];
+  g.fblk_y = pl.fblk[1];
+}
+
+// Timing: events recorded around the forcing and the stream-collide.
+void ev_record(lbm_ctx* c, int kind, bool start) {
+  if (!c->timing) return;
+  if (c->ev_used + 1 >= c->ev_pool.size()) {
+    size_t old = c->ev_pool.size();
+    c->ev_pool.resize(std::max<size_t>(64, 2 * old));
+    for (size_t k = old; k < c->ev_pool.size(); ++k) (void)hipEventCreate(&c->ev_pool[k]);
+  }
+  (void)hipEventRecord(c->ev_pool[c->ev_used++], c->stream);
+  if (start) c->ev_kind.push_back(kind);
+}
+
+void ev_collect(lbm_ctx* c) {
+  if (c->ev_used == 0) return;
+  (void)hipEventSynchronize(c->ev_pool[c->ev_used - 1]);
+  for (size_t k = 0; k + 1 < c->ev_used && k / 2 < c->ev_kind.size(); k += 2) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]);
+    const int kind = c->ev_kind[k / 2];
+    c->t_acc[kind] += ms;
+    c->t_acc[2 + kind] += 1.0;
+  }
+  c->ev_used = 0;
+  c->ev_kind.clear();
+}
+
+lbm_status do_forcing(lbm_ctx* c) {
+  ev_record(c, 0, true);
+  hipError_t e = launch_forcing(c);
+  if (e != hipSuccess) return hip_fail(c, e, "forcing");
+  ev_record(c, 0, false);
+  if (c->ev_used > 4000) ev_collect(c);
+  c->g_valid_step = c->step;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_buffer_sizes(const lbm_params* p, size_t sizes_out[LBM_NBUF]) {
+  std::string msg;
+  lbm_status st = check_params(p, msg);
+  if (st != LBM_OK) {
+    g_create_error = msg;
+    return st;
+  }
+  if (!sizes_out) {
+    g_create_error = "sizes_out is NULL";
+    return LBM_ERR_ARG;
+  }
+  Plan pl;
+  make_plan(p, pl);
+  for (int b = 0; b < LBM_NBUF; ++b) sizes_out[b] = pl.size[b];
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx** out) {
+  std::string msg;
+  lbm_status st = check_params(p, msg);
+  if (st != LBM_OK) {
+    g_create_error = msg;
+    return st;
+  }
+  if (!out || !bufs) {
+    g_create_error = "bufs or out is NULL";
+    return LBM_ERR_ARG;
+  }
+  for (int b = 0; b < LBM_NBUF; ++b)
+    if (!bufs[b] || ((uintptr_t)bufs[b] % ALIGN) != 0) {
+      g_create_error = "buffer " + std::to_string(b) + " is NULL or not 256-byte aligned";
+      return LBM_ERR_OOM;
+    }
+  Plan pl;
+  make_plan(p, pl);
+  lbm_ctx* c = new lbm_ctx();
+  c->p = *p;
+  c->stream = (hipStream_t)p->stream;
+  (void)hipGetDevice(&c->device);
+  c->ncell = pl.ncell;
+  for (int a = 0; a < 3; ++a) c->tiles[a] = pl.tiles[a];
+  c->ntiles = pl.ntiles;
+  c->elem = pl.elem;
+  fill_geom(c, pl);
+
+  char* L = (char*)bufs[LBM_BUF_LATTICE];
+  c->lat[0] = L;
+  c->lat[1] = L + pl.lat_bytes;
+  char* F = (char*)bufs[LBM_BUF_FIELDS];
+  c->U = (float*)F;
+  c->G = (float*)(F + align_up(3 * (size_t)pl.ncell * sizeof(float)));
+  char* P = (char*)bufs[LBM_BUF_POINTS];
+  c->rest = (float4*)(P + pl.o_rest);
+  c->body_of = (int32_t*)(P + pl.o_body_of);
+  c->key = (uint32_t*)(P + pl.o_key);
+  c->rank = (uint32_t*)(P + pl.o_rank);
+  c->sp_base = (int4*)(P + pl.o_base);
+  c->sp_frac = (float4*)(P + pl.o_frac);
+  c->sp_ub = (float4*)(P + pl.o_ub);
+  c->sp_g = (float4*)(P + pl.o_g);
+  c->sp_du = (float4*)(P + pl.o_du);
+  c->bodies = (double*)(P + pl.o_bodies);
+  c->motion = (BodyMotion*)(P + pl.o_motion);
+  c->tlist = (uint32_t*)(P + pl.o_tlist);
+  char* T = (char*)bufs[LBM_BUF_TILES];
+  for (int a = 0; a < 3; ++a) c->fblk[a] = pl.fblk[a];
+  c->nblocks4 = pl.nblocks4;
+  c->nbflag_words = pl.nbflag_words;
+  c->cnt_own = (uint32_t*)(T + pl.o_cnt_own);
+  c->cnt_touch = (uint32_t*)(T + pl.o_cnt_touch);
+  c->fill = (uint32_t*)(T + pl.o_fill);
+  c->start_own = (uint32_t*)(T + pl.o_start_own);
+  c->start_touch = (uint32_t*)(T + pl.o_start_touch);
+  c->own_tiles = (uint32_t*)(T + pl.o_own_tiles);
+  c->touch_tiles = (uint32_t*)(T + pl.o_touch_tiles);
+  c->meta = (uint32_t*)(T + pl.o_meta);
+  c->bflag = (uint8_t*)(T + pl.o_bflag);
+  char* S = (char*)bufs[LBM_BUF_SCRATCH];
+  c->sum_partials = (double*)(S + pl.o_sum_part);
+  c->n_cell_blocks = pl.n_cell_blocks;
+  c->pt_partials = (double*)(S + pl.o_pt_part);
+  c->part_row = pl.part_row;
+  c->small = (double*)(S + pl.o_small);
+
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = launch_fill_u32(c, c->cnt_own, 0u, c->ntiles);
+  if (e == hipSuccess) e = launch_fill_u32(c, c->cnt_touch, 0u, c->ntiles);
+  if (e == hipSuccess) e = launch_fill_u32(c, c->fill, 0u, c->ntiles);
+  if (e == hipSuccess) e = launch_fill_u32(c, c->meta, 0u, 4);
+  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->bflag, 0u, c->nbflag_words);
+  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->U, 0u, 3 * c->ncell);
+  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->G, 0u, 3 * c->ncell);
+  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->sum_partials, 0u, 8 * c->n_cell_blocks);
+  if (e == hipSuccess) e = launch_init_equilibrium(c);
+  if (e != hipSuccess) {
+    g_create_error = std::string("initialisation: ") + hipGetErrorString(e);
+    delete c;
+    return LBM_ERR_HIP;
+  }
+  c->have_sums = false;
+  *out = c;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  for (auto& ev : c->ev_pool) (void)hipEventDestroy(ev);
+  delete c;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) {
+  return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const float* area,
+                          const int64_t* body_off, int32_t nbodies, const ibm_body* bodies,
+                          int32_t n_iter, uint32_t flags, float eps) {
+  if (!c) return LBM_ERR_ARG;
+  if (n < 0 || n > c->p.max_points)
+    return fail(c, LBM_ERR_ARG, "n must be in [0, max_points]");
+  if (n == 0) {
+    c->npts = 0;
+    c->nbodies = 0;
+    c->g_valid_step = -1;
+    c->g_prescribed = false;
+    hipError_t e = launch_fill_u32(c, (uint32_t*)c->bflag, 0u, c->nbflag_words);
+    if (e != hipSuccess) return hip_fail(c, e, "clear force-block flags");
+    return LBM_OK;
+  }
+  if (!rest_xyz || !area || !body_off || !bodies)
+    return fail(c, LBM_ERR_ARG, "NULL point array");
+  if (nbodies < 1 || nbodies > LBM_MAX_BODIES)
+    return fail(c, LBM_ERR_ARG, "nbodies must be in [1, 65536]");
+  if (n_iter < 1 || n_iter > c->p.max_iter)
+    return fail(c, LBM_ERR_ARG, "n_iter must be in [1, max_iter]");
+  if (flags & ~(uint32_t)IBM_INNER_UNWEIGHTED) return fail(c, LBM_ERR_ARG, "unknown flags");
+  if (eps != 0.0f) return fail(c, LBM_ERR_ARG, "eps is reserved and must be 0");
+  if (body_off[0] != 0 || body_off[nbodies] != n)
+    return fail(c, LBM_ERR_ARG, "body_off must start at 0 and end at n");
+  for (int b = 0; b < nbodies; ++b)
+    if (body_off[b + 1] < body_off[b]) return fail(c, LBM_ERR_ARG, "body_off must not decrease");
+  std::vector<float4> rest((size_t)n);
+  std::vector<int32_t> body_of((size_t)n);
+  std::vector<double> btab((size_t)nbodies * 8);
+  const int dims[3] = {c->p.nx, c->p.ny, c->p.nz};
+  for (int b = 0; b < nbodies; ++b) {
+    const ibm_body& B = bodies[b];
+    const double al = std::sqrt(B.axis[0] * B.axis[0] + B.axis[1] * B.axis[1] + B.axis[2] * B.axis[2]);
+    if (!(al > 0.0) || !std::isfinite(al) || !std::isfinite(B.theta0) || !std::isfinite(B.omega))
+      return fail(c, LBM_ERR_ARG, "body axis must be nonzero and finite; theta0, omega finite");
+    double rmax = 0.0;
+    for (int64_t k = body_off[b]; k < body_off[b + 1]; ++k) {
+      const float* r = rest_xyz + 3 * k;
+      if (!std::isfinite(r[0]) || !std::isfinite(r[1]) || !std::isfinite(r[2]) ||
+          !std::isfinite(area[k]) || area[k] < 0.0f)
+        return fail(c, LBM_ERR_ARG, "rest positions must be finite and areas finite, >= 0");
+      rest[(size_t)k] = make_float4(r[0], r[1], r[2], area[k]);
+      body_of[(size_t)k] = b;
+      rmax = std::max(rmax, std::sqrt((double)r[0] * r[0] + (double)r[1] * r[1] + (double)r[2] * r[2]));
+    }
+    for (int a = 0; a < 3; ++a) {
+      if (!std::isfinite(B.center[a])) return fail(c, LBM_ERR_ARG, "body centre must be finite");
+      if (c->p.bc[a] == LBM_BC_BOUNCEBACK && body_off[b + 1] > body_off[b]) {
+        // every support must stay inside: 1 <= x < n - 2 for all angles
+        const double margin = 1e-6 * (1.0 + rmax + std::fabs(B.center[a]));
+        if (B.center[a] - rmax < 1.0 + margin || B.center[a] + rmax >= dims[a] - 2.0 - margin)
+          return fail(c, LBM_ERR_DOMAIN, "a body's kernel support can cross a wall");
+      }
+    }
+    for (int a = 0; a < 3; ++a) {
+      btab[8 * b + a] = B.center[a];
+      btab[8 * b + 3 + a] = B.axis[a];
+    }
+    btab[8 * b + 6] = B.theta0;
+    btab[8 * b + 7] = B.omega;
+  }
+  HIP_TRY(c, hipMemcpyAsync(c->rest, rest.data(), rest.size() * sizeof(float4), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->body_of, body_of.data(), body_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->bodies, btab.data(), btab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->npts = n;
+  c->nbodies = nbodies;
+  c->n_iter = n_iter;
+  c->flags = flags;
+  c->g_valid_step = -1;
+  c->g_prescribed = false;
+  return LBM_OK;
+}
+
+lbm_status ibm_force_iterate(lbm_ctx* c, ibm_stats* stats) {
+  if (!c) return LBM_ERR_ARG;
+  if (c->npts == 0) return fail(c, LBM_ERR_STATE, "no Lagrangian points set");
+  lbm_status st = do_forcing(c);
+  if (st != LBM_OK) return st;
+  if (stats) {
+    hipError_t e = launch_reduce_point_stats(c, c->small);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce point stats");
+    double h[2 + LBM_MAX_ITER];
+    HIP_TRY(c, hipMemcpyAsync(h, c->small, sizeof(double) * (2 + c->n_iter), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::memset(stats, 0, sizeof(*stats));
+    stats->n_iter = c->n_iter;
+    stats->sum_s = h[0];
+    stats->sum_s_ub2 = h[1];
+    for (int it = 0; it < c->n_iter; ++it) stats->resid[it] = h[2 + it];
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int32_t n_steps) {
+  if (!c) return LBM_ERR_ARG;
+  if (n_steps < 0) return fail(c, LBM_ERR_ARG, "n_steps must be >= 0");
+  for (int32_t s = 0; s < n_steps; ++s) {
+    if (c->npts > 0 && c->g_valid_step != c->step) {
+      lbm_status st = do_forcing(c);
+      if (st != LBM_OK) return st;
+    }
+    ev_record(c, 1, true);
+    hipError_t e = launch_stream_collide(c);
+    if (e != hipSuccess) return hip_fail(c, e, "stream_collide");
+    ev_record(c, 1, false);
+    if (c->ev_used > 4000) ev_collect(c);
+    c->have_sums = true;
+    c->step += 1;
+  }
+  return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Device staging for host destinations/sources.
+struct Staging {
+  void* p = nullptr;
+  ~Staging() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_read_fields(lbm_ctx* c, uint32_t mask, const lbm_fields* dst) {
+  if (!c) return LBM_ERR_ARG;
+  if (!dst) return fail(c, LBM_ERR_ARG, "dst is NULL");
+  const uint32_t known = LBM_F_RHO | LBM_F_VEL | LBM_F_FORCE | LBM_F_POPS | LBM_F_PT_X |
+                         LBM_F_PT_UB | LBM_F_PT_G | LBM_F_PT_DU | LBM_F_SUMS | LBM_F_STEP;
+  if (mask & ~known) return fail(c, LBM_ERR_ARG, "unknown field bits");
+  const bool dev = dst->on_device != 0;
+  const size_t nc = (size_t)c->ncell, np = (size_t)c->npts;
+  const size_t pop_b = (dst->pops_f64 ? 8 : 4) * 19 * nc;
+  if ((mask & LBM_F_RHO) && !dst->rho) return fail(c, LBM_ERR_ARG, "rho is NULL");
+  if ((mask & LBM_F_VEL) && !dst->vel) return fail(c, LBM_ERR_ARG, "vel is NULL");
+  if ((mask & LBM_F_FORCE) && !dst->force) return fail(c, LBM_ERR_ARG, "force is NULL");
+  if ((mask & LBM_F_POPS) && !dst->pops) return fail(c, LBM_ERR_ARG, "pops is NULL");
+  if ((mask & LBM_F_SUMS) && !dst->sums) return fail(c, LBM_ERR_ARG, "sums is NULL");
+  if ((mask & LBM_F_STEP) && !dst->step) return fail(c, LBM_ERR_ARG, "step is NULL");
+  if ((mask & LBM_F_SUMS) && !c->have_sums) return fail(c, LBM_ERR_STATE, "no step has run yet");
+  const uint32_t ptm = LBM_F_PT_X | LBM_F_PT_UB | LBM_F_PT_G | LBM_F_PT_DU;
+  if (mask & ptm) {
+    if (c->g_valid_step < 0) return fail(c, LBM_ERR_STATE, "no forcing has run for the current points");
+    if (((mask & LBM_F_PT_X) && !dst->pt_x) || ((mask & LBM_F_PT_UB) && !dst->pt_ub) ||
+        ((mask & LBM_F_PT_G) && !dst->pt_g) || ((mask & LBM_F_PT_DU) && !dst->pt_du))
+      return fail(c, LBM_ERR_ARG, "NULL point destination");
+  }
+
+  // Device destinations, or staging buffers for host ones.
+  float *rho = dst->rho, *vel = dst->vel, *force = dst->force;
+  void* pops = dst->pops;
+  double* ptx = dst->pt_x;
+  float *ptub = dst->pt_ub, *ptg = dst->pt_g, *ptdu = dst->pt_du;
+  double* sums = dst->sums;
+  Staging st;
+  if (!dev) {
+    size_t bytes = 0;
+    auto want = [&](uint32_t bit, size_t b) -> size_t {
+      if (!(mask & bit)) return 0;
+      size_t o = bytes;
+      bytes = align_up(bytes + b);
+      return o;
+    };
+    size_t o_rho = want(LBM_F_RHO, 4 * nc), o_vel = want(LBM_F_VEL, 12 * nc),
+           o_f = want(LBM_F_FORCE, 12 * nc), o_p = want(LBM_F_POPS, pop_b),
+           o_x = want(LBM_F_PT_X, 24 * np), o_ub = want(LBM_F_PT_UB, 12 * np),
+           o_g = want(LBM_F_PT_G, 12 * np), o_du = want(LBM_F_PT_DU, 12 * np),
+           o_s = want(LBM_F_SUMS, 32);
+    if (bytes) HIP_TRY(c, hipMalloc(&st.p, bytes));
+    char* b = (char*)st.p;
+    rho = (mask & LBM_F_RHO) ? (float*)(b + o_rho) : nullptr;
+    vel = (mask & LBM_F_VEL) ? (float*)(b + o_vel) : nullptr;
+    force = (mask & LBM_F_FORCE) ? (float*)(b + o_f) : nullptr;
+    pops = (mask & LBM_F_POPS) ? (void*)(b + o_p) : nullptr;
+    ptx = (mask & LBM_F_PT_X) ? (double*)(b + o_x) : nullptr;
+    ptub = (mask & LBM_F_PT_UB) ? (float*)(b + o_ub) : nullptr;
+    ptg = (mask & LBM_F_PT_G) ? (float*)(b + o_g) : nullptr;
+    ptdu = (mask & LBM_F_PT_DU) ? (float*)(b + o_du) : nullptr;
+    sums = (mask & LBM_F_SUMS) ? (double*)(b + o_s) : nullptr;
+  } else {
+    if (!(mask & LBM_F_RHO)) rho = nullptr;
+    if (!(mask & LBM_F_VEL)) vel = nullptr;
+    if (!(mask & LBM_F_FORCE)) force = nullptr;
+    if (!(mask & LBM_F_POPS)) pops = nullptr;
+    if (!(mask & LBM_F_PT_X)) ptx = nullptr;
+    if (!(mask & LBM_F_PT_UB)) ptub = nullptr;
+    if (!(mask & LBM_F_PT_G)) ptg = nullptr;
+    if (!(mask & LBM_F_PT_DU)) ptdu = nullptr;
+    if (!(mask & LBM_F_SUMS)) sums = nullptr;
+  }
+  hipError_t e = hipSuccess;
+  if (rho || vel || pops) e = launch_readout(c, rho, vel, pops, dst->pops_f64);
+  if (e == hipSuccess && force) e = launch_export_force(c, force);
+  if (e == hipSuccess && (ptx || ptub || ptg || ptdu)) e = launch_export_points(c, ptx, ptub, ptg, ptdu);
+  if (e == hipSuccess && sums) e = launch_reduce_sums(c, sums);
+  if (e != hipSuccess) return hip_fail(c, e, "read_fields");
+  if (!dev) {
+    auto back = [&](uint32_t bit, void* host, const void* devp, size_t b) -> hipError_t {
+      if (!(mask & bit)) return hipSuccess;
+      return hipMemcpyAsync(host, devp, b, hipMemcpyDeviceToHost, c->stream);
+    };
+    HIP_TRY(c, back(LBM_F_RHO, dst->rho, rho, 4 * nc));
+    HIP_TRY(c, back(LBM_F_VEL, dst->vel, vel, 12 * nc));
+    HIP_TRY(c, back(LBM_F_FORCE, dst->force, force, 12 * nc));
+    HIP_TRY(c, back(LBM_F_POPS, dst->pops, pops, pop_b));
+    HIP_TRY(c, back(LBM_F_PT_X, dst->pt_x, ptx, 24 * np));
+    HIP_TRY(c, back(LBM_F_PT_UB, dst->pt_ub, ptub, 12 * np));
+    HIP_TRY(c, back(LBM_F_PT_G, dst->pt_g, ptg, 12 * np));
+    HIP_TRY(c, back(LBM_F_PT_DU, dst->pt_du, ptdu, 12 * np));
+    HIP_TRY(c, back(LBM_F_SUMS, dst->sums, sums, 32));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (mask & LBM_F_STEP) *dst->step = c->step;
+  } else if (mask & LBM_F_STEP) {
+    HIP_TRY(c, hipMemcpyAsync(dst->step, &c->step, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_write_fields(lbm_ctx* c, uint32_t mask, const lbm_fields* src) {
+  if (!c) return LBM_ERR_ARG;
+  if (!src) return fail(c, LBM_ERR_ARG, "src is NULL");
+  if (mask & ~(uint32_t)(LBM_F_POPS | LBM_F_FORCE | LBM_F_STEP))
+    return fail(c, LBM_ERR_ARG, "only POPS, FORCE and STEP can be written");
+  if ((mask & LBM_F_POPS) && !src->pops) return fail(c, LBM_ERR_ARG, "pops is NULL");
+  if ((mask & LBM_F_FORCE) && !src->force) return fail(c, LBM_ERR_ARG, "force is NULL");
+  if ((mask & LBM_F_STEP) && !src->step) return fail(c, LBM_ERR_ARG, "step is NULL");
+  if ((mask & LBM_F_FORCE) && c->npts > 0)
+    return fail(c, LBM_ERR_STATE, "a prescribed force needs a context without points");
+  const bool dev = src->on_device != 0;
+  const size_t nc = (size_t)c->ncell;
+  if (mask & LBM_F_POPS) {
+    const size_t b = (src->pops_f64 ? 8 : 4) * 19 * nc;
+    const void* p = src->pops;
+    Staging st;
+    if (!dev) {
+      HIP_TRY(c, hipMalloc(&st.p, b));
+      HIP_TRY(c, hipMemcpyAsync(st.p, src->pops, b, hipMemcpyHostToDevice, c->stream));
+      p = st.p;
+    }
+    hipError_t e = launch_unstream_from(c, p, src->pops_f64);
+    if (e != hipSuccess) return hip_fail(c, e, "write pops");
+    if (!dev) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->g_valid_step = -1;
+  }
+  if (mask & LBM_F_FORCE) {
+    Staging st;
+    const float* p = src->force;
+    if (!dev) {
+      HIP_TRY(c, hipMalloc(&st.p, 12 * nc));
+      HIP_TRY(c, hipMemcpyAsync(st.p, src->force, 12 * nc, hipMemcpyHostToDevice, c->stream));
+      p = (const float*)st.p;
+    }
+    hipError_t e = launch_copy_f32(c, c->G, p, 3 * c->ncell);
+    if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->bflag, 0x01010101u, c->nbflag_words);
+    if (e != hipSuccess) return hip_fail(c, e, "write force");
+    if (!dev) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->g_prescribed = true;
+  }
+  if (mask & LBM_F_STEP) {
+    int64_t s;
+    if (dev) {
+      HIP_TRY(c, hipMemcpyAsync(&s, src->step, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+    } else {
+      s = *src->step;
+    }
+    if (s < 0) return fail(c, LBM_ERR_ARG, "step must be >= 0");
+    c->step = s;
+    c->g_valid_step = -1;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_set_timing(lbm_ctx* c, int32_t enable) {
+  if (!c) return LBM_ERR_ARG;
+  if (c->timing && !enable) ev_collect(c);
+  c->timing = enable != 0;
+  for (double& v : c->t_acc) v = 0.0;
+  c->ev_used = 0;
+  c->ev_kind.clear();
+  return LBM_OK;
+}
+
+lbm_status lbm_get_timing(lbm_ctx* c, double out[4]) {
+  if (!c || !out) return LBM_ERR_ARG;
+  ev_collect(c);
+  for (int k = 0; k < 4; ++k) out[k] = c->t_acc[k];
+  return LBM_OK;
+}
+
+}  // extern "C"
