@@ -109,22 +109,27 @@ __device__ __forceinline__ uint32_t tile_index(const PointGeom& pg, int tx, int 
   return (uint32_t)tx + (uint32_t)pg.tiles[0] * ((uint32_t)ty + (uint32_t)pg.tiles[1] * (uint32_t)tz);
 }
 
-// Distinct blocks (edge 2^shift), per axis, holding the four support cells
-// base-1 .. base+2.  Up to three per axis when a short last block is crossed.
-struct Span {
-  int t[3][3];
-  int n[3];
+// Distinct blocks (edge 2^shift) holding the four support cells base-1 ..
+// base+2 along one axis: up to three when a short last block is crossed.
+struct Span1 {
+  int t0, t1, t2, n;
+  __device__ __forceinline__ int at(int j) const { return j == 0 ? t0 : (j == 1 ? t1 : t2); }
 };
 
-__device__ __forceinline__ Span support_span(const PointGeom& pg, const int base[3], int shift) {
-  Span sp;
-  for (int a = 0; a < 3; ++a) {
-    sp.n[a] = 0;
-    for (int j = 0; j < 4; ++j) {
-      const int tv = tap_coord(base[a] - 1 + j, pg.n[a], pg.bc[a]) >> shift;
-      bool seen = false;
-      for (int q = 0; q < sp.n[a]; ++q) seen |= sp.t[a][q] == tv;
-      if (!seen && sp.n[a] < 3) sp.t[a][sp.n[a]++] = tv;
+__device__ __forceinline__ Span1 span_axis(int base, int n, int bc, int shift) {
+  Span1 sp;
+  sp.t0 = tap_coord(base - 1, n, bc) >> shift;
+  sp.t1 = sp.t0;
+  sp.t2 = sp.t0;
+  sp.n = 1;
+#pragma unroll
+  for (int j = 1; j < 4; ++j) {
+    const int v = tap_coord(base - 1 + j, n, bc) >> shift;
+    const bool fresh = v != sp.t0 && (sp.n < 2 || v != sp.t1) && (sp.n < 3 || v != sp.t2);
+    if (fresh) {
+      if (sp.n == 1) sp.t1 = v;
+      else if (sp.n == 2) sp.t2 = v;
+      sp.n = sp.n < 3 ? sp.n + 1 : 3;
     }
   }
   return sp;
@@ -167,68 +172,112 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_point_count(
     key[k] = own;
     rank[k] = r;
   }
-  Span ts{};
-  if (valid) ts = support_span(pg, ps.base, TILE_SHIFT);
+  Span1 sx{0, 0, 0, 0}, sy{0, 0, 0, 0}, sz{0, 0, 0, 0};
+  if (valid) {
+    sx = span_axis(ps.base[0], pg.n[0], pg.bc[0], TILE_SHIFT);
+    sy = span_axis(ps.base[1], pg.n[1], pg.bc[1], TILE_SHIFT);
+    sz = span_axis(ps.base[2], pg.n[2], pg.bc[2], TILE_SHIFT);
+  }
   for (int j = 0; j < 27; ++j) {
     const int jx = j % 3, jy = (j / 3) % 3, jz = j / 9;
-    const bool v = valid && jx < ts.n[0] && jy < ts.n[1] && jz < ts.n[2];
+    const bool v = valid && jx < sx.n && jy < sy.n && jz < sz.n;
     if (!__ballot(v)) continue;
-    const uint32_t t = v ? tile_index(pg, ts.t[0][jx], ts.t[1][jy], ts.t[2][jz]) : 0u;
+    const uint32_t t = v ? tile_index(pg, sx.at(jx), sy.at(jy), sz.at(jz)) : 0u;
     agg_increment(cnt_touch, t, v);
   }
 }
 
 // Pass 2 (one workgroup): exclusive scans of the owner and touch counts, the
 // compact lists of tiles that own points / are touched, and clearing of the
-// counters and force-block flags for this step.
+// counters and force-block flags for this step.  Tiles are taken in chunks
+// of SCAN_THREADS * SCAN_PER; each thread owns SCAN_PER consecutive tiles,
+// waves scan their thread totals with shuffles, one wave scans the wave
+// totals, and a running carry joins the chunks.
 constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_PER = 16;
+constexpr int SCAN_WAVES = SCAN_THREADS / 64;
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(
     uint32_t* __restrict__ cnt_own, uint32_t* __restrict__ cnt_touch, uint32_t* __restrict__ fill,
     uint32_t* __restrict__ start_own, uint32_t* __restrict__ start_touch,
     uint32_t* __restrict__ own_tiles, uint32_t* __restrict__ touch_tiles,
     uint32_t* __restrict__ meta, uint32_t* __restrict__ bflag_words, int64_t nbflag_words,
     int64_t ntiles) {
-  __shared__ uint32_t part[4][SCAN_THREADS];
-  const int tid = threadIdx.x;
-  const int64_t per = (ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
-  const int64_t lo = (int64_t)tid * per;
-  const int64_t hi = lo + per < ntiles ? lo + per : ntiles;
-  uint32_t s[4] = {0, 0, 0, 0};
-  for (int64_t t = lo; t < hi; ++t) {
-    const uint32_t a = cnt_own[t], b = cnt_touch[t];
-    s[0] += a;
-    s[1] += b;
-    s[2] += a ? 1u : 0u;
-    s[3] += b ? 1u : 0u;
-  }
-  for (int q = 0; q < 4; ++q) part[q][tid] = s[q];
+  __shared__ uint32_t wtot[4][SCAN_WAVES];
+  __shared__ uint32_t carry[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid < 4) carry[tid] = 0u;
   __syncthreads();
-  for (int off = 1; off < SCAN_THREADS; off <<= 1) {  // Hillis-Steele inclusive scans
-    uint32_t v[4];
-    for (int q = 0; q < 4; ++q) v[q] = tid >= off ? part[q][tid - off] : 0u;
+  for (int64_t c0 = 0; c0 < ntiles; c0 += (int64_t)SCAN_THREADS * SCAN_PER) {
+    const int64_t t0 = c0 + (int64_t)tid * SCAN_PER;
+    uint32_t a[SCAN_PER], b[SCAN_PER];
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; ++j) {
+      const bool in = t0 + j < ntiles;
+      a[j] = in ? cnt_own[t0 + j] : 0u;
+      b[j] = in ? cnt_touch[t0 + j] : 0u;
+    }
+    uint32_t s[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; ++j) {
+      s[0] += a[j];
+      s[1] += b[j];
+      s[2] += a[j] ? 1u : 0u;
+      s[3] += b[j] ? 1u : 0u;
+    }
+    uint32_t inc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t v = s[q];
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t u = __shfl_up(v, off, 64);
+        if (lane >= off) v += u;
+      }
+      inc[q] = v;
+      if (lane == 63) wtot[q][wv] = v;
+    }
     __syncthreads();
-    for (int q = 0; q < 4; ++q) part[q][tid] += v[q];
+    if (wv == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t v = lane < SCAN_WAVES ? wtot[q][lane] : 0u;
+#pragma unroll
+        for (int off = 1; off < SCAN_WAVES; off <<= 1) {
+          const uint32_t u = __shfl_up(v, off, 64);
+          if (lane >= off) v += u;
+        }
+        if (lane < SCAN_WAVES) wtot[q][lane] = v;  // inclusive over waves
+      }
+    }
+    __syncthreads();
+    uint32_t run[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      run[q] = carry[q] + (wv ? wtot[q][wv - 1] : 0u) + inc[q] - s[q];
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; ++j) {
+      const int64_t t = t0 + j;
+      if (t < ntiles) {
+        start_own[t] = run[0];
+        start_touch[t] = run[1];
+        if (a[j]) own_tiles[run[2]++] = (uint32_t)t;
+        if (b[j]) touch_tiles[run[3]++] = (uint32_t)t;
+        run[0] += a[j];
+        run[1] += b[j];
+        cnt_own[t] = 0u;
+        cnt_touch[t] = 0u;
+        fill[t] = 0u;
+      }
+    }
+    __syncthreads();
+    if (tid < 4) carry[tid] += wtot[tid][SCAN_WAVES - 1];
     __syncthreads();
   }
-  uint32_t run[4];
-  for (int q = 0; q < 4; ++q) run[q] = part[q][tid] - s[q];
-  for (int64_t t = lo; t < hi; ++t) {
-    const uint32_t a = cnt_own[t], b = cnt_touch[t];
-    start_own[t] = run[0];
-    start_touch[t] = run[1];
-    if (a) own_tiles[run[2]++] = (uint32_t)t;
-    if (b) touch_tiles[run[3]++] = (uint32_t)t;
-    run[0] += a;
-    run[1] += b;
-    cnt_own[t] = 0u;
-    cnt_touch[t] = 0u;
-    fill[t] = 0u;
-  }
-  if (tid == SCAN_THREADS - 1) {
-    start_own[ntiles] = part[0][tid];
-    start_touch[ntiles] = part[1][tid];
-    meta[0] = part[2][tid];
-    meta[1] = part[3][tid];
+  if (tid == 0) {
+    start_own[ntiles] = carry[0];
+    start_touch[ntiles] = carry[1];
+    meta[0] = carry[2];
+    meta[1] = carry[3];
   }
   for (int64_t w = tid; w < nbflag_words; w += SCAN_THREADS) bflag_words[w] = 0u;
 }
@@ -257,23 +306,30 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_point_scatter(
     sp_base[slot] = make_int4(ps.base[0], ps.base[1], ps.base[2], (int)k);
     sp_frac[slot] = make_float4(ps.frac[0], ps.frac[1], ps.frac[2], r4.w);
     sp_ub[slot] = make_float4(ps.ub[0], ps.ub[1], ps.ub[2], 0.0f);
-    const Span fb = support_span(pg, ps.base, FBLK_SHIFT);  // idempotent flag stores
-    for (int cz = 0; cz < fb.n[2]; ++cz)
-      for (int cy = 0; cy < fb.n[1]; ++cy)
-        for (int cx = 0; cx < fb.n[0]; ++cx)
-          bflag[(int64_t)fb.t[0][cx] +
-                (int64_t)pg.fblk[0] * ((int64_t)fb.t[1][cy] + (int64_t)pg.fblk[1] * fb.t[2][cz])] = 1u;
+    // flag the force blocks of the support (idempotent byte stores)
+    const Span1 fx = span_axis(ps.base[0], pg.n[0], pg.bc[0], FBLK_SHIFT);
+    const Span1 fy = span_axis(ps.base[1], pg.n[1], pg.bc[1], FBLK_SHIFT);
+    const Span1 fz = span_axis(ps.base[2], pg.n[2], pg.bc[2], FBLK_SHIFT);
+    for (int cz = 0; cz < fz.n; ++cz)
+      for (int cy = 0; cy < fy.n; ++cy)
+        for (int cx = 0; cx < fx.n; ++cx)
+          bflag[(int64_t)fx.at(cx) +
+                (int64_t)pg.fblk[0] * ((int64_t)fy.at(cy) + (int64_t)pg.fblk[1] * fz.at(cz))] = 1u;
     ps_s = r4.w;
     ps_ub2 = (double)r4.w * ((double)ps.ub[0] * ps.ub[0] + (double)ps.ub[1] * ps.ub[1] +
                              (double)ps.ub[2] * ps.ub[2]);
   }
-  Span ts{};
-  if (valid) ts = support_span(pg, ps.base, TILE_SHIFT);
+  Span1 sx{0, 0, 0, 0}, sy{0, 0, 0, 0}, sz{0, 0, 0, 0};
+  if (valid) {
+    sx = span_axis(ps.base[0], pg.n[0], pg.bc[0], TILE_SHIFT);
+    sy = span_axis(ps.base[1], pg.n[1], pg.bc[1], TILE_SHIFT);
+    sz = span_axis(ps.base[2], pg.n[2], pg.bc[2], TILE_SHIFT);
+  }
   for (int j = 0; j < 27; ++j) {
     const int jx = j % 3, jy = (j / 3) % 3, jz = j / 9;
-    const bool v = valid && jx < ts.n[0] && jy < ts.n[1] && jz < ts.n[2];
+    const bool v = valid && jx < sx.n && jy < sy.n && jz < sz.n;
     if (!__ballot(v)) continue;
-    const uint32_t t = v ? tile_index(pg, ts.t[0][jx], ts.t[1][jy], ts.t[2][jz]) : 0u;
+    const uint32_t t = v ? tile_index(pg, sx.at(jx), sy.at(jy), sz.at(jz)) : 0u;
     const uint32_t pos = agg_increment(fill, t, v);
     if (v) tlist[start_touch[t] + pos] = slot;
   }
@@ -315,7 +371,7 @@ __device__ __forceinline__ void tile_origin(const PointGeom& pg, uint32_t t, int
 
 // Velocity U = sum e f / rho (eq. 1) of the post-stream populations on the
 // flagged 4^3 blocks of every touched tile (the paper's lbm_u_start limited
-// to the cells the supports reach).  512 threads: one wave per 4^3 block.
+// to the cells the supports reach).  512 threads: one wave per 8x8 z-plane.
 template <int S>
 __global__ __launch_bounds__(TILE3) void k_moments_blocks(
     const typename Store<S>::T* __restrict__ lat, const LatticeGeom g, PointGeom pg,
@@ -325,10 +381,9 @@ __global__ __launch_bounds__(TILE3) void k_moments_blocks(
   if (e < 0) return;
   int o[3];
   tile_origin(pg, touch_tiles[e], o);
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int x = o[0] + (w & 1) * FBLK + (lane & 3);
-  const int y = o[1] + ((w >> 1) & 1) * FBLK + ((lane >> 2) & 3);
-  const int z = o[2] + (w >> 2) * FBLK + (lane >> 4);
+  const int x = o[0] + (threadIdx.x & (TILE - 1));
+  const int y = o[1] + ((threadIdx.x >> TILE_SHIFT) & (TILE - 1));
+  const int z = o[2] + (threadIdx.x >> (2 * TILE_SHIFT));
   if (x >= g.nx || y >= g.ny || z >= g.nz) return;
   if (!bflag[fblock_of(g, x, y, z)]) return;
   float f[Q];
@@ -401,11 +456,12 @@ __global__ __launch_bounds__(WG) void k_interp_tiles(
       // box-local index of tap (-1, -1, -1): the box starts one cell before the tile
       const int l0 = (b.x - o[0]) + BOX * ((b.y - o[1]) + BOX * (b.z - o[2]));
       float u0 = 0.f, u1 = 0.f, u2 = 0.f;
-#pragma unroll
-      for (int cz = 0; cz < 4; ++cz)
+#pragma unroll 1
+      for (int cz = 0; cz < 4; ++cz) {
+        const float wzc = cz == 0 ? wz[0] : (cz == 1 ? wz[1] : (cz == 2 ? wz[2] : wz[3]));
 #pragma unroll
         for (int cy = 0; cy < 4; ++cy) {
-          const float wyz = wz[cz] * wy[cy];
+          const float wyz = wzc * wy[cy];
           const int row = l0 + BOX * (cy + BOX * cz);
 #pragma unroll
           for (int cx = 0; cx < 4; ++cx) {
@@ -415,6 +471,7 @@ __global__ __launch_bounds__(WG) void k_interp_tiles(
             u2 += w * sUz[row + cx];
           }
         }
+      }
       const float4 ub = sp_ub[k];
       const float g0 = ub.x - u0, g1 = ub.y - u1, g2 = ub.z - u2;
       float4 du = first ? make_float4(0.f, 0.f, 0.f, 0.f) : sp_du[k];
@@ -441,20 +498,43 @@ __global__ __launch_bounds__(WG) void k_interp_tiles(
 // v(k) W_k over its listed points in LDS, then
 //   mode 0/1 (inner sweep, v = s g or g):  U += sum   on cells with a nonzero sum
 //   mode 2   (final spread, v = du):       G  = sum   on every cell of the tile.
+// The LDS sum is kept in 32-bit fixed point (integer LDS atomics are fast on
+// CDNA; float ones are not) with a per-tile unit B / 2^30, where
+// B = (1/8) sum_k max_c |v_k,c| bounds every cell's sum (a tap weight is at
+// most 1/8), so it cannot overflow; integer addition also makes the result
+// independent of the order of the atomics.
+constexpr float FIX_ONE = 1073741824.0f;  // 2^30
 __global__ __launch_bounds__(WG) void k_spread_tiles(
     const uint32_t* __restrict__ touch_tiles, const uint32_t* __restrict__ meta,
     const uint32_t* __restrict__ start_touch, const uint32_t* __restrict__ tlist,
     const int4* __restrict__ sp_base, const float4* __restrict__ sp_frac,
     const float4* __restrict__ vsrc, float* __restrict__ target, PointGeom pg, int mode) {
-  __shared__ float acc[3][TILE3];
+  __shared__ int acc[3][TILE3];
+  __shared__ float red[WG / 64];
   const int64_t e = list_entry(meta[1]);
   if (e < 0) return;
   const uint32_t t = touch_tiles[e];
   int o[3];
   tile_origin(pg, t, o);
-  for (int i = threadIdx.x; i < 3 * TILE3; i += WG) (&acc[0][0])[i] = 0.0f;
-  __syncthreads();
+  for (int i = threadIdx.x; i < 3 * TILE3; i += WG) (&acc[0][0])[i] = 0;
   const uint32_t q0 = start_touch[t], L = start_touch[t + 1] - q0;
+  // bound of the cell sums
+  float bsum = 0.0f;
+  for (uint32_t i = threadIdx.x; i < L; i += WG) {
+    const uint32_t k = tlist[q0 + i];
+    const float4 v = vsrc[k];
+    const float sc = mode == 0 ? sp_frac[k].w : 1.0f;
+    bsum += sc * fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) bsum += __shfl_xor(bsum, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = bsum;
+  __syncthreads();
+  float B = 0.0f;
+#pragma unroll
+  for (int w = 0; w < WG / 64; ++w) B += red[w];
+  B *= 0.125f;
+  const float scale = B > 0.0f ? FIX_ONE / B : 0.0f;
   // Neighbouring list entries are neighbouring points; a stride coprime to
   // the list length deals them to lanes in scattered order so that the lanes
   // of a wave rarely add into the same LDS word at once.
@@ -464,11 +544,10 @@ __global__ __launch_bounds__(WG) void k_spread_tiles(
     const int4 b = sp_base[k];
     const float4 fr = sp_frac[k];
     float4 v = vsrc[k];
-    if (mode == 0) {
-      v.x *= fr.w;
-      v.y *= fr.w;
-      v.z *= fr.w;
-    }
+    const float vs = (mode == 0 ? fr.w : 1.0f) * scale;
+    v.x *= vs;
+    v.y *= vs;
+    v.z *= vs;
     float wx[4], wy[4], wz[4];
     peskin4(fr.x, wx);
     peskin4(fr.y, wy);
@@ -495,29 +574,30 @@ __global__ __launch_bounds__(WG) void k_spread_tiles(
           if (in_yz && lx[cx] >= 0) {
             const float w = wyz * wx[cx];
             const int idx = row + lx[cx];
-            atomicAdd(&acc[0][idx], w * v.x);
-            atomicAdd(&acc[1][idx], w * v.y);
-            atomicAdd(&acc[2][idx], w * v.z);
+            atomicAdd(&acc[0][idx], __float2int_rn(w * v.x));
+            atomicAdd(&acc[1][idx], __float2int_rn(w * v.y));
+            atomicAdd(&acc[2][idx], __float2int_rn(w * v.z));
           }
         }
       }
     }
   }
   __syncthreads();
+  const float unit = B / FIX_ONE;
   for (int i = threadIdx.x; i < TILE3; i += WG) {
     const int x = o[0] + (i & (TILE - 1)), y = o[1] + ((i >> TILE_SHIFT) & (TILE - 1)),
               z = o[2] + (i >> (2 * TILE_SHIFT));
     if (x >= pg.n[0] || y >= pg.n[1] || z >= pg.n[2]) continue;
     const int64_t c = (int64_t)x + (int64_t)pg.n[0] * ((int64_t)y + (int64_t)pg.n[1] * z);
-    const float a0 = acc[0][i], a1 = acc[1][i], a2 = acc[2][i];
+    const int a0 = acc[0][i], a1 = acc[1][i], a2 = acc[2][i];
     if (mode == 2) {
-      target[c] = a0;
-      target[pg.ncell + c] = a1;
-      target[2 * pg.ncell + c] = a2;
-    } else if (a0 != 0.0f || a1 != 0.0f || a2 != 0.0f) {
-      target[c] += a0;
-      target[pg.ncell + c] += a1;
-      target[2 * pg.ncell + c] += a2;
+      target[c] = (float)a0 * unit;
+      target[pg.ncell + c] = (float)a1 * unit;
+      target[2 * pg.ncell + c] = (float)a2 * unit;
+    } else if (a0 != 0 || a1 != 0 || a2 != 0) {
+      target[c] += (float)a0 * unit;
+      target[pg.ncell + c] += (float)a1 * unit;
+      target[2 * pg.ncell + c] += (float)a2 * unit;
     }
   }
 }
