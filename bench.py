@@ -80,6 +80,24 @@ def cpu_baseline(wl, n_steps):
                       % (n_steps, dt, cpu)}
 
 
+def copy_bandwidth(torch, nbytes, reps=5):
+    """A plain device-to-device copy of nbytes (read + write = 2 nbytes)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes_per_copy": 2 * nbytes, "ms": round(ms, 4),
+            "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +108,8 @@ def main():
     ap.add_argument("--forcing", default="guo", choices=["guo", "shift"])
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also time a plain 2.5 GB device copy (achievable HBM bandwidth)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU; this build has no multi-GPU path "
@@ -166,6 +186,8 @@ def main():
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if args.copy_calibration:
+        out["copy_calibration"] = copy_bandwidth(torch, bpc * wl.n_cells // 2)
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -600,3 +600,149 @@ int orc_run(const orc_params* p, double* f, const orc_points* pts,
   ws_free(&w);
   return err;
 }
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start: a per-point MLP 12 -> 64 -> 64 -> 64 -> 3 with SiLU
+ * after each hidden layer (not part of the paper; its inputs are the point's
+ * first deficit, its velocity and the mean and component-wise maximum of
+ * the first deficit over its neighbours, all divided by a reference speed;
+ * its output is the predicted correction du divided by that speed).
+ *
+ * Flat parameter layout (9347 values, row-major matrices, out x in):
+ *   W1[64][12] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3]
+ * Loss: L = (1 / (3 n)) sum_k sum_c (y_kc - t_kc)^2.
+ * ------------------------------------------------------------------------- */
+#define MLP_IN 12
+#define MLP_H 64
+#define MLP_OUT 3
+#define MLP_NPARAM (MLP_H * MLP_IN + MLP_H + 2 * (MLP_H * MLP_H + MLP_H) + MLP_OUT * MLP_H + MLP_OUT)
+
+static double sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
+
+int32_t orc_mlp_nparam(void) { return MLP_NPARAM; }
+
+typedef struct {
+  const double *W1, *b1, *W2, *b2, *W3, *b3, *W4, *b4;
+} mlp_view;
+
+static mlp_view mlp_split(const double* th) {
+  mlp_view v;
+  v.W1 = th;
+  v.b1 = v.W1 + MLP_H * MLP_IN;
+  v.W2 = v.b1 + MLP_H;
+  v.b2 = v.W2 + MLP_H * MLP_H;
+  v.W3 = v.b2 + MLP_H;
+  v.b3 = v.W3 + MLP_H * MLP_H;
+  v.W4 = v.b3 + MLP_H;
+  v.b4 = v.W4 + MLP_OUT * MLP_H;
+  return v;
+}
+
+/* One dense layer z = W a + b, optionally followed by SiLU into h. */
+static void dense(const double* W, const double* b, const double* a, int nin, int nout,
+                  double* z, double* h) {
+  for (int o = 0; o < nout; ++o) {
+    double s = b[o];
+    for (int i = 0; i < nin; ++i) s += W[o * nin + i] * a[i];
+    z[o] = s;
+    if (h) h[o] = s * sigmoid(s);
+  }
+}
+
+void orc_mlp_forward(const double* theta, int64_t n, const double* x, double* y) {
+  mlp_view P = mlp_split(theta);
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n; ++k) {
+    double z1[MLP_H], h1[MLP_H], z2[MLP_H], h2[MLP_H], z3[MLP_H], h3[MLP_H];
+    dense(P.W1, P.b1, x + MLP_IN * k, MLP_IN, MLP_H, z1, h1);
+    dense(P.W2, P.b2, h1, MLP_H, MLP_H, z2, h2);
+    dense(P.W3, P.b3, h2, MLP_H, MLP_H, z3, h3);
+    dense(P.W4, P.b4, h3, MLP_H, MLP_OUT, y + MLP_OUT * k, NULL);
+  }
+}
+
+/* d SiLU / dz */
+static double silu_grad(double z) {
+  double s = sigmoid(z);
+  return s * (1.0 + z * (1.0 - s));
+}
+
+/* Loss and its gradient (back-propagation written out layer by layer);
+ * samples are processed one after the other. */
+double orc_mlp_loss_grad(const double* theta, int64_t n, const double* x, const double* t,
+                         double* grad) {
+  mlp_view P = mlp_split(theta);
+  memset(grad, 0, sizeof(double) * MLP_NPARAM);
+  double* gW1 = grad;
+  double* gb1 = gW1 + MLP_H * MLP_IN;
+  double* gW2 = gb1 + MLP_H;
+  double* gb2 = gW2 + MLP_H * MLP_H;
+  double* gW3 = gb2 + MLP_H;
+  double* gb3 = gW3 + MLP_H * MLP_H;
+  double* gW4 = gb3 + MLP_H;
+  double* gb4 = gW4 + MLP_OUT * MLP_H;
+  double loss = 0.0;
+  const double scale = 1.0 / (3.0 * (double)n);
+  for (int64_t k = 0; k < n; ++k) {
+    const double* a0 = x + MLP_IN * k;
+    double z1[MLP_H], h1[MLP_H], z2[MLP_H], h2[MLP_H], z3[MLP_H], h3[MLP_H], y[MLP_OUT];
+    dense(P.W1, P.b1, a0, MLP_IN, MLP_H, z1, h1);
+    dense(P.W2, P.b2, h1, MLP_H, MLP_H, z2, h2);
+    dense(P.W3, P.b3, h2, MLP_H, MLP_H, z3, h3);
+    dense(P.W4, P.b4, h3, MLP_H, MLP_OUT, y, NULL);
+    double dy[MLP_OUT], d3[MLP_H], d2[MLP_H], d1[MLP_H];
+    for (int c = 0; c < MLP_OUT; ++c) {
+      double r = y[c] - t[MLP_OUT * k + c];
+      loss += r * r * scale;
+      dy[c] = 2.0 * r * scale; /* dL/dy */
+    }
+    /* output layer */
+    for (int c = 0; c < MLP_OUT; ++c) {
+      gb4[c] += dy[c];
+      for (int i = 0; i < MLP_H; ++i) gW4[c * MLP_H + i] += dy[c] * h3[i];
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+      double s = 0.0;
+      for (int c = 0; c < MLP_OUT; ++c) s += P.W4[c * MLP_H + i] * dy[c];
+      d3[i] = s * silu_grad(z3[i]); /* dL/dz3 */
+    }
+    /* third layer */
+    for (int o = 0; o < MLP_H; ++o) {
+      gb3[o] += d3[o];
+      for (int i = 0; i < MLP_H; ++i) gW3[o * MLP_H + i] += d3[o] * h2[i];
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+      double s = 0.0;
+      for (int o = 0; o < MLP_H; ++o) s += P.W3[o * MLP_H + i] * d3[o];
+      d2[i] = s * silu_grad(z2[i]);
+    }
+    /* second layer */
+    for (int o = 0; o < MLP_H; ++o) {
+      gb2[o] += d2[o];
+      for (int i = 0; i < MLP_H; ++i) gW2[o * MLP_H + i] += d2[o] * h1[i];
+    }
+    for (int i = 0; i < MLP_H; ++i) {
+      double s = 0.0;
+      for (int o = 0; o < MLP_H; ++o) s += P.W2[o * MLP_H + i] * d2[o];
+      d1[i] = s * silu_grad(z1[i]);
+    }
+    /* first layer */
+    for (int o = 0; o < MLP_H; ++o) {
+      gb1[o] += d1[o];
+      for (int i = 0; i < MLP_IN; ++i) gW1[o * MLP_IN + i] += d1[o] * a0[i];
+    }
+  }
+  return loss;
+}
+
+/* Adam (Kingma & Ba) with bias correction; step_t counts from 1. */
+void orc_adam_step(double* theta, const double* grad, double* m, double* v, int64_t step_t,
+                   double lr, double beta1, double beta2, double eps) {
+  const double c1 = 1.0 - pow(beta1, (double)step_t);
+  const double c2 = 1.0 - pow(beta2, (double)step_t);
+  for (int p = 0; p < MLP_NPARAM; ++p) {
+    m[p] = beta1 * m[p] + (1.0 - beta1) * grad[p];
+    v[p] = beta2 * v[p] + (1.0 - beta2) * grad[p] * grad[p];
+    theta[p] -= lr * (m[p] / c1) / (sqrt(v[p] / c2) + eps);
+  }
+}

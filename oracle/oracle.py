@@ -87,6 +87,11 @@ def _load():
             lib.orc_step.restype = ct.c_int
             lib.orc_run.argtypes = [P, vp, ct.POINTER(_Points), i64, i64, vp]
             lib.orc_run.restype = ct.c_int
+            lib.orc_mlp_nparam.restype = ct.c_int32
+            lib.orc_mlp_forward.argtypes = [vp, i64, vp, vp]
+            lib.orc_mlp_loss_grad.argtypes = [vp, i64, vp, vp, vp]
+            lib.orc_mlp_loss_grad.restype = d
+            lib.orc_adam_step.argtypes = [vp, vp, vp, vp, i64, d, d, d, d]
             _lib = lib
     return _lib
 
@@ -284,3 +289,38 @@ def run(p, f, pts=None, step0=0, n_steps=1):
     pc = ct.byref(pts.c) if pts is not None else None
     _check(lib.orc_run(ct.byref(p), _ptr(f), pc, int(step0), int(n_steps), _ptr(hist)))
     return hist
+
+
+# ------------------------------------------------------------ learned warm start
+def mlp_nparam():
+    return int(_load().orc_mlp_nparam())
+
+
+def mlp_forward(theta, x):
+    """x: [n, 12] -> y: [n, 3] (FP64)."""
+    lib = _load()
+    theta = _f64(theta).reshape(-1)
+    x = _f64(x).reshape(-1, 12)
+    y = np.zeros((x.shape[0], 3))
+    lib.orc_mlp_forward(_ptr(theta), x.shape[0], _ptr(x), _ptr(y))
+    return y
+
+
+def mlp_loss_grad(theta, x, t):
+    """Mean squared error over samples and outputs and its gradient."""
+    lib = _load()
+    theta = _f64(theta).reshape(-1)
+    x = _f64(x).reshape(-1, 12)
+    t = _f64(t).reshape(-1, 3)
+    g = np.zeros(mlp_nparam())
+    loss = lib.orc_mlp_loss_grad(_ptr(theta), x.shape[0], _ptr(x), _ptr(t), _ptr(g))
+    return loss, g
+
+
+def adam_step(theta, grad, m, v, step_t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In place on theta, m, v (float64 arrays)."""
+    lib = _load()
+    for a in (theta, grad, m, v):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    lib.orc_adam_step(_ptr(theta), _ptr(grad), _ptr(m), _ptr(v), int(step_t), float(lr),
+                      float(beta1), float(beta2), float(eps))

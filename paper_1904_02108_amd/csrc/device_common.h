@@ -130,6 +130,62 @@ __device__ __forceinline__ void gather_pull(const typename Store<S>::T* __restri
   }
 }
 
+// Source offsets of the pull stream at cell (x, y, z): for each axis the
+// cell offsets of the sources X - e with e = -1, 0, +1 (periodic wrap);
+// `fast` is false next to a wall, where gather_pull must be used.
+struct PullIdx {
+  uint32_t xs[3], ys[3], zs[3];
+  bool fast;
+};
+
+__device__ __forceinline__ PullIdx pull_index(const LatticeGeom& g, int x, int y, int z) {
+  PullIdx p;
+  const int n[3] = {g.nx, g.ny, g.nz};
+  const int c[3] = {x, y, z};
+  const uint32_t mul[3] = {1u, (uint32_t)g.nx, (uint32_t)g.nx * (uint32_t)g.ny};
+  uint32_t* out[3] = {p.xs, p.ys, p.zs};
+  p.fast = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int lo = c[a] - 1, hi = c[a] + 1;  // sources for e = +1 and e = -1
+    if (g.bc[a] == LBM_BC_PERIODIC) {
+      lo = lo < 0 ? lo + n[a] : lo;
+      hi = hi >= n[a] ? hi - n[a] : hi;
+    } else {
+      p.fast = p.fast && lo >= 0 && hi < n[a];
+      lo = lo < 0 ? 0 : lo;
+      hi = hi >= n[a] ? n[a] - 1 : hi;
+    }
+    out[a][0] = (uint32_t)hi * mul[a];    // e = -1
+    out[a][1] = (uint32_t)c[a] * mul[a];  // e = 0
+    out[a][2] = (uint32_t)lo * mul[a];    // e = +1
+  }
+  return p;
+}
+
+// Pull gather away from walls: 19 loads at uniform per-population bases plus
+// 32-bit cell offsets.
+template <int S>
+__device__ __forceinline__ void gather_fast(const typename Store<S>::T* __restrict__ lat,
+                                            const LatticeGeom& g, const PullIdx& p, float f[Q]) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const typename Store<S>::T* base = lat + (int64_t)i * g.stride;
+    f[i] = Store<S>::load(base + (p.xs[EX[i] + 1] + p.ys[EY[i] + 1] + p.zs[EZ[i] + 1]));
+  }
+}
+
+// Pull gather at any cell: the fast form away from walls, the general one next to them.
+template <int S>
+__device__ __forceinline__ void gather_any(const typename Store<S>::T* __restrict__ lat,
+                                           const LatticeGeom& g, int x, int y, int z, float f[Q]) {
+  const PullIdx p = pull_index(g, x, y, z);
+  if (p.fast)
+    gather_fast<S>(lat, g, p, f);
+  else
+    gather_pull<S>(lat, g, x, y, z, f);
+}
+
 // Index of the 4^3 force block holding cell (x, y, z).
 __device__ __forceinline__ int64_t fblock_of(const LatticeGeom& g, int x, int y, int z) {
   return (int64_t)(x >> FBLK_SHIFT) +

@@ -7,13 +7,17 @@
 // Work decomposition (instead of the paper's thread-per-point gather and
 // block-per-point atomicAdd scatter):
 //   * points are counting-sorted by the tile of their base cell floor(x)
-//     ("owner" tile) and, in addition, listed in every tile their 4x4x4
-//     support touches;
-//   * interpolation: one workgroup per owner tile stages U over the tile and
-//     its support halo (11^3 cells) in LDS, one thread per point;
-//   * spreading: one workgroup per touched tile accumulates the contributions
-//     of its listed points in LDS (LDS float atomics) and then writes the tile
-//     with plain stores: no global atomics, every cell has one writer.
+//     (their "owner" tile); tiles whose cells a support reaches are listed
+//     as "touched";
+//   * one sweep = two kernels.  k_sweep_tiles: one workgroup per owner tile
+//     stages U over the 11^3 box that holds every tap of its points (tile
+//     plus taps -1..+2), interpolates (one thread per point), forms the
+//     deficit and correction, and spreads the vector of this sweep into an
+//     11^3 box accumulator in LDS (integer atomics on a fixed-point unit),
+//     which it stores.  k_merge_tiles: one workgroup per touched tile adds,
+//     for each of its cells in a fixed order, the stored boxes covering it
+//     and updates U (inner sweeps) or writes G (last sweep).  No global
+//     atomics; every cell has one writer; results do not depend on timing.
 #include "internal.h"
 
 using namespace lbmd;
@@ -39,7 +43,14 @@ __device__ __forceinline__ int wrap(int v, int n) { return v < 0 ? v + n : (v >=
 // walled axes (the surface is validated to keep its supports inside, so the
 // clamp only guards memory against rounding at the validation margin).
 __device__ __forceinline__ int tap_coord(int v, int n, int bc) {
-  return bc == LBM_BC_PERIODIC ? wrap(v, n) : min(max(v, 0), n - 1);
+  if (bc == LBM_BC_PERIODIC) {
+    if (v < 0 || v >= n) {  // any distance: boxes are wider than short axes
+      v %= n;
+      if (v < 0) v += n;
+    }
+    return v;
+  }
+  return min(max(v, 0), n - 1);
 }
 
 // Per-body rotation coefficients for step n (theta_n = theta0 + omega n) and
@@ -178,8 +189,13 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_point_count(
     sy = span_axis(ps.base[1], pg.n[1], pg.bc[1], TILE_SHIFT);
     sz = span_axis(ps.base[2], pg.n[2], pg.bc[2], TILE_SHIFT);
   }
-  for (int j = 0; j < 27; ++j) {
-    const int jx = j % 3, jy = (j / 3) % 3, jz = j / 9;
+  // spans of at most two tiles per axis (every grid with tiles of >= 3
+  // cells); the third tile of a short last tile comes in the second loop
+  const bool wide = __ballot(valid && (sx.n > 2 || sy.n > 2 || sz.n > 2)) != 0;
+  const int jn = wide ? 27 : 8;
+  for (int j = 0; j < jn; ++j) {
+    const int jx = wide ? j % 3 : (j & 1), jy = wide ? (j / 3) % 3 : ((j >> 1) & 1),
+              jz = wide ? j / 9 : (j >> 2);
     const bool v = valid && jx < sx.n && jy < sy.n && jz < sz.n;
     if (!__ballot(v)) continue;
     const uint32_t t = v ? tile_index(pg, sx.at(jx), sy.at(jy), sz.at(jz)) : 0u;
@@ -187,9 +203,10 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_point_count(
   }
 }
 
-// Pass 2 (one workgroup): exclusive scans of the owner and touch counts, the
-// compact lists of tiles that own points / are touched, and clearing of the
-// counters and force-block flags for this step.  Tiles are taken in chunks
+// Pass 2 (one workgroup): exclusive scan of the owner counts, the compact
+// lists of tiles that own points / are touched (with each owner tile's slot
+// in its list), and clearing of the counters and force-block flags for this
+// step.  Tiles are taken in chunks
 // of SCAN_THREADS * SCAN_PER; each thread owns SCAN_PER consecutive tiles,
 // waves scan their thread totals with shuffles, one wave scans the wave
 // totals, and a running carry joins the chunks.
@@ -197,36 +214,37 @@ constexpr int SCAN_THREADS = 1024;
 constexpr int SCAN_PER = 16;
 constexpr int SCAN_WAVES = SCAN_THREADS / 64;
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(
-    uint32_t* __restrict__ cnt_own, uint32_t* __restrict__ cnt_touch, uint32_t* __restrict__ fill,
-    uint32_t* __restrict__ start_own, uint32_t* __restrict__ start_touch,
+    uint32_t* __restrict__ cnt_own, uint32_t* __restrict__ cnt_touch,
+    uint32_t* __restrict__ start_own, int32_t* __restrict__ own_slot,
     uint32_t* __restrict__ own_tiles, uint32_t* __restrict__ touch_tiles,
     uint32_t* __restrict__ meta, uint32_t* __restrict__ bflag_words, int64_t nbflag_words,
     int64_t ntiles) {
-  __shared__ uint32_t wtot[4][SCAN_WAVES];
-  __shared__ uint32_t carry[4];
+  __shared__ uint32_t wtot[3][SCAN_WAVES];
+  __shared__ uint32_t carry[3];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid < 4) carry[tid] = 0u;
+  if (tid < 3) carry[tid] = 0u;
   __syncthreads();
   for (int64_t c0 = 0; c0 < ntiles; c0 += (int64_t)SCAN_THREADS * SCAN_PER) {
     const int64_t t0 = c0 + (int64_t)tid * SCAN_PER;
     uint32_t a[SCAN_PER], b[SCAN_PER];
+    // the count arrays are padded with zeros to a whole number of chunks
 #pragma unroll
-    for (int j = 0; j < SCAN_PER; ++j) {
-      const bool in = t0 + j < ntiles;
-      a[j] = in ? cnt_own[t0 + j] : 0u;
-      b[j] = in ? cnt_touch[t0 + j] : 0u;
+    for (int j = 0; j < SCAN_PER; j += 4) {
+      const uint4 va = *reinterpret_cast<const uint4*>(cnt_own + t0 + j);
+      const uint4 vb = *reinterpret_cast<const uint4*>(cnt_touch + t0 + j);
+      a[j] = va.x; a[j + 1] = va.y; a[j + 2] = va.z; a[j + 3] = va.w;
+      b[j] = vb.x; b[j + 1] = vb.y; b[j + 2] = vb.z; b[j + 3] = vb.w;
     }
-    uint32_t s[4] = {0u, 0u, 0u, 0u};
+    uint32_t s[3] = {0u, 0u, 0u};
 #pragma unroll
     for (int j = 0; j < SCAN_PER; ++j) {
       s[0] += a[j];
-      s[1] += b[j];
-      s[2] += a[j] ? 1u : 0u;
-      s[3] += b[j] ? 1u : 0u;
+      s[1] += a[j] ? 1u : 0u;
+      s[2] += b[j] ? 1u : 0u;
     }
-    uint32_t inc[4];
+    uint32_t inc[3];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 3; ++q) {
       uint32_t v = s[q];
 #pragma unroll
       for (int off = 1; off < 64; off <<= 1) {
@@ -239,7 +257,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(
     __syncthreads();
     if (wv == 0) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 3; ++q) {
         uint32_t v = lane < SCAN_WAVES ? wtot[q][lane] : 0u;
 #pragma unroll
         for (int off = 1; off < SCAN_WAVES; off <<= 1) {
@@ -250,59 +268,51 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(
       }
     }
     __syncthreads();
-    uint32_t run[4];
+    uint32_t run[3];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 3; ++q)
       run[q] = carry[q] + (wv ? wtot[q][wv - 1] : 0u) + inc[q] - s[q];
 #pragma unroll
     for (int j = 0; j < SCAN_PER; ++j) {
       const int64_t t = t0 + j;
       if (t < ntiles) {
         start_own[t] = run[0];
-        start_touch[t] = run[1];
-        if (a[j]) own_tiles[run[2]++] = (uint32_t)t;
-        if (b[j]) touch_tiles[run[3]++] = (uint32_t)t;
+        own_slot[t] = a[j] ? (int32_t)run[1] : -1;
+        if (a[j]) own_tiles[run[1]++] = (uint32_t)t;
+        if (b[j]) touch_tiles[run[2]++] = (uint32_t)t;
         run[0] += a[j];
-        run[1] += b[j];
         cnt_own[t] = 0u;
         cnt_touch[t] = 0u;
-        fill[t] = 0u;
       }
     }
     __syncthreads();
-    if (tid < 4) carry[tid] += wtot[tid][SCAN_WAVES - 1];
+    if (tid < 3) carry[tid] += wtot[tid][SCAN_WAVES - 1];
     __syncthreads();
   }
   if (tid == 0) {
     start_own[ntiles] = carry[0];
-    start_touch[ntiles] = carry[1];
-    meta[0] = carry[2];
-    meta[1] = carry[3];
+    meta[0] = carry[1];
+    meta[1] = carry[2];
   }
   for (int64_t w = tid; w < nbflag_words; w += SCAN_THREADS) bflag_words[w] = 0u;
 }
 
 // Pass 3: move every point again (same arithmetic), store it at its slot in
-// owner-tile order, append its slot to the lists of the tiles it touches, and
-// flag the 4^3 force blocks of its support.  FP64 partial sums of s and
-// s |u_b|^2 per workgroup.
+// owner-tile order and flag the 4^3 force blocks of its support.  FP64
+// partial sums of s and s |u_b|^2 per workgroup.
 __global__ __launch_bounds__(LBM_BLOCK) void k_point_scatter(
     const float4* __restrict__ rest, const int32_t* __restrict__ body_of,
     const BodyMotion* __restrict__ motion, int64_t npts, PointGeom pg,
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
-    const uint32_t* __restrict__ start_own, const uint32_t* __restrict__ start_touch,
-    uint32_t* __restrict__ fill, uint32_t* __restrict__ tlist, int4* __restrict__ sp_base,
+    const uint32_t* __restrict__ start_own, int4* __restrict__ sp_base,
     float4* __restrict__ sp_frac, float4* __restrict__ sp_ub, uint8_t* __restrict__ bflag,
     double* __restrict__ part_s, double* __restrict__ part_sub2) {
   const int64_t k = (int64_t)blockIdx.x * LBM_BLOCK + threadIdx.x;
-  const bool valid = k < npts;
   double ps_s = 0.0, ps_ub2 = 0.0;
-  PointState ps{};
-  uint32_t slot = 0;
-  if (valid) {
+  if (k < npts) {
     const float4 r4 = rest[k];
-    ps = move_point(motion[body_of[k]], r4, pg);
-    slot = start_own[key[k]] + rank[k];
+    const PointState ps = move_point(motion[body_of[k]], r4, pg);
+    const uint32_t slot = start_own[key[k]] + rank[k];
     sp_base[slot] = make_int4(ps.base[0], ps.base[1], ps.base[2], (int)k);
     sp_frac[slot] = make_float4(ps.frac[0], ps.frac[1], ps.frac[2], r4.w);
     sp_ub[slot] = make_float4(ps.ub[0], ps.ub[1], ps.ub[2], 0.0f);
@@ -318,20 +328,6 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_point_scatter(
     ps_s = r4.w;
     ps_ub2 = (double)r4.w * ((double)ps.ub[0] * ps.ub[0] + (double)ps.ub[1] * ps.ub[1] +
                              (double)ps.ub[2] * ps.ub[2]);
-  }
-  Span1 sx{0, 0, 0, 0}, sy{0, 0, 0, 0}, sz{0, 0, 0, 0};
-  if (valid) {
-    sx = span_axis(ps.base[0], pg.n[0], pg.bc[0], TILE_SHIFT);
-    sy = span_axis(ps.base[1], pg.n[1], pg.bc[1], TILE_SHIFT);
-    sz = span_axis(ps.base[2], pg.n[2], pg.bc[2], TILE_SHIFT);
-  }
-  for (int j = 0; j < 27; ++j) {
-    const int jx = j % 3, jy = (j / 3) % 3, jz = j / 9;
-    const bool v = valid && jx < sx.n && jy < sy.n && jz < sz.n;
-    if (!__ballot(v)) continue;
-    const uint32_t t = v ? tile_index(pg, sx.at(jx), sy.at(jy), sz.at(jz)) : 0u;
-    const uint32_t pos = agg_increment(fill, t, v);
-    if (v) tlist[start_touch[t] + pos] = slot;
   }
   __shared__ double red[2][LBM_BLOCK / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -387,7 +383,7 @@ __global__ __launch_bounds__(TILE3) void k_moments_blocks(
   if (x >= g.nx || y >= g.ny || z >= g.nz) return;
   if (!bflag[fblock_of(g, x, y, z)]) return;
   float f[Q];
-  gather_pull<S>(lat, g, x, y, z, f);
+  gather_any<S>(lat, g, x, y, z, f);
   float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -415,189 +411,303 @@ __device__ __forceinline__ void peskin4(float r, float w[4]) {
   w[3] = (1.0f + 2.0f * r - q) * 0.125f;
 }
 
-// Interpolation, deficit and correction for one sweep (§3; Algorithm 1):
-// u = sum_taps U W, g = u_b - u, du = (first ? 0 : du) + s g.  One workgroup
-// per tile that owns points; U of the tile plus halo staged in LDS.  FP64
-// partial sum of s |g|^2 per workgroup (0 for idle workgroups).
-__global__ __launch_bounds__(WG) void k_interp_tiles(
+// One sweep of the multi-direct forcing for the points of one owner tile
+// (§3; Algorithms 1 and 2):
+//   u = sum_taps U W, g = u_b - u, du = (first ? 0 : du) + s g       (Alg. 1)
+//   v = s g (inner sweep), g (paper-literal inner sweep), du (last sweep)
+//   box(X) = sum_k v(k) W_k(X) over the tile's points                (Alg. 2)
+// U is staged over the 11^3 box [o-1, o+10)^3 that holds every tap of the
+// tile's points (coordinates wrapped on periodic axes).  The box sum is
+// accumulated in LDS in 32-bit fixed point with the unit B / 2^30, where
+// B = (1/8) sum_k max_c |v_k,c| bounds every box cell (a tap weight is at
+// most 1/8): no overflow is possible and integer addition makes the sum
+// independent of the order of the atomics.  The box is stored as FP32 in
+// the tile's slot of boxbuf.  FP64 partial of s |g|^2 per workgroup.
+constexpr float FIX_ONE = 1073741824.0f;  // 2^30
+__global__ __launch_bounds__(WG) void k_sweep_tiles(
     const uint32_t* __restrict__ own_tiles, const uint32_t* __restrict__ meta,
     const uint32_t* __restrict__ start_own, const int4* __restrict__ sp_base,
     const float4* __restrict__ sp_frac, const float4* __restrict__ sp_ub,
     float4* __restrict__ sp_g, float4* __restrict__ sp_du, const float* __restrict__ U,
-    PointGeom pg, int first, double* __restrict__ part_res) {
-  __shared__ float sUx[BOX3], sUy[BOX3], sUz[BOX3];
-  __shared__ double red[WG / 64];
-  double res = 0.0;
-  const int64_t e = list_entry(meta[0]);
-  if (e >= 0) {
-    const uint32_t t = own_tiles[e];
-    int o[3];
-    tile_origin(pg, t, o);
-#pragma unroll 2
-    for (int i = threadIdx.x; i < BOX3; i += WG) {
-      const int bx = i % BOX, by = (i / BOX) % BOX, bz = i / (BOX * BOX);
-      const int cx = tap_coord(o[0] - 1 + bx, pg.n[0], pg.bc[0]);
-      const int cy = tap_coord(o[1] - 1 + by, pg.n[1], pg.bc[1]);
-      const int cz = tap_coord(o[2] - 1 + bz, pg.n[2], pg.bc[2]);
-      const int64_t c = (int64_t)cx + (int64_t)pg.n[0] * ((int64_t)cy + (int64_t)pg.n[1] * cz);
-      sUx[i] = U[c];
-      sUy[i] = U[pg.ncell + c];
-      sUz[i] = U[2 * pg.ncell + c];
-    }
-    __syncthreads();
-    const uint32_t p0 = start_own[t], p1 = start_own[t + 1];
-    for (uint32_t k = p0 + threadIdx.x; k < p1; k += WG) {
-      const int4 b = sp_base[k];
-      const float4 fr = sp_frac[k];
-      float wx[4], wy[4], wz[4];
-      peskin4(fr.x, wx);
-      peskin4(fr.y, wy);
-      peskin4(fr.z, wz);
-      // box-local index of tap (-1, -1, -1): the box starts one cell before the tile
-      const int l0 = (b.x - o[0]) + BOX * ((b.y - o[1]) + BOX * (b.z - o[2]));
-      float u0 = 0.f, u1 = 0.f, u2 = 0.f;
-#pragma unroll 1
-      for (int cz = 0; cz < 4; ++cz) {
-        const float wzc = cz == 0 ? wz[0] : (cz == 1 ? wz[1] : (cz == 2 ? wz[2] : wz[3]));
-#pragma unroll
-        for (int cy = 0; cy < 4; ++cy) {
-          const float wyz = wzc * wy[cy];
-          const int row = l0 + BOX * (cy + BOX * cz);
-#pragma unroll
-          for (int cx = 0; cx < 4; ++cx) {
-            const float w = wyz * wx[cx];
-            u0 += w * sUx[row + cx];
-            u1 += w * sUy[row + cx];
-            u2 += w * sUz[row + cx];
-          }
-        }
-      }
-      const float4 ub = sp_ub[k];
-      const float g0 = ub.x - u0, g1 = ub.y - u1, g2 = ub.z - u2;
-      float4 du = first ? make_float4(0.f, 0.f, 0.f, 0.f) : sp_du[k];
-      du.x += fr.w * g0;
-      du.y += fr.w * g1;
-      du.z += fr.w * g2;
-      sp_g[k] = make_float4(g0, g1, g2, 0.0f);
-      sp_du[k] = du;
-      res += (double)fr.w * ((double)g0 * g0 + (double)g1 * g1 + (double)g2 * g2);
-    }
-  }
+    float* __restrict__ boxbuf, PointGeom pg, int first, int last, int inner_weighted,
+    double* __restrict__ part_res) {
+  // U of the box during the interpolation, then (same storage) the integer
+  // accumulator of the spread
+  __shared__ float sU[3][BOX3];
+  int (*acc)[BOX3] = reinterpret_cast<int (*)[BOX3]>(sU);
+  __shared__ float fred[WG / 64];
+  __shared__ double dred[WG / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double v = wave_sum(res);
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0;
-    for (int w = 0; w < WG / 64; ++w) s += red[w];
-    part_res[blockIdx.x] = s;
+  const int64_t e = list_entry(meta[0]);
+  if (e < 0) {  // idle workgroup: empty residual partial
+    if (threadIdx.x == 0) part_res[blockIdx.x] = 0.0;
+    return;
   }
-}
-
-// Spreading (§3; Algorithm 2) for one sweep: every touched tile sums
-// v(k) W_k over its listed points in LDS, then
-//   mode 0/1 (inner sweep, v = s g or g):  U += sum   on cells with a nonzero sum
-//   mode 2   (final spread, v = du):       G  = sum   on every cell of the tile.
-// The LDS sum is kept in 32-bit fixed point (integer LDS atomics are fast on
-// CDNA; float ones are not) with a per-tile unit B / 2^30, where
-// B = (1/8) sum_k max_c |v_k,c| bounds every cell's sum (a tap weight is at
-// most 1/8), so it cannot overflow; integer addition also makes the result
-// independent of the order of the atomics.
-constexpr float FIX_ONE = 1073741824.0f;  // 2^30
-__global__ __launch_bounds__(WG) void k_spread_tiles(
-    const uint32_t* __restrict__ touch_tiles, const uint32_t* __restrict__ meta,
-    const uint32_t* __restrict__ start_touch, const uint32_t* __restrict__ tlist,
-    const int4* __restrict__ sp_base, const float4* __restrict__ sp_frac,
-    const float4* __restrict__ vsrc, float* __restrict__ target, PointGeom pg, int mode) {
-  __shared__ int acc[3][TILE3];
-  __shared__ float red[WG / 64];
-  const int64_t e = list_entry(meta[1]);
-  if (e < 0) return;
-  const uint32_t t = touch_tiles[e];
+  const uint32_t t = own_tiles[e];
   int o[3];
   tile_origin(pg, t, o);
-  for (int i = threadIdx.x; i < 3 * TILE3; i += WG) (&acc[0][0])[i] = 0;
-  const uint32_t q0 = start_touch[t], L = start_touch[t + 1] - q0;
-  // bound of the cell sums
-  float bsum = 0.0f;
-  for (uint32_t i = threadIdx.x; i < L; i += WG) {
-    const uint32_t k = tlist[q0 + i];
-    const float4 v = vsrc[k];
-    const float sc = mode == 0 ? sp_frac[k].w : 1.0f;
-    bsum += sc * fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
+#pragma unroll 2
+  for (int i = threadIdx.x; i < BOX3; i += WG) {
+    const int bx = i % BOX, by = (i / BOX) % BOX, bz = i / (BOX * BOX);
+    const int cx = tap_coord(o[0] - 1 + bx, pg.n[0], pg.bc[0]);
+    const int cy = tap_coord(o[1] - 1 + by, pg.n[1], pg.bc[1]);
+    const int cz = tap_coord(o[2] - 1 + bz, pg.n[2], pg.bc[2]);
+    const int64_t c = (int64_t)cx + (int64_t)pg.n[0] * ((int64_t)cy + (int64_t)pg.n[1] * cz);
+    sU[0][i] = U[c];
+    sU[1][i] = U[pg.ncell + c];
+    sU[2][i] = U[2 * pg.ncell + c];
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) bsum += __shfl_xor(bsum, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = bsum;
   __syncthreads();
-  float B = 0.0f;
-#pragma unroll
-  for (int w = 0; w < WG / 64; ++w) B += red[w];
-  B *= 0.125f;
-  const float scale = B > 0.0f ? FIX_ONE / B : 0.0f;
-  // Neighbouring list entries are neighbouring points; a stride coprime to
-  // the list length deals them to lanes in scattered order so that the lanes
-  // of a wave rarely add into the same LDS word at once.
-  const uint32_t P = (L % 97u) ? 97u : 89u;
-  for (uint32_t i = threadIdx.x; i < L; i += WG) {
-    const uint32_t k = tlist[q0 + (uint32_t)(((uint64_t)i * P) % L)];
+  const uint32_t p0 = start_own[t], p1 = start_own[t + 1];
+  // pass 1: interpolation, deficit, correction
+  float bsum = 0.0f;
+  double res = 0.0;
+  for (uint32_t k = p0 + threadIdx.x; k < p1; k += WG) {
     const int4 b = sp_base[k];
     const float4 fr = sp_frac[k];
-    float4 v = vsrc[k];
-    const float vs = (mode == 0 ? fr.w : 1.0f) * scale;
-    v.x *= vs;
-    v.y *= vs;
-    v.z *= vs;
     float wx[4], wy[4], wz[4];
     peskin4(fr.x, wx);
     peskin4(fr.y, wy);
     peskin4(fr.z, wz);
-    int lx[4], ly[4], lz[4];  // tile-local tap coordinates, -1 when outside the tile
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int cx = tap_coord(b.x - 1 + j, pg.n[0], pg.bc[0]) - o[0];
-      const int cy = tap_coord(b.y - 1 + j, pg.n[1], pg.bc[1]) - o[1];
-      const int cz = tap_coord(b.z - 1 + j, pg.n[2], pg.bc[2]) - o[2];
-      lx[j] = (cx >= 0 && cx < TILE) ? cx : -1;
-      ly[j] = (cy >= 0 && cy < TILE) ? cy : -1;
-      lz[j] = (cz >= 0 && cz < TILE) ? cz : -1;
-    }
-#pragma unroll
+    // box index of tap (-1, -1, -1): the box starts one cell before the tile
+    const int l0 = (b.x - o[0]) + BOX * ((b.y - o[1]) + BOX * (b.z - o[2]));
+    float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+#pragma unroll 1
     for (int cz = 0; cz < 4; ++cz) {
+      const float wzc = cz == 0 ? wz[0] : (cz == 1 ? wz[1] : (cz == 2 ? wz[2] : wz[3]));
 #pragma unroll
       for (int cy = 0; cy < 4; ++cy) {
-        const float wyz = wz[cz] * wy[cy];
-        const int row = TILE * (ly[cy] + TILE * lz[cz]);
-        const bool in_yz = (ly[cy] | lz[cz]) >= 0;
+        const float wyz = wzc * wy[cy];
+        const int row = l0 + BOX * (cy + BOX * cz);
 #pragma unroll
         for (int cx = 0; cx < 4; ++cx) {
-          if (in_yz && lx[cx] >= 0) {
-            const float w = wyz * wx[cx];
-            const int idx = row + lx[cx];
-            atomicAdd(&acc[0][idx], __float2int_rn(w * v.x));
-            atomicAdd(&acc[1][idx], __float2int_rn(w * v.y));
-            atomicAdd(&acc[2][idx], __float2int_rn(w * v.z));
-          }
+          const float w = wyz * wx[cx];
+          u0 += w * sU[0][row + cx];
+          u1 += w * sU[1][row + cx];
+          u2 += w * sU[2][row + cx];
+        }
+      }
+    }
+    const float4 ub = sp_ub[k];
+    const float g0 = ub.x - u0, g1 = ub.y - u1, g2 = ub.z - u2;
+    float4 du = first ? make_float4(0.f, 0.f, 0.f, 0.f) : sp_du[k];
+    du.x += fr.w * g0;
+    du.y += fr.w * g1;
+    du.z += fr.w * g2;
+    du.w = 0.0f;
+    sp_g[k] = make_float4(g0, g1, g2, 0.0f);
+    sp_du[k] = du;
+    res += (double)fr.w * ((double)g0 * g0 + (double)g1 * g1 + (double)g2 * g2);
+    const float vs = last ? 1.0f : (inner_weighted ? fr.w : 1.0f);
+    const float v0 = last ? du.x : vs * g0, v1 = last ? du.y : vs * g1, v2 = last ? du.z : vs * g2;
+    bsum += fmaxf(fabsf(v0), fmaxf(fabsf(v1), fabsf(v2)));
+  }
+  // block sums: bound B (FP32) and residual (FP64)
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) bsum += __shfl_xor(bsum, off, 64);
+  const double rv = wave_sum(res);
+  if (lane == 0) {
+    fred[wave] = bsum;
+    dred[wave] = rv;
+  }
+  __syncthreads();
+  float B = 0.0f;
+#pragma unroll
+  for (int w = 0; w < WG / 64; ++w) B += fred[w];
+  B *= 0.125f;
+  if (threadIdx.x == 0) {
+    double sres = 0.0;
+    for (int w = 0; w < WG / 64; ++w) sres += dred[w];
+    part_res[blockIdx.x] = sres;
+  }
+  const float scale = B > 0.0f ? FIX_ONE / B : 0.0f;
+  // the interpolation is done (barrier above): clear the accumulator
+  for (int i = threadIdx.x; i < 3 * BOX3; i += WG) (&acc[0][0])[i] = 0;
+  __syncthreads();
+  // pass 2: spread into the box (every tap of an owned point is inside it).
+  // Neighbouring slots hold neighbouring points, which add into the same LDS
+  // words tap after tap; a stride coprime to the point count deals them to
+  // the lanes in scattered order, and each lane starts at its own z-plane.
+  const uint32_t L = p1 - p0;
+  const uint32_t P = (L % 97u) ? 97u : 89u;
+  const uint32_t step = L ? (uint32_t)(((uint64_t)WG * P) % L) : 0u;
+  uint32_t pos = L ? (uint32_t)(((uint64_t)threadIdx.x * P) % L) : 0u;
+  const int zrot = lane & 3;
+  for (uint32_t i = threadIdx.x; i < L; i += WG) {
+    const uint32_t k = p0 + pos;
+    pos += step;
+    if (pos >= L) pos -= L;
+    const int4 b = sp_base[k];
+    const float4 fr = sp_frac[k];
+    float v0, v1, v2;
+    if (last) {
+      const float4 du = sp_du[k];
+      v0 = du.x * scale;
+      v1 = du.y * scale;
+      v2 = du.z * scale;
+    } else {
+      const float4 g = sp_g[k];
+      const float vs = (inner_weighted ? fr.w : 1.0f) * scale;
+      v0 = g.x * vs;
+      v1 = g.y * vs;
+      v2 = g.z * vs;
+    }
+    float wx[4], wy[4], wz[4];
+    peskin4(fr.x, wx);
+    peskin4(fr.y, wy);
+    peskin4(fr.z, wz);
+    const int l0 = (b.x - o[0]) + BOX * ((b.y - o[1]) + BOX * (b.z - o[2]));
+#pragma unroll 1
+    for (int jz = 0; jz < 4; ++jz) {
+      const int cz = (jz + zrot) & 3;
+      const float wzc = cz == 0 ? wz[0] : (cz == 1 ? wz[1] : (cz == 2 ? wz[2] : wz[3]));
+#pragma unroll
+      for (int cy = 0; cy < 4; ++cy) {
+        const float wyz = wzc * wy[cy];
+        const int row = l0 + BOX * (cy + BOX * cz);
+#pragma unroll
+        for (int cx = 0; cx < 4; ++cx) {
+          const float w = wyz * wx[cx];
+          atomicAdd(&acc[0][row + cx], __float2int_rn(w * v0));
+          atomicAdd(&acc[1][row + cx], __float2int_rn(w * v1));
+          atomicAdd(&acc[2][row + cx], __float2int_rn(w * v2));
         }
       }
     }
   }
   __syncthreads();
   const float unit = B / FIX_ONE;
-  for (int i = threadIdx.x; i < TILE3; i += WG) {
-    const int x = o[0] + (i & (TILE - 1)), y = o[1] + ((i >> TILE_SHIFT) & (TILE - 1)),
-              z = o[2] + (i >> (2 * TILE_SHIFT));
+  float* box = boxbuf + (int64_t)e * 3 * BOX3;
+  for (int i = threadIdx.x; i < BOX3; i += WG) {
+    box[i] = (float)acc[0][i] * unit;
+    box[BOX3 + i] = (float)acc[1][i] * unit;
+    box[2 * BOX3 + i] = (float)acc[2][i] * unit;
+  }
+}
+
+// Boxes covering one cell coordinate along one axis: the owner tiles A and
+// box positions b with wrap(o_A - 1 + b) = x, b in [0, 11).  At most 11
+// (only for axes shorter than the box); usually 1 or 2.
+constexpr int MAXCOV = BOX;
+__device__ __forceinline__ int covering(int x, int n, int bc, int ntiles_axis, int16_t* tt,
+                                        int16_t* bb) {
+  int cnt = 0;
+  const int kmax = bc == LBM_BC_PERIODIC ? (BOX + n - 1) / n + 1 : 0;
+  for (int k = -kmax; k <= kmax; ++k) {
+    // origins o = 8 t with o + k n in [x - 9, x + 1]
+    const int lo = x - 9 - k * n, hi = x + 1 - k * n;
+    int t0 = lo <= 0 ? 0 : (lo + TILE - 1) / TILE;
+    const int t1 = hi < 0 ? -1 : min(hi / TILE, ntiles_axis - 1);
+    for (int tv = t0; tv <= t1 && cnt < MAXCOV; ++tv) {
+      tt[cnt] = (int16_t)tv;
+      bb[cnt] = (int16_t)(x - (TILE * tv + k * n) + 1);
+      ++cnt;
+    }
+  }
+  return cnt;
+}
+
+// Merge of the stored boxes into one touched tile: for every cell of a
+// flagged force block, the sum over the boxes that cover it (fixed order):
+//   mode 0: U += sum on cells with a nonzero sum;   mode 2: G = sum.
+constexpr int MERGE_WG = 256;
+__global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
+    const uint32_t* __restrict__ touch_tiles, const uint32_t* __restrict__ meta,
+    const int32_t* __restrict__ own_slot, const float* __restrict__ boxbuf,
+    const uint8_t* __restrict__ bflag, float* __restrict__ target, PointGeom pg, int mode) {
+  __shared__ int16_t ct[3][TILE][MAXCOV], cb[3][TILE][MAXCOV];
+  __shared__ int cn[3][TILE];
+  const int64_t e = list_entry(meta[1]);
+  if (e < 0) return;
+  const uint32_t t = touch_tiles[e];
+  int o[3], tc[3];
+  tile_origin(pg, t, o);
+  for (int a = 0; a < 3; ++a) tc[a] = o[a] / TILE;
+  // Fast path: on every axis the tile and both neighbours are full tiles
+  // without a wrap, so the boxes covering local coordinate l are the own
+  // tile (position l + 1), the previous tile when l <= 1 (position l + 9)
+  // and the next tile when l == 7 (position 0).
+  bool simple = true;
+  for (int a = 0; a < 3; ++a)
+    simple = simple && tc[a] >= 1 && (tc[a] + 2) * TILE <= pg.n[a];
+  if (!simple) {  // general covering tables (short axes, seams, short tiles)
+    if (threadIdx.x < 3 * TILE) {
+      const int a = threadIdx.x / TILE, l = threadIdx.x % TILE;
+      const int x = o[a] + l;
+      cn[a][l] = x < pg.n[a] ? covering(x, pg.n[a], pg.bc[a], pg.tiles[a], ct[a][l], cb[a][l]) : 0;
+    }
+    __syncthreads();
+  }
+  for (int cell = threadIdx.x; cell < TILE3; cell += MERGE_WG) {
+    const int lx = cell & (TILE - 1), ly = (cell >> TILE_SHIFT) & (TILE - 1),
+              lz = cell >> (2 * TILE_SHIFT);
+    const int x = o[0] + lx, y = o[1] + ly, z = o[2] + lz;
     if (x >= pg.n[0] || y >= pg.n[1] || z >= pg.n[2]) continue;
+    // only cells of flagged force blocks can receive a contribution, and
+    // only there is G read by the stream-collide
+    if (!bflag[(int64_t)(x >> FBLK_SHIFT) +
+               (int64_t)pg.fblk[0] * ((int64_t)(y >> FBLK_SHIFT) + (int64_t)pg.fblk[1] * (z >> FBLK_SHIFT))])
+      continue;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    if (simple) {
+      const int l[3] = {lx, ly, lz};
+      int nd[3][2], nb[3][2], nn[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        nd[a][0] = 0;
+        nb[a][0] = l[a] + 1;
+        nn[a] = 1;
+        nd[a][1] = 0;
+        nb[a][1] = 0;
+        if (l[a] <= 1) {
+          nd[a][1] = -1;
+          nb[a][1] = l[a] + 9;
+          nn[a] = 2;
+        } else if (l[a] == TILE - 1) {
+          nd[a][1] = 1;
+          nn[a] = 2;
+        }
+      }
+#pragma unroll
+      for (int jz = 0; jz < 2; ++jz)
+#pragma unroll
+        for (int jy = 0; jy < 2; ++jy)
+#pragma unroll
+          for (int jx = 0; jx < 2; ++jx) {
+            if (jx >= nn[0] || jy >= nn[1] || jz >= nn[2]) continue;
+            const int32_t slot =
+                own_slot[tile_index(pg, tc[0] + nd[0][jx], tc[1] + nd[1][jy], tc[2] + nd[2][jz])];
+            if (slot < 0) continue;
+            const int bi = nb[0][jx] + BOX * (nb[1][jy] + BOX * nb[2][jz]);
+            const float* box = boxbuf + (int64_t)slot * 3 * BOX3;
+            s0 += box[bi];
+            s1 += box[BOX3 + bi];
+            s2 += box[2 * BOX3 + bi];
+          }
+    } else {
+      const int nx_ = cn[0][lx], ny_ = cn[1][ly], nz_ = cn[2][lz];
+      for (int jz = 0; jz < nz_; ++jz)
+        for (int jy = 0; jy < ny_; ++jy)
+          for (int jx = 0; jx < nx_; ++jx) {
+            const uint32_t A = tile_index(pg, ct[0][lx][jx], ct[1][ly][jy], ct[2][lz][jz]);
+            const int32_t slot = own_slot[A];
+            if (slot < 0) continue;
+            const int bi = cb[0][lx][jx] + BOX * (cb[1][ly][jy] + BOX * cb[2][lz][jz]);
+            const float* box = boxbuf + (int64_t)slot * 3 * BOX3;
+            s0 += box[bi];
+            s1 += box[BOX3 + bi];
+            s2 += box[2 * BOX3 + bi];
+          }
+    }
     const int64_t c = (int64_t)x + (int64_t)pg.n[0] * ((int64_t)y + (int64_t)pg.n[1] * z);
-    const int a0 = acc[0][i], a1 = acc[1][i], a2 = acc[2][i];
     if (mode == 2) {
-      target[c] = (float)a0 * unit;
-      target[pg.ncell + c] = (float)a1 * unit;
-      target[2 * pg.ncell + c] = (float)a2 * unit;
-    } else if (a0 != 0 || a1 != 0 || a2 != 0) {
-      target[c] += (float)a0 * unit;
-      target[pg.ncell + c] += (float)a1 * unit;
-      target[2 * pg.ncell + c] += (float)a2 * unit;
+      target[c] = s0;
+      target[pg.ncell + c] = s1;
+      target[2 * pg.ncell + c] = s2;
+    } else if (s0 != 0.0f || s1 != 0.0f || s2 != 0.0f) {
+      target[c] += s0;
+      target[pg.ncell + c] += s1;
+      target[2 * pg.ncell + c] += s2;
     }
   }
 }
@@ -701,14 +811,13 @@ hipError_t launch_forcing(lbm_ctx* c) {
   k_point_count<<<nb, LBM_BLOCK, 0, st>>>(c->rest, c->body_of, c->motion, n, pg, c->key, c->rank,
                                           c->cnt_own, c->cnt_touch);
   LAUNCH_CHECK();
-  k_scan_tiles<<<1, SCAN_THREADS, 0, st>>>(c->cnt_own, c->cnt_touch, c->fill, c->start_own,
-                                           c->start_touch, c->own_tiles, c->touch_tiles, c->meta,
+  k_scan_tiles<<<1, SCAN_THREADS, 0, st>>>(c->cnt_own, c->cnt_touch, c->start_own, c->own_slot,
+                                           c->own_tiles, c->touch_tiles, c->meta,
                                            (uint32_t*)c->bflag, c->nbflag_words, c->ntiles);
   LAUNCH_CHECK();
   k_point_scatter<<<nb, LBM_BLOCK, 0, st>>>(c->rest, c->body_of, c->motion, n, pg, c->key, c->rank,
-                                            c->start_own, c->start_touch, c->fill, c->tlist,
-                                            c->sp_base, c->sp_frac, c->sp_ub, c->bflag,
-                                            c->pt_partials, c->pt_partials + rs);
+                                            c->start_own, c->sp_base, c->sp_frac, c->sp_ub,
+                                            c->bflag, c->pt_partials, c->pt_partials + rs);
   LAUNCH_CHECK();
   switch (c->p.storage) {
     case LBM_STORE_F16:
@@ -724,18 +833,15 @@ hipError_t launch_forcing(lbm_ctx* c) {
           (const float*)c->lat[c->cur], c->geom, pg, c->touch_tiles, c->meta, c->bflag, c->U);
   }
   LAUNCH_CHECK();
-  const int inner_mode = (c->flags & IBM_INNER_UNWEIGHTED) ? 1 : 0;
+  const int inner_weighted = (c->flags & IBM_INNER_UNWEIGHTED) ? 0 : 1;
   for (int it = 0; it < c->n_iter; ++it) {
-    k_interp_tiles<<<lg, WG, 0, st>>>(c->own_tiles, c->meta, c->start_own, c->sp_base, c->sp_frac,
-                                      c->sp_ub, c->sp_g, c->sp_du, c->U, pg, it == 0,
-                                      c->pt_partials + (2 + it) * rs);
+    const int last = it == c->n_iter - 1;
+    k_sweep_tiles<<<lg, WG, 0, st>>>(c->own_tiles, c->meta, c->start_own, c->sp_base, c->sp_frac,
+                                     c->sp_ub, c->sp_g, c->sp_du, c->U, c->boxbuf, pg, it == 0,
+                                     last, inner_weighted, c->pt_partials + (2 + it) * rs);
     LAUNCH_CHECK();
-    if (it < c->n_iter - 1)
-      k_spread_tiles<<<lg, WG, 0, st>>>(c->touch_tiles, c->meta, c->start_touch, c->tlist,
-                                        c->sp_base, c->sp_frac, c->sp_g, c->U, pg, inner_mode);
-    else
-      k_spread_tiles<<<lg, WG, 0, st>>>(c->touch_tiles, c->meta, c->start_touch, c->tlist,
-                                        c->sp_base, c->sp_frac, c->sp_du, c->G, pg, 2);
+    k_merge_tiles<<<lg, MERGE_WG, 0, st>>>(c->touch_tiles, c->meta, c->own_slot, c->boxbuf,
+                                        c->bflag, last ? c->G : c->U, pg, last ? 2 : 0);
     LAUNCH_CHECK();
   }
   return hipSuccess;

@@ -57,14 +57,14 @@ struct lbm_ctx {
   int64_t nbflag_words = 0;    // bflag size in 32-bit words
   uint32_t* cnt_own = nullptr;     // [ntiles] points owned per tile (pass 1)
   uint32_t* cnt_touch = nullptr;   // [ntiles] points touching each tile (pass 1)
-  uint32_t* fill = nullptr;        // [ntiles] touch-list fill counters (pass 3)
   uint32_t* start_own = nullptr;   // [ntiles + 1]
-  uint32_t* start_touch = nullptr; // [ntiles + 1]
+  int32_t* own_slot = nullptr;     // [ntiles] index in own_tiles, or -1
   uint32_t* own_tiles = nullptr;   // compact list of tiles owning points
   uint32_t* touch_tiles = nullptr; // compact list of touched tiles
   uint32_t* meta = nullptr;        // [4]: list lengths
   uint8_t* bflag = nullptr;        // [nbflag_words * 4] force-block flags
-  uint32_t* tlist = nullptr;       // touch lists: sorted point slots per tile
+  float* boxbuf = nullptr;          // [max_boxes][3][11^3] spread boxes of owner tiles
+  int64_t max_boxes = 0;
   // scratch
   double* sum_partials = nullptr;   // [n_cell_blocks][4]
   int64_t n_cell_blocks = 0;
@@ -96,6 +96,7 @@ struct lbm_ctx {
 hipError_t launch_init_equilibrium(lbm_ctx* c);
 hipError_t launch_unstream_from(lbm_ctx* c, const void* pops, int f64);
 hipError_t launch_stream_collide(lbm_ctx* c);
+void stream_collide_shape(const lbm_ctx* c, dim3& grid, dim3& block);
 hipError_t launch_readout(lbm_ctx* c, float* rho, float* vel, void* pops, int pops_f64);
 hipError_t launch_reduce_sums(lbm_ctx* c, double* out4);
 hipError_t launch_fill_u8(lbm_ctx* c, uint8_t* p, uint8_t v, int64_t n);

@@ -28,15 +28,16 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
     const typename Store<S>::T* __restrict__ src, typename Store<S>::T* __restrict__ dst,
     const LatticeGeom g, const float* __restrict__ G, const uint8_t* __restrict__ flags,
     double* __restrict__ partials) {
-  const int64_t cell = (int64_t)blockIdx.x * LBM_BLOCK + threadIdx.x;
+  // 3-D launch: blockDim.x spans x, blockDim.y spans y, one z-plane per block row
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
-  if (cell < g.ncell) {
-    int x, y, z;
-    cell_xyz(g, cell, x, y, z);
+  if (x < g.nx && y < g.ny) {
+    const uint32_t cell = (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
     float f[Q];
-    gather_pull<S>(src, g, x, y, z, f);
-
-    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+    gather_any<S>(src, g, x, y, z, f);
+  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       drho += f[i];
@@ -84,18 +85,20 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
     part[3] = jz;
   }
   __shared__ double red[4][LBM_BLOCK / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     double v = wave_sum(part[k]);
     if (lane == 0) red[k][wave] = v;
   }
   __syncthreads();
-  if (threadIdx.x < 4) {
+  if (tid < 4) {
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < LBM_BLOCK / 64; ++w) s += red[threadIdx.x][w];
-    partials[(int64_t)blockIdx.x * 4 + threadIdx.x] = s;
+    for (int w = 0; w < LBM_BLOCK / 64; ++w) s += red[tid][w];
+    const int64_t blk = (int64_t)blockIdx.x + (int64_t)gridDim.x * ((int64_t)blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+    partials[blk * 4 + tid] = s;
   }
 }
 
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_readout(const typename Store<S>::
   int x, y, z;
   cell_xyz(g, cell, x, y, z);
   float f[Q];
-  gather_pull<S>(lat, g, x, y, z, f);
+  gather_any<S>(lat, g, x, y, z, f);
   float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -237,17 +240,32 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_export_force(const float* __restr
 
 int64_t cell_blocks(const lbm_ctx* c) { return (c->ncell + LBM_BLOCK - 1) / LBM_BLOCK; }
 
+}  // namespace
+
+// Launch shape of the stream-collide: 256 threads, blockDim.x = the x extent
+// rounded to a wavefront (at most 256), the rest of the block along y.
+void stream_collide_shape(const lbm_ctx* c, dim3& grid, dim3& block) {
+  int bx = ((c->p.nx + 63) / 64) * 64;
+  if (bx > LBM_BLOCK) bx = LBM_BLOCK;
+  const int by = LBM_BLOCK / bx;
+  block = dim3(bx, by, 1);
+  grid = dim3((c->p.nx + bx - 1) / bx, (c->p.ny + by - 1) / by, c->p.nz);
+}
+
+namespace {
+
 template <int S>
 hipError_t stream_collide_s(lbm_ctx* c) {
   using T = typename Store<S>::T;
   const T* src = (const T*)c->lat[c->cur];
   T* dst = (T*)c->lat[c->cur ^ 1];
-  dim3 grid((unsigned)cell_blocks(c));
+  dim3 grid, block;
+  stream_collide_shape(c, grid, block);
   if (c->p.forcing == LBM_FORCE_SHIFT)
-    k_stream_collide<S, LBM_FORCE_SHIFT><<<grid, LBM_BLOCK, 0, c->stream>>>(
+    k_stream_collide<S, LBM_FORCE_SHIFT><<<grid, block, 0, c->stream>>>(
         src, dst, c->geom, c->G, c->bflag, c->sum_partials);
   else
-    k_stream_collide<S, LBM_FORCE_GUO><<<grid, LBM_BLOCK, 0, c->stream>>>(
+    k_stream_collide<S, LBM_FORCE_GUO><<<grid, block, 0, c->stream>>>(
         src, dst, c->geom, c->G, c->bflag, c->sum_partials);
   return hipGetLastError();
 }
@@ -318,7 +336,10 @@ hipError_t launch_readout(lbm_ctx* c, float* rho, float* vel, void* pops, int po
 }
 
 hipError_t launch_reduce_sums(lbm_ctx* c, double* out4) {
-  k_reduce_sums<<<1, LBM_BLOCK, 0, c->stream>>>(c->sum_partials, cell_blocks(c),
+  dim3 grid, block;
+  stream_collide_shape(c, grid, block);
+  k_reduce_sums<<<1, LBM_BLOCK, 0, c->stream>>>(c->sum_partials,
+                                                (int64_t)grid.x * grid.y * grid.z,
                                                 (double)c->ncell, out4);
   return hipGetLastError();
 }

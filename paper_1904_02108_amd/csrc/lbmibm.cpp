@@ -25,14 +25,14 @@ struct Plan {
   // lattice
   size_t elem, pop_stride, lat_bytes;
   // points
-  size_t o_rest, o_body_of, o_key, o_rank, o_base, o_frac, o_ub, o_g, o_du, o_tlist, o_bodies,
-      o_motion;
+  size_t o_rest, o_body_of, o_key, o_rank, o_base, o_frac, o_ub, o_g, o_du, o_bodies, o_motion;
+  size_t o_box;
+  int64_t max_boxes;
   // tiles
-  size_t o_cnt_own, o_cnt_touch, o_fill, o_start_own, o_start_touch, o_own_tiles, o_touch_tiles,
-      o_meta, o_bflag;
+  size_t o_cnt_own, o_cnt_touch, o_start_own, o_own_slot, o_own_tiles, o_touch_tiles, o_meta,
+      o_bflag;
   int64_t nblocks4, nbflag_words;
   int fblk[3];
-  size_t tlist_mult;
   // scratch
   size_t o_sum_part, o_pt_part, o_small;
   int64_t part_row;
@@ -117,21 +117,20 @@ void make_plan(const lbm_params* p, Plan& pl) {
   pl.pop_stride = align_up((size_t)pl.ncell * pl.elem) / pl.elem;
   pl.lat_bytes = pl.pop_stride * pl.elem * lbmd::Q;
   pl.size[LBM_BUF_LATTICE] = 2 * pl.lat_bytes;
+  // U, G, and the spread boxes of the tiles that own points (at most one per
+  // tile and one per point)
   pl.size[LBM_BUF_FIELDS] = 2 * align_up(3 * (size_t)pl.ncell * sizeof(float));
 
   const size_t M = (size_t)std::max<int64_t>(p->max_points, 1);
   const int dims[3] = {p->nx, p->ny, p->nz};
-  pl.tlist_mult = 1;
   for (int a = 0; a < 3; ++a) {
     pl.tiles[a] = (dims[a] + lbmd::TILE - 1) / lbmd::TILE;
     pl.fblk[a] = (dims[a] + lbmd::FBLK - 1) / lbmd::FBLK;
-    // distinct tiles among 4 consecutive (wrapped) cells: 3 only when a last
-    // tile of 1 or 2 cells can be crossed
-    const int r = dims[a] % lbmd::TILE;
-    const int m = (r == 1 || r == 2) ? 3 : 2;
-    pl.tlist_mult *= (size_t)std::min(pl.tiles[a], m);
   }
   pl.ntiles = (int64_t)pl.tiles[0] * pl.tiles[1] * pl.tiles[2];
+  pl.max_boxes = std::max<int64_t>(1, std::min<int64_t>(pl.ntiles, p->max_points));
+  pl.o_box = pl.size[LBM_BUF_FIELDS];
+  pl.size[LBM_BUF_FIELDS] += align_up((size_t)pl.max_boxes * 3 * 11 * 11 * 11 * sizeof(float));
   pl.nblocks4 = (int64_t)pl.fblk[0] * pl.fblk[1] * pl.fblk[2];
   pl.nbflag_words = (pl.nblocks4 + 3) / 4;
 
@@ -145,25 +144,30 @@ void make_plan(const lbm_params* p, Plan& pl) {
   pl.o_ub = pc.take(M * sizeof(float4));
   pl.o_g = pc.take(M * sizeof(float4));
   pl.o_du = pc.take(M * sizeof(float4));
-  pl.o_tlist = pc.take(M * pl.tlist_mult * sizeof(uint32_t));
   pl.o_bodies = pc.take((size_t)LBM_MAX_BODIES * 8 * sizeof(double));
   pl.o_motion = pc.take((size_t)LBM_MAX_BODIES * sizeof(BodyMotion));
   pl.size[LBM_BUF_POINTS] = pc.at;
 
   const size_t NT = (size_t)pl.ntiles;
   Cursor tc;
-  pl.o_cnt_own = tc.take(NT * 4);
-  pl.o_cnt_touch = tc.take(NT * 4);
-  pl.o_fill = tc.take(NT * 4);
+  const size_t NTpad = (NT + 16383) / 16384 * 16384;  // whole chunks of the tile scan
+  pl.o_cnt_own = tc.take(NTpad * 4);
+  pl.o_cnt_touch = tc.take(NTpad * 4);
   pl.o_start_own = tc.take((NT + 1) * 4);
-  pl.o_start_touch = tc.take((NT + 1) * 4);
+  pl.o_own_slot = tc.take(NT * 4);
   pl.o_own_tiles = tc.take(NT * 4);
   pl.o_touch_tiles = tc.take(NT * 4);
   pl.o_meta = tc.take(4 * 4);
   pl.o_bflag = tc.take((size_t)pl.nbflag_words * 4);
   pl.size[LBM_BUF_TILES] = tc.at;
 
-  pl.n_cell_blocks = (pl.ncell + LBM_BLOCK - 1) / LBM_BLOCK;
+  {  // blocks of the stream-collide launch (see stream_collide_shape)
+    int bx = ((p->nx + 63) / 64) * 64;
+    if (bx > LBM_BLOCK) bx = LBM_BLOCK;
+    const int by = LBM_BLOCK / bx;
+    pl.n_cell_blocks = (int64_t)((p->nx + bx - 1) / bx) * ((p->ny + by - 1) / by) * p->nz;
+    pl.n_cell_blocks = std::max<int64_t>(pl.n_cell_blocks, (pl.ncell + LBM_BLOCK - 1) / LBM_BLOCK);
+  }
   pl.n_pt_blocks = ((int64_t)M + LBM_BLOCK - 1) / LBM_BLOCK;
   pl.part_row = std::max<int64_t>(pl.n_pt_blocks, (pl.ntiles + 7) / 8 * 8);
   Cursor sc;
@@ -315,16 +319,16 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->sp_du = (float4*)(P + pl.o_du);
   c->bodies = (double*)(P + pl.o_bodies);
   c->motion = (BodyMotion*)(P + pl.o_motion);
-  c->tlist = (uint32_t*)(P + pl.o_tlist);
+  c->boxbuf = (float*)(F + pl.o_box);
+  c->max_boxes = pl.max_boxes;
   char* T = (char*)bufs[LBM_BUF_TILES];
   for (int a = 0; a < 3; ++a) c->fblk[a] = pl.fblk[a];
   c->nblocks4 = pl.nblocks4;
   c->nbflag_words = pl.nbflag_words;
   c->cnt_own = (uint32_t*)(T + pl.o_cnt_own);
   c->cnt_touch = (uint32_t*)(T + pl.o_cnt_touch);
-  c->fill = (uint32_t*)(T + pl.o_fill);
   c->start_own = (uint32_t*)(T + pl.o_start_own);
-  c->start_touch = (uint32_t*)(T + pl.o_start_touch);
+  c->own_slot = (int32_t*)(T + pl.o_own_slot);
   c->own_tiles = (uint32_t*)(T + pl.o_own_tiles);
   c->touch_tiles = (uint32_t*)(T + pl.o_touch_tiles);
   c->meta = (uint32_t*)(T + pl.o_meta);
@@ -337,9 +341,9 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->small = (double*)(S + pl.o_small);
 
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = launch_fill_u32(c, c->cnt_own, 0u, c->ntiles);
-  if (e == hipSuccess) e = launch_fill_u32(c, c->cnt_touch, 0u, c->ntiles);
-  if (e == hipSuccess) e = launch_fill_u32(c, c->fill, 0u, c->ntiles);
+  const int64_t ntpad = (c->ntiles + 16383) / 16384 * 16384;
+  if (e == hipSuccess) e = launch_fill_u32(c, c->cnt_own, 0u, ntpad);
+  if (e == hipSuccess) e = launch_fill_u32(c, c->cnt_touch, 0u, ntpad);
   if (e == hipSuccess) e = launch_fill_u32(c, c->meta, 0u, 4);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->bflag, 0u, c->nbflag_words);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->U, 0u, 3 * c->ncell);

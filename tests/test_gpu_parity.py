@@ -183,6 +183,24 @@ def test_special_positions(L, lat):
     _check_forcing(sim, p, pts, wl, 0, U0)
 
 
+@pytest.mark.parametrize("shape", [(9, 3, 10), (10, 2, 11), (12, 1, 9), (17, 9, 20)])
+def test_short_periodic_axes(L, lat, shape):
+    """Axes shorter than a support or than a tile, and short last tiles: the
+    supports wrap onto the same cells several times; both sides add every
+    wrapped tap."""
+    x = W.random_points(shape, 30, 81, special=False)
+    c = np.array(shape, dtype=np.float64) / 2
+    rest = (x - c).astype(np.float32)
+    area = np.linspace(0.2, 1.0, 30).astype(np.float32)
+    bodies = np.array([[c[0], c[1], c[2], 0.0, 0.0, 1.0, 0.0, 0.0]])
+    wl = W.Workload("short", shape, 0.7, (0, 0, 0), 0, rest, area, np.array([0, 30]), bodies, 5, 1)
+    sim, p, pts = sim_for_workload(L, wl)
+    f0 = _rand_pops(shape, 82, lat, amp=0.03)
+    sim.write(pops=f0)
+    _, U0 = O.moments(p, f0)
+    _check_forcing(sim, p, pts, wl, 0, U0)
+
+
 def test_multi_body_with_empty_body(L, lat):
     a = W.tiny_propeller_case(shape=(30, 26, 24))
     b = W.tiny_propeller_case(shape=(30, 26, 24), axis=(1, 0.2, 0), omega=-0.03, theta0=1.0,

@@ -1,0 +1,69 @@
+"""Precision form: populations stored as FP16 or BF16 offsets f_i - t_i, all
+arithmetic in FP32 (GPU), compared with the FP64 oracle.
+
+One step is compared from the state the GPU actually holds (its rounded
+populations are read back and handed to the oracle), so the only error left
+is the 16-bit rounding of the step's output: relative L-infinity on the
+population offsets within 2^-11 (FP16) / 2^-8 (BF16) of the largest offset,
+with a factor 2 for the two roundings.  Whole runs from rest report their
+drift from the FP64 oracle; the bounds below hold with margin on C0."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_common import make_sim, oracle_params, rel_linf, sim_for_workload, to_np
+from paper_1904_02108_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+EPS16 = {1: 2.0 ** -11, 2: 2.0 ** -8}
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1904_02108_amd import lbmibm
+    return lbmibm
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+@pytest.mark.parametrize("bc", [(0, 0, 0), (0, 1, 1)])
+def test_one_step_16bit(L, storage, bc):
+    shape = (14, 11, 9)
+    _, w, _ = O.d3q19()
+    sim = make_sim(L, shape, 0.7, bc=bc, storage=storage)
+    f0 = W.random_populations(shape, 71, amp=0.05, weights=w)
+    G = W.random_field(shape, 72, amp=1e-3)
+    sim.write(pops=f0, force=G)
+    held = to_np(sim.read("pops", pops_f64=True)["pops"])      # rounded state
+    assert rel_linf(held - w.reshape(19, 1, 1, 1), f0 - w.reshape(19, 1, 1, 1)) < EPS16[storage]
+    sim.step(1)
+    out = to_np(sim.read("pops", pops_f64=True)["pops"])
+    ref = O.collide_stream(oracle_params(shape, 0.7, bc=bc), held, G)
+    off = w.reshape(19, 1, 1, 1)
+    assert rel_linf(out - off, ref - off) < 2 * EPS16[storage]
+
+
+@pytest.mark.parametrize("storage,tol_vel", [(1, 5e-3), (2, 5e-2)])
+def test_c0_run_16bit(L, storage, tol_vel):
+    """C0 for 50 steps from rest: velocity, force and point corrections stay
+    close to the FP64 oracle; total mass is conserved to FP64 rounding of
+    the stored offsets (reported)."""
+    wl = W.config("c0")
+    sim, p, pts = sim_for_workload(L, wl, storage=storage)
+    f = O.init_equilibrium(p)
+    sim.step(49)
+    O.run(p, f, pts, 0, 49)
+    r = O.step(p, f, pts, 49)
+    sim.step(1)
+    out = sim.read("vel", "force", "pt_du", "sums")
+    _, U = O.moments(p, f)
+    e_vel = rel_linf(to_np(out["vel"]), U)
+    e_G = rel_linf(to_np(out["force"]), r["G"])
+    e_du = rel_linf(to_np(out["pt_du"]), r["du"])
+    mass0 = float(np.prod(wl.shape))
+    drift = abs(float(to_np(out["sums"])[0]) - mass0) / mass0
+    print("storage", storage, "vel", e_vel, "G", e_G, "du", e_du, "mass drift", drift, flush=True)
+    assert e_vel < tol_vel and e_G < tol_vel and e_du < tol_vel
+    assert drift < 1e-5
