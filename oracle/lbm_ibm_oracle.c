@@ -68,7 +68,11 @@ static int opposite(int i) {
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_BOUNCEBACK = 1 };
 enum { ORC_FORCE_GUO = 0, ORC_FORCE_SHIFT = 1 };
-enum { ORC_IBM_INNER_UNWEIGHTED = 1 };
+enum {
+  ORC_IBM_INNER_UNWEIGHTED = 1,
+  ORC_IBM_STOP_RESIDUAL = 2, /* stop once sum s|g|^2 <= eps^2 sum s|u_b|^2 */
+  ORC_IBM_WARM_START = 4     /* learned warm start after the first sweep  */
+};
 enum { ORC_OK = 0, ORC_ERR_DOMAIN = -5 };
 
 typedef struct {
@@ -403,30 +407,152 @@ void orc_kinematics(int64_t npts, const double* rest, const int64_t* body_off,
 }
 
 /* ---------------------------------------------------------------------------
- * Multi-direct forcing (§3; Algorithms 1 and 2), n_iter sweeps:
+ * Learned warm start, inputs (not part of the paper).
+ *
+ * orc_neighbours: N(k) for every point k (idx == NULL) or for the listed
+ * points: up to 16 other points of k's body, nearest first, with squared
+ * rest-frame distance ((dx^2 + dy^2) + dz^2) < 4, ties by index; -1 pads.
+ * Brute force over the body.  nbr: [n][16] (rows of unlisted points are left
+ * untouched).
+ * ------------------------------------------------------------------------- */
+#define NNBR 16
+void orc_neighbours(int64_t npts, const double* rest, const int64_t* body_off,
+                    int32_t nbodies, const int64_t* idx, int64_t n_idx, int32_t* nbr) {
+  int32_t* body = (int32_t*)malloc(sizeof(int32_t) * (npts > 0 ? npts : 1));
+  for (int32_t b = 0; b < nbodies; ++b)
+    for (int64_t k = body_off[b]; k < body_off[b + 1]; ++k) body[k] = b;
+  const int64_t m = idx ? n_idx : npts;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t j = 0; j < m; ++j) {
+    const int64_t k = idx ? idx[j] : j;
+    double bd[NNBR];
+    int64_t bi[NNBR];
+    int cnt = 0;
+    const int32_t b = body[k];
+    for (int64_t q = body_off[b]; q < body_off[b + 1]; ++q) {
+      if (q == k) continue;
+      const double dx = rest[3 * q] - rest[3 * k];
+      const double dy = rest[3 * q + 1] - rest[3 * k + 1];
+      const double dz = rest[3 * q + 2] - rest[3 * k + 2];
+      const double d2 = (dx * dx + dy * dy) + dz * dz;
+      if (!(d2 < 4.0)) continue;
+      /* keep the 16 smallest (d2, q): insert q in order if it beats the last */
+      int pos = cnt;
+      while (pos > 0 && (d2 < bd[pos - 1] || (d2 == bd[pos - 1] && q < bi[pos - 1]))) --pos;
+      if (pos >= NNBR) continue;
+      const int last = cnt < NNBR ? cnt : NNBR - 1;
+      for (int i = last; i > pos; --i) {
+        bd[i] = bd[i - 1];
+        bi[i] = bi[i - 1];
+      }
+      bd[pos] = d2;
+      bi[pos] = q;
+      if (cnt < NNBR) ++cnt;
+    }
+    for (int i = 0; i < NNBR; ++i) nbr[NNBR * k + i] = i < cnt ? (int32_t)bi[i] : -1;
+  }
+  free(body);
+}
+
+/* Reference speed of each body: |omega| max_k |r_k| over its rest points,
+ * or 1 when that is zero (a body at rest). */
+void orc_vref(const double* rest, const int64_t* body_off, int32_t nbodies,
+              const orc_body* bodies, double* vref) {
+  for (int32_t b = 0; b < nbodies; ++b) {
+    double rmax = 0.0;
+    for (int64_t k = body_off[b]; k < body_off[b + 1]; ++k) {
+      const double* r = rest + 3 * k;
+      const double len = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+      if (len > rmax) rmax = len;
+    }
+    const double v = fabs(bodies[b].omega) * rmax;
+    vref[b] = v > 0.0 ? v : 1.0;
+  }
+}
+
+/* Features of every point: g0 (3), u_b (3), the mean and the component-wise
+ * maximum of g0 over N(k) (3 + 3; zeros when N(k) is empty), each divided
+ * by v_pt[k], the reference speed of k's body.  feat: [n][12]. */
+void orc_features(int64_t npts, const double* g0, const double* ub, const int32_t* nbr,
+                  const double* v_pt, double* feat) {
+  for (int64_t k = 0; k < npts; ++k) {
+    double* x = feat + 12 * k;
+    const double v = v_pt[k];
+    double mean[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+    int cnt = 0;
+    for (int i = 0; i < NNBR; ++i) {
+      const int32_t q = nbr[NNBR * k + i];
+      if (q < 0) break;
+      for (int a = 0; a < 3; ++a) {
+        const double gq = g0[3 * q + a];
+        mean[a] += gq;
+        mx[a] = cnt == 0 ? gq : (gq > mx[a] ? gq : mx[a]);
+      }
+      ++cnt;
+    }
+    for (int a = 0; a < 3; ++a) {
+      x[a] = g0[3 * k + a] / v;
+      x[3 + a] = ub[3 * k + a] / v;
+      x[6 + a] = cnt ? mean[a] / cnt / v : 0.0;
+      x[9 + a] = cnt ? mx[a] / v : 0.0;
+    }
+  }
+}
+
+void orc_mlp_forward(const double* theta, int64_t n, const double* x, double* y);
+
+/* ---------------------------------------------------------------------------
+ * Multi-direct forcing (§3; Algorithms 1 and 2), up to n_iter sweeps:
  *   U_0 = U;  du = 0
  *   for it in 0 .. n_iter-1:
  *     u_it(k) = interpolation of U_it at x(k)
  *     g_it(k) = u_b(k) - u_it(k)
  *     du(k)  += s(k) g_it(k)
- *     if it < n_iter-1:  U_{it+1} = U_it + spread of s(k) g_it(k)
+ *     stop after this sweep if it = n_iter-1, or, with ORC_IBM_STOP_RESIDUAL,
+ *       if sum_k s|g_it|^2 <= eps^2 sum_k s|u_b|^2 (§3 remarks that the
+ *       sweeps may continue until the deficit is small)
+ *     otherwise U_{it+1} = U_it + spread of s(k) g_it(k)
  *                        (or of g_it(k) with ORC_IBM_INNER_UNWEIGHTED)
  *   G = spread of du(k)
+ * With ORC_IBM_WARM_START (an extension, not in the paper) the first sweep
+ * that does not stop replaces its correction: du(k) = s(k) v(k) y(k), with
+ * y = MLP(theta; features of k) and v(k) the reference speed of k's body,
+ * and U_1 = U_0 + spread of du.
  * U0 is not modified.  resid[it] = sum_k s(k) |g_it(k)|^2.
- * G_out: [3][ncell] overwritten.  du_out, g_out: [n][3] (nullable).
+ * G_out: [3][ncell] overwritten.  du_out, g_out: [n][3] (nullable);
+ * feat_out [n][12] (nullable, needs nbr and v_pt); n_sweeps (nullable).
  * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_iter;
+  int32_t flags;       /* ORC_IBM_* */
+  double eps;          /* residual threshold of ORC_IBM_STOP_RESIDUAL */
+  const double* theta; /* MLP parameters (ORC_IBM_WARM_START) */
+  const int32_t* nbr;  /* [n][16] neighbour lists (features) */
+  const double* v_pt;  /* [n] reference speed of each point's body */
+} orc_ibm_opts;
+
 static int ibm_core(const orc_params* p, int64_t npts, const double* x,
-                    const double* ub, const double* s, double* U, int32_t n_iter,
-                    int32_t flags, double* G_out, double* du_out, double* g_out,
-                    double* resid) {
+                    const double* ub, const double* s, double* U, const orc_ibm_opts* o,
+                    double* G_out, double* du_out, double* g_out, double* resid,
+                    double* feat_out, int32_t* n_sweeps) {
   const int64_t n = ncells(p);
   const int64_t m = npts > 0 ? npts : 1;
+  const int warm = (o->flags & ORC_IBM_WARM_START) != 0;
+  const int want_feat = warm || feat_out;
   double* u = (double*)malloc(sizeof(double) * 3 * m);
   double* g = (double*)malloc(sizeof(double) * 3 * m);
   double* v = (double*)malloc(sizeof(double) * 3 * m);
   double* du = (double*)calloc(3 * m, sizeof(double));
+  double* feat = want_feat ? (double*)malloc(sizeof(double) * 12 * m) : NULL;
+  double* y = warm ? (double*)malloc(sizeof(double) * 3 * m) : NULL;
+  double thr = 0.0;
+  for (int64_t k = 0; k < npts; ++k)
+    thr += s[k] * (ub[3 * k] * ub[3 * k] + ub[3 * k + 1] * ub[3 * k + 1] +
+                   ub[3 * k + 2] * ub[3 * k + 2]);
+  thr *= o->eps * o->eps;
   int err = ORC_OK;
-  for (int it = 0; it < n_iter && err == ORC_OK; ++it) {
+  int it = 0;
+  for (it = 0; it < o->n_iter; ++it) {
     err = orc_interpolate(p, npts, x, U, u);
     if (err != ORC_OK) break;
     double r = 0.0;
@@ -440,14 +566,23 @@ static int ibm_core(const orc_params* p, int64_t npts, const double* x,
       r += s[k] * sq;
     }
     if (resid) resid[it] = r;
-    if (it < n_iter - 1) {
+    if (it == 0 && want_feat) orc_features(npts, g, ub, o->nbr, o->v_pt, feat);
+    const int stop = it == o->n_iter - 1 || ((o->flags & ORC_IBM_STOP_RESIDUAL) && r <= thr);
+    if (stop) break;
+    if (it == 0 && warm) {
+      orc_mlp_forward(o->theta, npts, feat, y);
+      for (int64_t k = 0; k < npts; ++k)
+        for (int a = 0; a < 3; ++a) du[3 * k + a] = s[k] * o->v_pt[k] * y[3 * k + a];
+      err = orc_spread(p, npts, x, du, U);
+    } else {
       for (int64_t k = 0; k < npts; ++k)
         for (int a = 0; a < 3; ++a)
-          v[3 * k + a] = (flags & ORC_IBM_INNER_UNWEIGHTED)
+          v[3 * k + a] = (o->flags & ORC_IBM_INNER_UNWEIGHTED)
                              ? g[3 * k + a]
                              : s[k] * g[3 * k + a];
       err = orc_spread(p, npts, x, v, U);
     }
+    if (err != ORC_OK) break;
   }
   if (err == ORC_OK) {
     memset(G_out, 0, sizeof(double) * 3 * n);
@@ -456,23 +591,27 @@ static int ibm_core(const orc_params* p, int64_t npts, const double* x,
   if (err == ORC_OK) {
     if (du_out) memcpy(du_out, du, sizeof(double) * 3 * npts);
     if (g_out) memcpy(g_out, g, sizeof(double) * 3 * npts);
+    if (feat_out) memcpy(feat_out, feat, sizeof(double) * 12 * npts);
+    if (n_sweeps) *n_sweeps = it < o->n_iter ? it + 1 : o->n_iter;
   }
   free(u);
   free(g);
   free(v);
   free(du);
+  free(feat);
+  free(y);
   return err;
 }
 
 int orc_ibm(const orc_params* p, int64_t npts, const double* x,
             const double* ub, const double* s, const double* U0,
-            int32_t n_iter, int32_t flags, double* G_out, double* du_out,
-            double* g_out, double* resid) {
+            const orc_ibm_opts* o, double* G_out, double* du_out,
+            double* g_out, double* resid, double* feat_out, int32_t* n_sweeps) {
   const int64_t n = ncells(p);
   double* U = (double*)malloc(sizeof(double) * 3 * n);
   memcpy(U, U0, sizeof(double) * 3 * n);
-  int err = ibm_core(p, npts, x, ub, s, U, n_iter, flags, G_out, du_out, g_out,
-                     resid);
+  int err = ibm_core(p, npts, x, ub, s, U, o, G_out, du_out, g_out, resid,
+                     feat_out, n_sweeps);
   free(U);
   return err;
 }
@@ -497,6 +636,8 @@ typedef struct {
   int32_t flags;
   int32_t pad_;
   const orc_body* bodies;
+  double eps;           /* ORC_IBM_STOP_RESIDUAL threshold */
+  const double* theta;  /* ORC_IBM_WARM_START parameters */
 } orc_points;
 
 typedef struct {
@@ -507,11 +648,15 @@ typedef struct {
   double* g;     /* [n][3] */
   double* du;    /* [n][3] */
   double* resid; /* [n_iter] */
+  double* feat;  /* [n][12] features of the first sweep */
+  int32_t* n_sweeps;
 } orc_step_out;
 
 /* Buffers reused across the steps of one run. */
 typedef struct {
   double *fn, *rho, *U, *G, *x, *ub;
+  int32_t* nbr;  /* neighbour lists, found once per run when needed */
+  double* v_pt;
 } orc_ws;
 
 static void ws_alloc(orc_ws* w, int64_t n, int64_t m) {
@@ -522,6 +667,8 @@ static void ws_alloc(orc_ws* w, int64_t n, int64_t m) {
   w->G = (double*)malloc(sizeof(double) * 3 * n);
   w->x = (double*)malloc(sizeof(double) * 3 * m);
   w->ub = (double*)malloc(sizeof(double) * 3 * m);
+  w->nbr = NULL;
+  w->v_pt = NULL;
 }
 
 static void ws_free(orc_ws* w) {
@@ -531,6 +678,22 @@ static void ws_free(orc_ws* w) {
   free(w->G);
   free(w->x);
   free(w->ub);
+  free(w->nbr);
+  free(w->v_pt);
+}
+
+/* Neighbour lists and per-point reference speeds of the warm start. */
+static void ws_learned(orc_ws* w, const orc_points* pts) {
+  if (w->nbr) return;
+  const int64_t m = pts->npts > 0 ? pts->npts : 1;
+  w->nbr = (int32_t*)malloc(sizeof(int32_t) * NNBR * m);
+  w->v_pt = (double*)malloc(sizeof(double) * m);
+  double* vb = (double*)malloc(sizeof(double) * (pts->nbodies > 0 ? pts->nbodies : 1));
+  orc_neighbours(pts->npts, pts->rest, pts->body_off, pts->nbodies, NULL, 0, w->nbr);
+  orc_vref(pts->rest, pts->body_off, pts->nbodies, pts->bodies, vb);
+  for (int32_t b = 0; b < pts->nbodies; ++b)
+    for (int64_t k = pts->body_off[b]; k < pts->body_off[b + 1]; ++k) w->v_pt[k] = vb[b];
+  free(vb);
 }
 
 /* One step from f into w->fn (f is left unchanged). */
@@ -545,9 +708,19 @@ static int step_into(const orc_params* p, const double* f, const orc_points* pts
     orc_moments(p, f, w->rho, w->U);
     orc_kinematics(m, pts->rest, pts->body_off, pts->nbodies, pts->bodies,
                    step, w->x, w->ub);
-    err = ibm_core(p, m, w->x, w->ub, pts->area, w->U, pts->n_iter, pts->flags,
-                   w->G, out ? out->du : NULL, out ? out->g : NULL,
-                   out ? out->resid : NULL);
+    const int learned = (pts->flags & ORC_IBM_WARM_START) || (out && out->feat);
+    if (learned) ws_learned(w, pts);
+    orc_ibm_opts o;
+    o.n_iter = pts->n_iter;
+    o.flags = pts->flags;
+    o.eps = pts->eps;
+    o.theta = pts->theta;
+    o.nbr = w->nbr;
+    o.v_pt = w->v_pt;
+    err = ibm_core(p, m, w->x, w->ub, pts->area, w->U, &o, w->G,
+                   out ? out->du : NULL, out ? out->g : NULL,
+                   out ? out->resid : NULL, out ? out->feat : NULL,
+                   out ? out->n_sweeps : NULL);
     if (out && out->x) memcpy(out->x, w->x, sizeof(double) * 3 * m);
     if (out && out->ub) memcpy(out->ub, w->ub, sizeof(double) * 3 * m);
     G = w->G;
@@ -574,9 +747,10 @@ int orc_step(const orc_params* p, double* f, const orc_points* pts,
 }
 
 /* n_steps full steps starting at time `step0`; sums_hist (nullable) gets
- * the sums before each step, [n_steps][4]. */
+ * the sums before each step, [n_steps][4]; sweeps_hist (nullable) the
+ * sweeps of each step's forcing, [n_steps]. */
 int orc_run(const orc_params* p, double* f, const orc_points* pts,
-            int64_t step0, int64_t n_steps, double* sums_hist) {
+            int64_t step0, int64_t n_steps, double* sums_hist, int32_t* sweeps_hist) {
   const int64_t n = ncells(p);
   orc_ws w;
   ws_alloc(&w, n, pts ? pts->npts : 0);
@@ -586,6 +760,7 @@ int orc_run(const orc_params* p, double* f, const orc_points* pts,
     orc_step_out o;
     memset(&o, 0, sizeof(o));
     o.sums = sums_hist ? sums_hist + 4 * s : NULL;
+    o.n_sweeps = sweeps_hist ? sweeps_hist + s : NULL;
     err = step_into(p, cur, pts, step0 + s, &o, &w);
     if (err == ORC_OK) { /* swap the state and the work lattice */
       double* t = w.fn;

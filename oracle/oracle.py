@@ -52,13 +52,19 @@ class Params(ct.Structure):
 class _Points(ct.Structure):
     _fields_ = [("npts", ct.c_int64), ("rest", ct.c_void_p), ("area", ct.c_void_p),
                 ("body_off", ct.c_void_p), ("nbodies", ct.c_int32), ("n_iter", ct.c_int32),
-                ("flags", ct.c_int32), ("pad_", ct.c_int32), ("bodies", ct.c_void_p)]
+                ("flags", ct.c_int32), ("pad_", ct.c_int32), ("bodies", ct.c_void_p),
+                ("eps", ct.c_double), ("theta", ct.c_void_p)]
+
+
+class _IbmOpts(ct.Structure):
+    _fields_ = [("n_iter", ct.c_int32), ("flags", ct.c_int32), ("eps", ct.c_double),
+                ("theta", ct.c_void_p), ("nbr", ct.c_void_p), ("v_pt", ct.c_void_p)]
 
 
 class _StepOut(ct.Structure):
     _fields_ = [("sums", ct.c_void_p), ("G", ct.c_void_p), ("x", ct.c_void_p),
                 ("ub", ct.c_void_p), ("g", ct.c_void_p), ("du", ct.c_void_p),
-                ("resid", ct.c_void_p)]
+                ("resid", ct.c_void_p), ("feat", ct.c_void_p), ("n_sweeps", ct.c_void_p)]
 
 
 def _load():
@@ -81,11 +87,15 @@ def _load():
             lib.orc_spread.argtypes = [P, i64, vp, vp, vp]
             lib.orc_spread.restype = ct.c_int
             lib.orc_kinematics.argtypes = [i64, vp, vp, i32, vp, i64, vp, vp]
-            lib.orc_ibm.argtypes = [P, i64, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp]
+            lib.orc_ibm.argtypes = [P, i64, vp, vp, vp, vp, ct.POINTER(_IbmOpts), vp, vp, vp,
+                                    vp, vp, vp]
             lib.orc_ibm.restype = ct.c_int
             lib.orc_step.argtypes = [P, vp, ct.POINTER(_Points), i64, ct.POINTER(_StepOut)]
             lib.orc_step.restype = ct.c_int
-            lib.orc_run.argtypes = [P, vp, ct.POINTER(_Points), i64, i64, vp]
+            lib.orc_run.argtypes = [P, vp, ct.POINTER(_Points), i64, i64, vp, vp]
+            lib.orc_neighbours.argtypes = [i64, vp, vp, i32, vp, i64, vp]
+            lib.orc_vref.argtypes = [vp, vp, i32, vp, vp]
+            lib.orc_features.argtypes = [i64, vp, vp, vp, vp, vp]
             lib.orc_run.restype = ct.c_int
             lib.orc_mlp_nparam.restype = ct.c_int32
             lib.orc_mlp_forward.argtypes = [vp, i64, vp, vp]
@@ -224,44 +234,120 @@ def kinematics(rest, body_off, bodies, step):
 
 def ibm(p, x, ub, s, U0, n_iter=5, flags=0):
     """Returns G [3,nz,ny,nx], du [n,3], g_last [n,3], resid [n_iter]."""
+    r = ibm_ex(p, x, ub, s, U0, n_iter=n_iter, flags=flags)
+    return r["G"], r["du"], r["g"], r["resid"]
+
+
+def ibm_ex(p, x, ub, s, U0, n_iter=5, flags=0, eps=0.0, theta=None, nbr=None, v_pt=None,
+           features=False):
+    """Forcing with every option: residual stop (flags 2, eps), warm start
+    (flags 4, theta, nbr [n,16] int32, v_pt [n]); features=True also returns
+    the features of the first sweep (needs nbr and v_pt).  Returns a dict
+    with G, du, g (last sweep), resid [n_sweeps], n_sweeps, feat."""
     lib = _load()
     x = _f64(x).reshape(-1, 3)
     ub = _f64(ub).reshape(-1, 3)
     s = _f64(s).reshape(-1)
     U0 = _f64(U0)
     n = x.shape[0]
-    G = np.zeros((3,) + grid_shape(p))
-    du = np.zeros((n, 3))
-    g = np.zeros((n, 3))
+    o = _IbmOpts()
+    o.n_iter, o.flags, o.eps = int(n_iter), int(flags), float(eps)
+    keep = []
+    if theta is not None:
+        keep.append(_f64(theta))
+        o.theta = _ptr(keep[-1])
+    if nbr is not None:
+        keep.append(np.ascontiguousarray(nbr, dtype=np.int32))
+        o.nbr = _ptr(keep[-1])
+    if v_pt is not None:
+        keep.append(_f64(v_pt))
+        o.v_pt = _ptr(keep[-1])
+    res = {"G": np.zeros((3,) + grid_shape(p)), "du": np.zeros((n, 3)), "g": np.zeros((n, 3))}
     resid = np.zeros(max(int(n_iter), 1))
-    _check(lib.orc_ibm(ct.byref(p), n, _ptr(x), _ptr(ub), _ptr(s), _ptr(U0),
-                       int(n_iter), int(flags), _ptr(G), _ptr(du), _ptr(g), _ptr(resid)))
-    return G, du, g, resid[:n_iter]
+    ns = np.zeros(1, dtype=np.int32)
+    feat = np.zeros((n, 12)) if features else None
+    _check(lib.orc_ibm(ct.byref(p), n, _ptr(x), _ptr(ub), _ptr(s), _ptr(U0), ct.byref(o),
+                       _ptr(res["G"]), _ptr(res["du"]), _ptr(res["g"]), _ptr(resid),
+                       _ptr(feat), _ptr(ns)))
+    res["n_sweeps"] = int(ns[0])
+    res["resid"] = resid[:res["n_sweeps"]]
+    res["feat"] = feat
+    return res
+
+
+def neighbours(rest, body_off, idx=None):
+    """N(k) of the warm-start features: [n,16] int32 (-1 pads); with idx,
+    only the listed rows are computed (the others are -2)."""
+    lib = _load()
+    rest = _f64(rest).reshape(-1, 3)
+    body_off = np.ascontiguousarray(body_off, dtype=np.int64)
+    nbr = np.full((rest.shape[0], 16), -2, dtype=np.int32)
+    if idx is None:
+        lib.orc_neighbours(rest.shape[0], _ptr(rest), _ptr(body_off), body_off.size - 1, None, 0,
+                           _ptr(nbr))
+    else:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        lib.orc_neighbours(rest.shape[0], _ptr(rest), _ptr(body_off), body_off.size - 1,
+                           _ptr(idx), idx.size, _ptr(nbr))
+    return nbr
+
+
+def vref(rest, body_off, bodies):
+    """Reference speed of each body [nb]."""
+    lib = _load()
+    rest = _f64(rest).reshape(-1, 3)
+    body_off = np.ascontiguousarray(body_off, dtype=np.int64)
+    bodies = _f64(bodies).reshape(-1, 8)
+    out = np.zeros(bodies.shape[0])
+    lib.orc_vref(_ptr(rest), _ptr(body_off), bodies.shape[0], _ptr(bodies), _ptr(out))
+    return out
+
+
+def vref_points(rest, body_off, bodies):
+    """Reference speed of each point's body [n]."""
+    vb = vref(rest, body_off, bodies)
+    body_off = np.asarray(body_off, dtype=np.int64)
+    return np.repeat(vb, np.diff(body_off))
+
+
+def features(g0, ub, nbr, v_pt):
+    """Warm-start features [n,12] from the first deficit g0 and u_b [n,3]."""
+    lib = _load()
+    g0 = _f64(g0).reshape(-1, 3)
+    ub = _f64(ub).reshape(-1, 3)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    v_pt = _f64(v_pt).reshape(-1)
+    out = np.zeros((g0.shape[0], 12))
+    lib.orc_features(g0.shape[0], _ptr(g0), _ptr(ub), _ptr(nbr), _ptr(v_pt), _ptr(out))
+    return out
 
 
 class Points:
     """Lagrangian surface description handed to the step functions."""
 
-    def __init__(self, rest, area, body_off, bodies, n_iter=5, flags=0):
+    def __init__(self, rest, area, body_off, bodies, n_iter=5, flags=0, eps=0.0, theta=None):
         self.rest = _f64(rest).reshape(-1, 3)
         self.area = _f64(area).reshape(-1)
         self.body_off = np.ascontiguousarray(body_off, dtype=np.int64)
         self.bodies = _f64(bodies).reshape(-1, 8)
         self.n_iter = int(n_iter)
         self.flags = int(flags)
+        self.eps = float(eps)
+        self.theta = None if theta is None else _f64(theta).reshape(-1)
         self.c = _Points(self.rest.shape[0], _ptr(self.rest), _ptr(self.area),
                          _ptr(self.body_off), self.bodies.shape[0], self.n_iter,
-                         self.flags, 0, _ptr(self.bodies))
+                         self.flags, 0, _ptr(self.bodies), self.eps, _ptr(self.theta))
 
     @property
     def n(self):
         return self.rest.shape[0]
 
 
-def step(p, f, pts=None, step_index=0, outputs=True):
+def step(p, f, pts=None, step_index=0, outputs=True, features=False):
     """One full time step in place on f (float64 [19,nz,ny,nx], C-contiguous).
 
-    Returns a dict with sums (before the step), G, x, ub, g, du, resid."""
+    Returns a dict with sums (before the step), G, x, ub, g, du, resid
+    [n_sweeps], n_sweeps, and with features=True feat [n,12]."""
     lib = _load()
     assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"]
     o = _StepOut()
@@ -276,19 +362,29 @@ def step(p, f, pts=None, step_index=0, outputs=True):
             res["resid"] = np.zeros(max(pts.n_iter, 1))
             o.x, o.ub, o.g, o.du = (_ptr(res[k]) for k in ("x", "ub", "g", "du"))
             o.resid = _ptr(res["resid"])
+            res["n_sweeps"] = np.zeros(1, dtype=np.int32)
+            o.n_sweeps = _ptr(res["n_sweeps"])
+            if features:
+                res["feat"] = np.zeros((pts.n, 12))
+                o.feat = _ptr(res["feat"])
     pc = ct.byref(pts.c) if pts is not None else None
     _check(lib.orc_step(ct.byref(p), _ptr(f), pc, int(step_index), ct.byref(o)))
+    if "n_sweeps" in res:
+        res["n_sweeps"] = int(res["n_sweeps"][0])
+        res["resid"] = res["resid"][:res["n_sweeps"]]
     return res
 
 
-def run(p, f, pts=None, step0=0, n_steps=1):
-    """n_steps steps in place on f; returns the sums before each step."""
+def run(p, f, pts=None, step0=0, n_steps=1, sweeps=False):
+    """n_steps steps in place on f; returns the sums before each step (and,
+    with sweeps=True, also the sweeps of each step's forcing)."""
     lib = _load()
     assert f.dtype == np.float64 and f.flags["C_CONTIGUOUS"]
     hist = np.zeros((int(n_steps), 4))
+    sw = np.zeros(int(n_steps), dtype=np.int32)
     pc = ct.byref(pts.c) if pts is not None else None
-    _check(lib.orc_run(ct.byref(p), _ptr(f), pc, int(step0), int(n_steps), _ptr(hist)))
-    return hist
+    _check(lib.orc_run(ct.byref(p), _ptr(f), pc, int(step0), int(n_steps), _ptr(hist), _ptr(sw)))
+    return (hist, sw) if sweeps else hist
 
 
 # ------------------------------------------------------------ learned warm start
