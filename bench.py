@@ -11,8 +11,10 @@ with 64 rotating propellers (h 0.41, about 1.6M Lagrangian points, seed 0),
 
 Prints ONE JSON line: MLUPS including the forcing (value), point-updates/s,
 the fraction of the HBM roofline, the stream-collide kernel's roofline entry
-(bytes per launch / measured launch time) and the FP64 oracle timed on the
-host cores on a bounded sample of the same workload.
+(bytes per launch / measured launch time), the FP64 oracle timed on the
+host cores on a bounded sample of the same workload, and the learned
+warm start against the plain sweep at an equal residual threshold on the
+single-propeller case (network trained on the GPU in the same run).
 """
 from __future__ import annotations
 
@@ -100,6 +102,91 @@ def copy_bandwidth(torch, nbytes, reps=5):
             "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
+def learned_leg(torch, L, W, n_pairs_steps=300, epochs=10, eval_steps=40, warm=5):
+    """C4: the warm-start network trained on the GPU from plain runs of the
+    single-propeller geometry with other seeds (1-4), then the canonical
+    single-propeller case (seed 0, held out) run three ways: plain with a
+    fixed 5 sweeps, plain to the residual threshold, and warm-started to the
+    same threshold.  The threshold is the median relative residual that the
+    plain method reaches at its 5th sweep on the held-out case."""
+    import numpy as np
+
+    from paper_1904_02108_amd import learned as LN
+    t0 = time.perf_counter()
+    xs, ts, kept = [], [], []
+    for seed in (1, 2, 3, 4):
+        wl_s = W.config("c1", seed=seed)
+        x, t = LN.collect_pairs(wl_s, n_pairs_steps, n_iter=12, skip=5)
+        kept.append(int(x.shape[0]) // wl_s.n_points)
+        xs.append(x)
+        ts.append(t)
+    x = torch.cat(xs)
+    t = torch.cat(ts)
+    del xs, ts
+    perm = torch.randperm(x.shape[0], generator=torch.Generator().manual_seed(0)).to(x.device)
+    x, t = x[perm].contiguous(), t[perm].contiguous()
+    t_collect = time.perf_counter() - t0
+    net = LN.Network(W.mlp_init(5), max_batch=1024)
+    t0 = time.perf_counter()
+    losses = net.train(x, t, batch=1024, epochs=epochs, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    n_pairs = int(x.shape[0])
+    del x, t, perm
+    wl = W.config("c1")
+    sim = LN.surface_sim(wl, 0, 5)
+    hist = LN.residual_history(sim, 40)
+    eps = float(np.median([rr[4] for _, rr in hist[warm:]]))
+    sim.close()
+    variants = {}
+    theta = net.numpy()
+    if not np.isfinite(theta).all():
+        return {"error": "training diverged", "loss_per_epoch": [float(v) for v in losses],
+                "steps_kept_per_seed": kept}
+    for name, flags, n_iter, th in (("plain_5", 0, 5, None),
+                                    ("plain_eps", L.IBM_STOP_RESIDUAL, 12, None),
+                                    ("learned_eps", L.IBM_STOP_RESIDUAL | L.IBM_WARM_START, 12, theta)):
+        sim = LN.surface_sim(wl, flags, n_iter, eps if flags else 0.0, theta=th)
+        sim.step(warm)
+        h = LN.residual_history(sim, eval_steps)       # sweeps and residuals per step
+        sweeps = np.array([n for n, _ in h], dtype=np.float64)
+        final = np.array([rr[n - 1] for n, rr in h])
+        # timing: the same number of steps again, without per-step syncs
+        torch.cuda.synchronize()
+        L.lbm_set_timing(sim.ctx, 1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(eval_steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / eval_steps
+        tm = L.lbm_get_timing(sim.ctx)
+        L.lbm_set_timing(sim.ctx, 0)
+        variants[name] = {
+            "mean_sweeps": round(float(sweeps.mean()), 3),
+            "max_final_resid_rel": float(final.max()),
+            "median_final_resid_rel": float(np.median(final)),
+            "ms_per_step": round(ms, 4),
+            "ms_forcing": round(tm["ms_forcing"] / max(tm["n_forcing"], 1), 4),
+            "ms_fluid": round(tm["ms_fluid"] / max(tm["n_fluid"], 1), 4),
+            "MLUPS": round(wl.n_cells / (ms * 1e-3) / 1e6, 2),
+            "point_updates_per_s": round(wl.n_points / (ms * 1e-3), 1),
+        }
+        sim.close()
+    pe, le = variants["plain_eps"], variants["learned_eps"]
+    return {
+        "workload": "c1 (seed 0, held out); training pairs from c1 seeds 1-4",
+        "eps_resid_rel": eps,
+        "train_pairs": n_pairs, "steps_kept_per_seed": kept, "epochs": epochs, "loss_per_epoch": [float(v) for v in losses],
+        "s_collect": round(t_collect, 2), "s_train": round(t_train, 2),
+        "variants": variants,
+        "sweeps_saved": round(pe["mean_sweeps"] - le["mean_sweeps"], 3),
+        "forcing_speedup_vs_plain_eps": round(pe["ms_forcing"] / le["ms_forcing"], 3),
+        "forcing_speedup_vs_plain_5": round(variants["plain_5"]["ms_forcing"] / le["ms_forcing"], 3),
+        "step_speedup_vs_plain_eps": round(pe["ms_per_step"] / le["ms_per_step"], 3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +197,8 @@ def main():
     ap.add_argument("--forcing", default="guo", choices=["guo", "shift"])
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned warm-start comparison on the single-propeller case")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a plain streaming kernel (read + write of half the lattice bytes each)")
     args = ap.parse_args()
@@ -156,7 +245,7 @@ def main():
     achieved = bpc * wl.n_cells / (fluid_ms * 1e-3) / 1e9
     traffic = traffic_from_profiles(storage)
     out = {
-        "metric": "MLUPS incl. IBM + Lagrangian pt-updates/s, %HBM roofline",
+        "metric": "MLUPS incl. IBM + Lagrangian pt-updates/s, %HBM roofline, learned vs plain at equal residual",
         "value": round(mlups, 2),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -188,6 +277,9 @@ def main():
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if not args.no_learned:
+        out["learned"] = learned_leg(torch, L, W)
+        torch.cuda.empty_cache()
     if args.copy_calibration:
         out["copy_calibration"] = copy_bandwidth(torch, bpc * wl.n_cells // 2)
     if not args.no_cpu_baseline and args.cpu_steps > 0:

@@ -106,9 +106,49 @@ typedef struct {
 
 /* ibm_set_points flags */
 enum {
-  IBM_INNER_UNWEIGHTED = 1u  /* spread g(k) (not s(k) g(k)) inside the sweep,
+  IBM_INNER_UNWEIGHTED = 1u, /* spread g(k) (not s(k) g(k)) inside the sweep,
                                 the paper-literal reading of §3             */
+  IBM_STOP_RESIDUAL = 2u,    /* sweep until the relative boundary-velocity
+                                residual R_rel <= eps, at most n_iter sweeps
+                                (§3 notes the sweeps could run until the
+                                deficit is negligible); the sweep that meets
+                                the threshold applies its correction and
+                                spreads du into G, as the last fixed sweep
+                                does.  R_rel = sqrt(sum s|g|^2 / sum s|u_b|^2)
+                                of the deficit g of a sweep (tested as
+                                sum s|g|^2 <= eps^2 sum s|u_b|^2, so a body at
+                                rest converges).  Decided on the device: the
+                                launches of later sweeps return at once, with
+                                no host synchronisation.                     */
+  IBM_WARM_START = 4u,       /* learned warm start (not in the paper): before
+                                the first correction, an MLP set with
+                                ibm_set_mlp predicts du from the first deficit
+                                g0, u_b and the mean and component-wise max of
+                                g0 over the point's neighbours, all divided by
+                                the body's reference speed; the prediction is
+                                spread into U and the sweeps continue from it.
+                                Useful with IBM_STOP_RESIDUAL, valid alone;
+                                not with IBM_INNER_UNWEIGHTED.                */
+  IBM_KEEP_FEATURES = 8u     /* compute the features in every forcing so that
+                                ibm_log_pairs can export training pairs       */
 };
+
+/* Learned warm start: a per-point MLP 12 -> 64 -> 64 -> 64 -> 3 with SiLU
+ * after each hidden layer.  Flat FP32 parameter layout (row-major, out x in):
+ *   W1[64][12] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3].
+ * Features of point k (in this order, each divided by the reference speed
+ * v_ref of k's body = |omega| * max_j |r_j| over the body's rest points, or
+ * 1 for a body at rest): g0 (3), u_b (3), mean of g0 over N(k) (3),
+ * component-wise max of g0 over N(k) (3), zeros when N(k) is empty.
+ * N(k): up to 16 points of k's body nearest to k at Euclidean distance < 2,
+ * ordered by (distance, index).  Distances are those of the rest positions,
+ * computed in FP64 as ((dx^2 + dy^2) + dz^2) with every operation rounded,
+ * so N(k) is exact, fixed for a rigid body, and found once per surface.
+ * Output y: du = s(k) v_ref y, so the training target is du / (s v_ref)
+ * (0 where s = 0). */
+#define IBM_MLP_NPARAM 9347
+#define IBM_MLP_NFEAT 12
+#define IBM_MLP_NNBR 16
 
 #define LBM_MAX_ITER 64
 
@@ -174,10 +214,11 @@ const char* lbm_last_error(const lbm_ctx* ctx);
  * float [n]), body ranges body_off[0..nbodies] (host, body b owns points
  * body_off[b] .. body_off[b+1]-1, body_off[0] = 0, body_off[nbodies] = n),
  * bodies (host [nbodies]), n_iter sweeps per step (1..max_iter), flags
- * (IBM_*), eps (reserved, 0).  Host arrays are copied before return.
- * n = 0 removes the surface.  Returns LBM_ERR_DOMAIN if for some rotation
- * angle a support could leave a walled axis (bounding-sphere test: on a
- * bounce-back axis every point must keep 1 <= x < n - 2). */
+ * (IBM_*), eps (see below).  Host arrays are copied before return.
+ * n = 0 removes the surface.  eps: residual threshold for
+ * IBM_STOP_RESIDUAL (else must be 0).  Returns LBM_ERR_DOMAIN if for some
+ * rotation angle a support could leave a walled axis (bounding-sphere test:
+ * on a bounce-back axis every point must keep 1 <= x < n - 2). */
 lbm_status ibm_set_points(lbm_ctx* ctx, int64_t n, const float* rest_xyz, const float* area,
                           const int64_t* body_off, int32_t nbodies, const ibm_body* bodies,
                           int32_t n_iter, uint32_t flags, float eps);
@@ -199,6 +240,43 @@ lbm_status lbm_read_fields(lbm_ctx* ctx, uint32_t mask, const lbm_fields* dst);
  * (prescribed G, kept until the next write, only without points) and
  * LBM_F_STEP.  Other bits are rejected with LBM_ERR_ARG. */
 lbm_status lbm_write_fields(lbm_ctx* ctx, uint32_t mask, const lbm_fields* src);
+
+/* Learned warm start: sets the MLP parameters (host float [IBM_MLP_NPARAM],
+ * copied before return). */
+lbm_status ibm_set_mlp(lbm_ctx* ctx, const float* theta);
+
+/* Training pairs of the last forcing (after ibm_force_iterate or lbm_step)
+ * of a surface set with IBM_KEEP_FEATURES or IBM_WARM_START: features
+ * [n][12] (those of the first sweep) and the target du / (s v_ref) [n][3]
+ * of the final correction du, in the order given to ibm_set_points, into
+ * caller device memory (enqueued on the context's stream).  LBM_ERR_STATE
+ * without such a forcing. */
+lbm_status ibm_log_pairs(lbm_ctx* ctx, float* features, float* targets);
+
+/* Statistics of the last forcing: sweeps run, sum s, sum s |u_b|^2 and the
+ * residual sum s |g|^2 of each sweep (synchronises). */
+lbm_status ibm_last_stats(lbm_ctx* ctx, ibm_stats* stats);
+
+/* Stateless MLP kernels on caller device memory, enqueued on `stream`:
+ *   mlp_forward:   y[n][3] = MLP(theta; x[n][12]);
+ *   mlp_loss_grad: loss = (1 / 3n) sum (y - t)^2 into loss_out (device
+ *                  double[1]) and its gradient into grad (device float
+ *                  [IBM_MLP_NPARAM]);
+ *   mlp_train:     n_epochs passes of Adam (beta1 0.9, beta2 0.999, eps 1e-8)
+ *                  over mini-batches of `batch` consecutive pairs, on theta in
+ *                  place; m, v: device float [IBM_MLP_NPARAM] Adam moments
+ *                  (zero them before the first call), *step_t: Adam step
+ *                  count (host, in/out); loss_per_epoch (host, nullable,
+ *                  [n_epochs]): mean batch loss of each epoch (synchronises).
+ * workspace: device memory of mlp_workspace_size(batch) bytes. */
+size_t mlp_workspace_size(int64_t batch);
+lbm_status mlp_forward(const float* theta, int64_t n, const float* x, float* y,
+                       void* workspace, void* stream);
+lbm_status mlp_loss_grad(const float* theta, int64_t n, const float* x, const float* t,
+                         float* grad, double* loss_out, void* workspace, void* stream);
+lbm_status mlp_train(float* theta, float* m, float* v, int64_t* step_t, int64_t n,
+                     const float* x, const float* t, int64_t batch, int32_t n_epochs,
+                     double lr, double* loss_per_epoch, void* workspace, void* stream);
 
 /* Optional per-phase timing with HIP events on the context's stream.
  * lbm_get_timing returns {ms forcing, ms stream-collide, forcing calls,

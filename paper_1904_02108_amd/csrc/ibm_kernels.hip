@@ -412,10 +412,16 @@ __device__ __forceinline__ void peskin4(float r, float w[4]) {
 }
 
 // One sweep of the multi-direct forcing for the points of one owner tile
-// (§3; Algorithms 1 and 2):
-//   u = sum_taps U W, g = u_b - u, du = (first ? 0 : du) + s g       (Alg. 1)
-//   v = s g (inner sweep), g (paper-literal inner sweep), du (last sweep)
-//   box(X) = sum_k v(k) W_k(X) over the tile's points                (Alg. 2)
+// (§3; Algorithms 1 and 2), in parts chosen by the mode bits:
+//   SW_INTERP:  u = sum_taps U W, g = u_b - u, du = (first ? 0 : du) + s g
+//                                                                   (Alg. 1)
+//   SW_SPREAD_G / SW_SPREAD_DU: the spread vector
+//               v = s g (inner sweep), g (SW_UNWEIGHTED: paper-literal inner
+//               sweep) or du (last sweep, or a predicted warm start), and
+//               box(X) = sum_k v(k) W_k(X) over the tile's points     (Alg. 2)
+// With neither spread bit only the interpolation runs; with SW_INTERP clear
+// only the spread.  A nonzero *gate (the forcing has converged) makes the
+// whole launch a no-op.  g_orig (nullable) receives g in the caller's order.
 // U is staged over the 11^3 box [o-1, o+10)^3 that holds every tap of the
 // tile's points (coordinates wrapped on periodic axes).  The box sum is
 // accumulated in LDS in 32-bit fixed point with the unit B / 2^30, where
@@ -424,13 +430,20 @@ __device__ __forceinline__ void peskin4(float r, float w[4]) {
 // independent of the order of the atomics.  The box is stored as FP32 in
 // the tile's slot of boxbuf.  FP64 partial of s |g|^2 per workgroup.
 constexpr float FIX_ONE = 1073741824.0f;  // 2^30
+enum : int {
+  SW_INTERP = 1,
+  SW_FIRST = 2,
+  SW_SPREAD_G = 4,
+  SW_SPREAD_DU = 8,
+  SW_UNWEIGHTED = 16,
+};
 __global__ __launch_bounds__(WG) void k_sweep_tiles(
     const uint32_t* __restrict__ own_tiles, const uint32_t* __restrict__ meta,
     const uint32_t* __restrict__ start_own, const int4* __restrict__ sp_base,
     const float4* __restrict__ sp_frac, const float4* __restrict__ sp_ub,
     float4* __restrict__ sp_g, float4* __restrict__ sp_du, const float* __restrict__ U,
-    float* __restrict__ boxbuf, PointGeom pg, int first, int last, int inner_weighted,
-    double* __restrict__ part_res) {
+    float* __restrict__ boxbuf, PointGeom pg, int mode, double* __restrict__ part_res,
+    const uint32_t* __restrict__ gate, float4* __restrict__ g_orig) {
   // U of the box during the interpolation, then (same storage) the integer
   // accumulator of the spread
   __shared__ float sU[3][BOX3];
@@ -438,16 +451,20 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
   __shared__ float fred[WG / 64];
   __shared__ double dred[WG / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (gate && *gate) return;  // the forcing has already converged
+  const bool interp = mode & SW_INTERP;
+  const bool spread_g = mode & SW_SPREAD_G, spread_du = mode & SW_SPREAD_DU;
+  const bool inner_weighted = !(mode & SW_UNWEIGHTED);
   const int64_t e = list_entry(meta[0]);
   if (e < 0) {  // idle workgroup: empty residual partial
-    if (threadIdx.x == 0) part_res[blockIdx.x] = 0.0;
+    if (interp && threadIdx.x == 0) part_res[blockIdx.x] = 0.0;
     return;
   }
   const uint32_t t = own_tiles[e];
   int o[3];
   tile_origin(pg, t, o);
 #pragma unroll 2
-  for (int i = threadIdx.x; i < BOX3; i += WG) {
+  for (int i = threadIdx.x; interp && i < BOX3; i += WG) {
     const int bx = i % BOX, by = (i / BOX) % BOX, bz = i / (BOX * BOX);
     const int cx = tap_coord(o[0] - 1 + bx, pg.n[0], pg.bc[0]);
     const int cy = tap_coord(o[1] - 1 + by, pg.n[1], pg.bc[1]);
@@ -459,10 +476,17 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
   }
   __syncthreads();
   const uint32_t p0 = start_own[t], p1 = start_own[t + 1];
-  // pass 1: interpolation, deficit, correction
+  // pass 1: interpolation, deficit, correction (or, spreading only, the
+  // bound of the spread vector)
   float bsum = 0.0f;
   double res = 0.0;
-  for (uint32_t k = p0 + threadIdx.x; k < p1; k += WG) {
+  for (uint32_t k = p0 + threadIdx.x; !interp && k < p1; k += WG) {
+    const float4 fr = sp_frac[k];
+    const float4 v = spread_du ? sp_du[k] : sp_g[k];
+    const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
+    bsum += vs * fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
+  }
+  for (uint32_t k = p0 + threadIdx.x; interp && k < p1; k += WG) {
     const int4 b = sp_base[k];
     const float4 fr = sp_frac[k];
     float wx[4], wy[4], wz[4];
@@ -490,17 +514,30 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
     }
     const float4 ub = sp_ub[k];
     const float g0 = ub.x - u0, g1 = ub.y - u1, g2 = ub.z - u2;
-    float4 du = first ? make_float4(0.f, 0.f, 0.f, 0.f) : sp_du[k];
+    float4 du = (mode & SW_FIRST) ? make_float4(0.f, 0.f, 0.f, 0.f) : sp_du[k];
     du.x += fr.w * g0;
     du.y += fr.w * g1;
     du.z += fr.w * g2;
     du.w = 0.0f;
     sp_g[k] = make_float4(g0, g1, g2, 0.0f);
     sp_du[k] = du;
+    if (g_orig) g_orig[b.w] = make_float4(g0, g1, g2, 0.0f);
     res += (double)fr.w * ((double)g0 * g0 + (double)g1 * g1 + (double)g2 * g2);
-    const float vs = last ? 1.0f : (inner_weighted ? fr.w : 1.0f);
-    const float v0 = last ? du.x : vs * g0, v1 = last ? du.y : vs * g1, v2 = last ? du.z : vs * g2;
+    const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
+    const float v0 = spread_du ? du.x : vs * g0, v1 = spread_du ? du.y : vs * g1,
+                v2 = spread_du ? du.z : vs * g2;
     bsum += fmaxf(fabsf(v0), fmaxf(fabsf(v1), fabsf(v2)));
+  }
+  if (!spread_g && !spread_du) {  // interpolation only: the residual partial
+    const double rv = wave_sum(res);
+    if (lane == 0) dred[wave] = rv;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sres = 0.0;
+      for (int w = 0; w < WG / 64; ++w) sres += dred[w];
+      part_res[blockIdx.x] = sres;
+    }
+    return;
   }
   // block sums: bound B (FP32) and residual (FP64)
 #pragma unroll
@@ -515,7 +552,7 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
 #pragma unroll
   for (int w = 0; w < WG / 64; ++w) B += fred[w];
   B *= 0.125f;
-  if (threadIdx.x == 0) {
+  if (interp && threadIdx.x == 0) {
     double sres = 0.0;
     for (int w = 0; w < WG / 64; ++w) sres += dred[w];
     part_res[blockIdx.x] = sres;
@@ -540,7 +577,7 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
     const int4 b = sp_base[k];
     const float4 fr = sp_frac[k];
     float v0, v1, v2;
-    if (last) {
+    if (spread_du) {
       const float4 du = sp_du[k];
       v0 = du.x * scale;
       v1 = du.y * scale;
@@ -614,9 +651,11 @@ constexpr int MERGE_WG = 256;
 __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
     const uint32_t* __restrict__ touch_tiles, const uint32_t* __restrict__ meta,
     const int32_t* __restrict__ own_slot, const float* __restrict__ boxbuf,
-    const uint8_t* __restrict__ bflag, float* __restrict__ target, PointGeom pg, int mode) {
+    const uint8_t* __restrict__ bflag, float* __restrict__ target, PointGeom pg, int mode,
+    const uint32_t* __restrict__ gate) {
   __shared__ int16_t ct[3][TILE][MAXCOV], cb[3][TILE][MAXCOV];
   __shared__ int cn[3][TILE];
+  if (gate && *gate) return;  // the forcing has already converged
   const int64_t e = list_entry(meta[1]);
   if (e < 0) return;
   const uint32_t t = touch_tiles[e];
@@ -734,6 +773,50 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_reduce_rows(const double* __restr
   }
 }
 
+// Residual-stopped forcing (ctl: [0] converged flag, [1] sweeps run).
+// k_resid_threshold: thr = eps^2 sum_k s |u_b|^2 (FP64, fixed order) and a
+// cleared control block.  k_resid_check after sweep `it`: unless already
+// converged, R = sum_k s |g|^2 of the sweep is compared with thr; R <= thr,
+// or the last allowed sweep, ends the forcing.  Comparing squared sums keeps
+// a body at rest (both sums zero) converged without a division.
+__global__ __launch_bounds__(LBM_BLOCK) void k_resid_threshold(const double* __restrict__ part_sub2,
+                                                               int64_t nblk, double eps2,
+                                                               double* __restrict__ thr,
+                                                               uint32_t* __restrict__ ctl) {
+  double s = 0.0;
+  for (int64_t b = threadIdx.x; b < nblk; b += LBM_BLOCK) s += part_sub2[b];
+  __shared__ double red[LBM_BLOCK / 64];
+  const double v = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < LBM_BLOCK / 64; ++w) t += red[w];
+    *thr = eps2 * t;
+    ctl[0] = 0u;
+    ctl[1] = 0u;
+  }
+}
+
+__global__ __launch_bounds__(LBM_BLOCK) void k_resid_check(const double* __restrict__ part_res,
+                                                           int64_t nblk, const double* __restrict__ thr,
+                                                           int it, int last, int use_thr,
+                                                           uint32_t* __restrict__ ctl) {
+  if (ctl[0]) return;
+  double s = 0.0;
+  for (int64_t b = threadIdx.x; b < nblk; b += LBM_BLOCK) s += part_res[b];
+  __shared__ double red[LBM_BLOCK / 64];
+  const double v = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < LBM_BLOCK / 64; ++w) t += red[w];
+    ctl[1] = (uint32_t)(it + 1);
+    if (last || (use_thr && t <= *thr)) ctl[0] = 1u;
+  }
+}
+
 // Sorted point arrays back to the caller's order.
 __global__ __launch_bounds__(LBM_BLOCK) void k_export_points(
     const int4* __restrict__ sp_base, const float4* __restrict__ sp_frac,
@@ -833,17 +916,72 @@ hipError_t launch_forcing(lbm_ctx* c) {
           (const float*)c->lat[c->cur], c->geom, pg, c->touch_tiles, c->meta, c->bflag, c->U);
   }
   LAUNCH_CHECK();
-  const int inner_weighted = (c->flags & IBM_INNER_UNWEIGHTED) ? 0 : 1;
-  for (int it = 0; it < c->n_iter; ++it) {
-    const int last = it == c->n_iter - 1;
-    k_sweep_tiles<<<lg, WG, 0, st>>>(c->own_tiles, c->meta, c->start_own, c->sp_base, c->sp_frac,
-                                     c->sp_ub, c->sp_g, c->sp_du, c->U, c->boxbuf, pg, it == 0,
-                                     last, inner_weighted, c->pt_partials + (2 + it) * rs);
-    LAUNCH_CHECK();
-    k_merge_tiles<<<lg, MERGE_WG, 0, st>>>(c->touch_tiles, c->meta, c->own_slot, c->boxbuf,
-                                        c->bflag, last ? c->G : c->U, pg, last ? 2 : 0);
-    LAUNCH_CHECK();
+  const int uw = (c->flags & IBM_INNER_UNWEIGHTED) ? SW_UNWEIGHTED : 0;
+  const bool feats = (c->flags & (IBM_WARM_START | IBM_KEEP_FEATURES)) != 0;
+  if (feats && !c->nbr_valid) {
+    hipError_t e = launch_neighbours(c);
+    if (e != hipSuccess) return e;
+    c->nbr_valid = true;
   }
+  auto sweep = [&](int it, int mode, const uint32_t* gate, float4* g_orig) {
+    k_sweep_tiles<<<lg, WG, 0, st>>>(c->own_tiles, c->meta, c->start_own, c->sp_base, c->sp_frac,
+                                     c->sp_ub, c->sp_g, c->sp_du, c->U, c->boxbuf, pg, mode | uw,
+                                     c->pt_partials + (2 + it) * rs, gate, g_orig);
+    return hipGetLastError();
+  };
+  auto merge = [&](bool final_, const uint32_t* gate) {
+    k_merge_tiles<<<lg, MERGE_WG, 0, st>>>(c->touch_tiles, c->meta, c->own_slot, c->boxbuf,
+                                        c->bflag, final_ ? c->G : c->U, pg, final_ ? 2 : 0, gate);
+    return hipGetLastError();
+  };
+#define TRY(x)                               \
+  do {                                       \
+    hipError_t e_ = (x);                     \
+    if (e_ != hipSuccess) return e_;         \
+  } while (0)
+  const int N = c->n_iter;
+  if (!(c->flags & (IBM_STOP_RESIDUAL | IBM_WARM_START))) {
+    // fixed number of sweeps; the last one spreads du into G
+    for (int it = 0; it < N; ++it) {
+      const bool last = it == N - 1;
+      const int mode = SW_INTERP | (it == 0 ? SW_FIRST : 0) | (last ? SW_SPREAD_DU : SW_SPREAD_G);
+      TRY(sweep(it, mode, nullptr, it == 0 && feats ? c->g0_orig : nullptr));
+      if (it == 0 && feats) TRY(launch_features_warm(c, false));
+      TRY(merge(last, nullptr));
+    }
+    return hipSuccess;
+  }
+  // Residual-stopped and/or warm-started: every launch of sweeps 1.. is gated
+  // by the device flag ctl[0], so the sequence runs without host round trips;
+  // the final spread of du into G always runs.
+  const bool warm = (c->flags & IBM_WARM_START) != 0;
+  const int use_thr = (c->flags & IBM_STOP_RESIDUAL) ? 1 : 0;
+  const int64_t na = (n + LBM_BLOCK - 1) / LBM_BLOCK;
+  k_resid_threshold<<<1, LBM_BLOCK, 0, st>>>(c->pt_partials + rs, na,
+                                             (double)c->eps * (double)c->eps, c->resid_thr, c->ctl);
+  TRY(hipGetLastError());
+  for (int it = 0; it < N; ++it) {
+    const bool last = it == N - 1;
+    const uint32_t* gate = it == 0 ? nullptr : c->ctl;
+    // sweep 0 under a warm start only interpolates: the predicted du is
+    // spread in place of s g0
+    const bool spread = !last && !(warm && it == 0);
+    const int mode = SW_INTERP | (it == 0 ? SW_FIRST : 0) | (spread ? SW_SPREAD_G : 0);
+    TRY(sweep(it, mode, gate, it == 0 && feats ? c->g0_orig : nullptr));
+    k_resid_check<<<1, LBM_BLOCK, 0, st>>>(c->pt_partials + (2 + it) * rs, lg, c->resid_thr, it,
+                                           last ? 1 : 0, use_thr, c->ctl);
+    TRY(hipGetLastError());
+    if (it == 0 && feats) TRY(launch_features_warm(c, warm));
+    if (it == 0 && warm && !last) {
+      TRY(sweep(0, SW_SPREAD_DU, c->ctl, nullptr));
+      TRY(merge(false, c->ctl));
+    } else if (spread) {
+      TRY(merge(false, c->ctl));
+    }
+  }
+  TRY(sweep(0, SW_SPREAD_DU, nullptr, nullptr));
+  TRY(merge(true, nullptr));
+#undef TRY
   return hipSuccess;
 }
 

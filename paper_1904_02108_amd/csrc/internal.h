@@ -63,6 +63,14 @@ struct lbm_ctx {
   uint32_t* touch_tiles = nullptr; // compact list of touched tiles
   uint32_t* meta = nullptr;        // [4]: list lengths
   uint8_t* bflag = nullptr;        // [nbflag_words * 4] force-block flags
+  // learned warm start
+  int32_t* nbr = nullptr;       // [max_points][16] neighbour lists (caller order)
+  float4* g0_orig = nullptr;    // [max_points] first deficit (caller order)
+  float* feat = nullptr;        // [max_points][12] features of the last forcing (sorted)
+  float* vref = nullptr;        // [LBM_MAX_BODIES] reference speed per body
+  float* theta = nullptr;       // [IBM_MLP_NPARAM] network parameters
+  uint32_t* ctl = nullptr;      // [4] residual stop: converged flag, sweeps run
+  double* resid_thr = nullptr;  // [1] eps^2 sum s |u_b|^2
   float* boxbuf = nullptr;          // [max_boxes][3][11^3] spread boxes of owner tiles
   int64_t max_boxes = 0;
   // scratch
@@ -77,6 +85,9 @@ struct lbm_ctx {
   int32_t nbodies = 0;
   int32_t n_iter = 5;
   uint32_t flags = 0;
+  float eps = 0.0f;
+  bool nbr_valid = false;   // neighbour lists match the current surface
+  bool theta_set = false;   // ibm_set_mlp has been called
   int64_t step = 0;
   int64_t g_valid_step = -1;
   bool g_prescribed = false;
@@ -109,3 +120,8 @@ hipError_t launch_forcing(lbm_ctx* c);
 int64_t forcing_list_grid(const lbm_ctx* c);
 hipError_t launch_reduce_point_stats(lbm_ctx* c, double* out /* [n_iter + 2] */);
 hipError_t launch_export_points(lbm_ctx* c, double* x, float* ub, float* g, float* du);
+
+// learned warm start (mlp_kernels.hip)
+hipError_t launch_neighbours(lbm_ctx* c);
+hipError_t launch_features_warm(lbm_ctx* c, bool predict);
+hipError_t launch_export_pairs(lbm_ctx* c, float* feat, float* targets);

@@ -26,6 +26,7 @@ struct Plan {
   size_t elem, pop_stride, lat_bytes;
   // points
   size_t o_rest, o_body_of, o_key, o_rank, o_base, o_frac, o_ub, o_g, o_du, o_bodies, o_motion;
+  size_t o_nbr, o_g0, o_feat, o_vref, o_theta;
   size_t o_box;
   int64_t max_boxes;
   // tiles
@@ -34,7 +35,7 @@ struct Plan {
   int64_t nblocks4, nbflag_words;
   int fblk[3];
   // scratch
-  size_t o_sum_part, o_pt_part, o_small;
+  size_t o_sum_part, o_pt_part, o_small, o_ctl, o_thr;
   int64_t part_row;
   int64_t n_cell_blocks, n_pt_blocks;
   int64_t ncell, ntiles;
@@ -146,6 +147,11 @@ void make_plan(const lbm_params* p, Plan& pl) {
   pl.o_du = pc.take(M * sizeof(float4));
   pl.o_bodies = pc.take((size_t)LBM_MAX_BODIES * 8 * sizeof(double));
   pl.o_motion = pc.take((size_t)LBM_MAX_BODIES * sizeof(BodyMotion));
+  pl.o_nbr = pc.take(M * IBM_MLP_NNBR * sizeof(int32_t));
+  pl.o_g0 = pc.take(M * sizeof(float4));
+  pl.o_feat = pc.take(M * IBM_MLP_NFEAT * sizeof(float));
+  pl.o_vref = pc.take((size_t)LBM_MAX_BODIES * sizeof(float));
+  pl.o_theta = pc.take((size_t)IBM_MLP_NPARAM * sizeof(float));
   pl.size[LBM_BUF_POINTS] = pc.at;
 
   const size_t NT = (size_t)pl.ntiles;
@@ -174,6 +180,8 @@ void make_plan(const lbm_params* p, Plan& pl) {
   pl.o_sum_part = sc.take((size_t)pl.n_cell_blocks * 4 * sizeof(double));
   pl.o_pt_part = sc.take((size_t)(p->max_iter + 2) * pl.part_row * sizeof(double));
   pl.o_small = sc.take(256 * sizeof(double));
+  pl.o_ctl = sc.take(4 * sizeof(uint32_t));
+  pl.o_thr = sc.take(sizeof(double));
   pl.size[LBM_BUF_SCRATCH] = sc.at;
 }
 
@@ -243,12 +251,34 @@ void ev_collect(lbm_ctx* c) {
 }
 
 lbm_status do_forcing(lbm_ctx* c) {
+  if ((c->flags & IBM_WARM_START) && !c->theta_set)
+    return fail(c, LBM_ERR_STATE, "IBM_WARM_START needs ibm_set_mlp first");
   ev_record(c, 0, true);
   hipError_t e = launch_forcing(c);
   if (e != hipSuccess) return hip_fail(c, e, "forcing");
   ev_record(c, 0, false);
   if (c->ev_used > 4000) ev_collect(c);
   c->g_valid_step = c->step;
+  return LBM_OK;
+}
+
+// Statistics of the last forcing: FP64 sums of the point partials; with a
+// residual stop, the sweeps run come from the device control block.
+lbm_status read_stats(lbm_ctx* c, ibm_stats* stats) {
+  hipError_t e = launch_reduce_point_stats(c, c->small);
+  if (e != hipSuccess) return hip_fail(c, e, "reduce point stats");
+  double h[2 + LBM_MAX_ITER];
+  uint32_t ctl[4] = {0, 0, 0, 0};
+  HIP_TRY(c, hipMemcpyAsync(h, c->small, sizeof(double) * (2 + c->n_iter), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(ctl, c->ctl, sizeof(ctl), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const bool gated = (c->flags & (IBM_STOP_RESIDUAL | IBM_WARM_START)) != 0;
+  const int ran = gated ? std::min<int>((int)ctl[1], c->n_iter) : c->n_iter;
+  std::memset(stats, 0, sizeof(*stats));
+  stats->n_iter = ran;
+  stats->sum_s = h[0];
+  stats->sum_s_ub2 = h[1];
+  for (int it = 0; it < ran; ++it) stats->resid[it] = h[2 + it];
   return LBM_OK;
 }
 
@@ -319,6 +349,11 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->sp_du = (float4*)(P + pl.o_du);
   c->bodies = (double*)(P + pl.o_bodies);
   c->motion = (BodyMotion*)(P + pl.o_motion);
+  c->nbr = (int32_t*)(P + pl.o_nbr);
+  c->g0_orig = (float4*)(P + pl.o_g0);
+  c->feat = (float*)(P + pl.o_feat);
+  c->vref = (float*)(P + pl.o_vref);
+  c->theta = (float*)(P + pl.o_theta);
   c->boxbuf = (float*)(F + pl.o_box);
   c->max_boxes = pl.max_boxes;
   char* T = (char*)bufs[LBM_BUF_TILES];
@@ -339,12 +374,15 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->pt_partials = (double*)(S + pl.o_pt_part);
   c->part_row = pl.part_row;
   c->small = (double*)(S + pl.o_small);
+  c->ctl = (uint32_t*)(S + pl.o_ctl);
+  c->resid_thr = (double*)(S + pl.o_thr);
 
   hipError_t e = hipSuccess;
   const int64_t ntpad = (c->ntiles + 16383) / 16384 * 16384;
   if (e == hipSuccess) e = launch_fill_u32(c, c->cnt_own, 0u, ntpad);
   if (e == hipSuccess) e = launch_fill_u32(c, c->cnt_touch, 0u, ntpad);
   if (e == hipSuccess) e = launch_fill_u32(c, c->meta, 0u, 4);
+  if (e == hipSuccess) e = launch_fill_u32(c, c->ctl, 0u, 4);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->bflag, 0u, c->nbflag_words);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->U, 0u, 3 * c->ncell);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->G, 0u, 3 * c->ncell);
@@ -391,8 +429,16 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
     return fail(c, LBM_ERR_ARG, "nbodies must be in [1, 65536]");
   if (n_iter < 1 || n_iter > c->p.max_iter)
     return fail(c, LBM_ERR_ARG, "n_iter must be in [1, max_iter]");
-  if (flags & ~(uint32_t)IBM_INNER_UNWEIGHTED) return fail(c, LBM_ERR_ARG, "unknown flags");
-  if (eps != 0.0f) return fail(c, LBM_ERR_ARG, "eps is reserved and must be 0");
+  const uint32_t known = IBM_INNER_UNWEIGHTED | IBM_STOP_RESIDUAL | IBM_WARM_START | IBM_KEEP_FEATURES;
+  if (flags & ~known) return fail(c, LBM_ERR_ARG, "unknown flags");
+  if ((flags & IBM_WARM_START) && (flags & IBM_INNER_UNWEIGHTED))
+    return fail(c, LBM_ERR_ARG, "IBM_WARM_START needs the weighted inner sweep");
+  if (flags & IBM_STOP_RESIDUAL) {
+    if (!(eps >= 0.0f) || !std::isfinite(eps))
+      return fail(c, LBM_ERR_ARG, "eps must be finite and >= 0");
+  } else if (eps != 0.0f) {
+    return fail(c, LBM_ERR_ARG, "eps must be 0 without IBM_STOP_RESIDUAL");
+  }
   if (body_off[0] != 0 || body_off[nbodies] != n)
     return fail(c, LBM_ERR_ARG, "body_off must start at 0 and end at n");
   for (int b = 0; b < nbodies; ++b)
@@ -400,6 +446,7 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
   std::vector<float4> rest((size_t)n);
   std::vector<int32_t> body_of((size_t)n);
   std::vector<double> btab((size_t)nbodies * 8);
+  std::vector<float> vref((size_t)nbodies);
   const int dims[3] = {c->p.nx, c->p.ny, c->p.nz};
   for (int b = 0; b < nbodies; ++b) {
     const ibm_body& B = bodies[b];
@@ -431,15 +478,22 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
     }
     btab[8 * b + 6] = B.theta0;
     btab[8 * b + 7] = B.omega;
+    // reference speed of the learned features: the fastest rest point's
+    // speed bound |omega| max |r|, or 1 for a body at rest
+    const double vr = std::fabs(B.omega) * rmax;
+    vref[(size_t)b] = vr > 0.0 ? (float)vr : 1.0f;
   }
   HIP_TRY(c, hipMemcpyAsync(c->rest, rest.data(), rest.size() * sizeof(float4), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->body_of, body_of.data(), body_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->bodies, btab.data(), btab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->vref, vref.data(), vref.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->npts = n;
   c->nbodies = nbodies;
   c->n_iter = n_iter;
   c->flags = flags;
+  c->eps = (flags & IBM_STOP_RESIDUAL) ? eps : 0.0f;
+  c->nbr_valid = false;
   c->g_valid_step = -1;
   c->g_prescribed = false;
   return LBM_OK;
@@ -450,18 +504,37 @@ lbm_status ibm_force_iterate(lbm_ctx* c, ibm_stats* stats) {
   if (c->npts == 0) return fail(c, LBM_ERR_STATE, "no Lagrangian points set");
   lbm_status st = do_forcing(c);
   if (st != LBM_OK) return st;
-  if (stats) {
-    hipError_t e = launch_reduce_point_stats(c, c->small);
-    if (e != hipSuccess) return hip_fail(c, e, "reduce point stats");
-    double h[2 + LBM_MAX_ITER];
-    HIP_TRY(c, hipMemcpyAsync(h, c->small, sizeof(double) * (2 + c->n_iter), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    std::memset(stats, 0, sizeof(*stats));
-    stats->n_iter = c->n_iter;
-    stats->sum_s = h[0];
-    stats->sum_s_ub2 = h[1];
-    for (int it = 0; it < c->n_iter; ++it) stats->resid[it] = h[2 + it];
-  }
+  return stats ? read_stats(c, stats) : LBM_OK;
+}
+
+lbm_status ibm_last_stats(lbm_ctx* c, ibm_stats* stats) {
+  if (!c) return LBM_ERR_ARG;
+  if (!stats) return fail(c, LBM_ERR_ARG, "stats is NULL");
+  if (c->npts == 0 || c->g_valid_step < 0)
+    return fail(c, LBM_ERR_STATE, "no forcing has run for the current points");
+  return read_stats(c, stats);
+}
+
+lbm_status ibm_set_mlp(lbm_ctx* c, const float* theta) {
+  if (!c) return LBM_ERR_ARG;
+  if (!theta) return fail(c, LBM_ERR_ARG, "theta is NULL");
+  for (int i = 0; i < IBM_MLP_NPARAM; ++i)
+    if (!std::isfinite(theta[i])) return fail(c, LBM_ERR_ARG, "theta must be finite");
+  HIP_TRY(c, hipMemcpyAsync(c->theta, theta, sizeof(float) * IBM_MLP_NPARAM, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->theta_set = true;
+  return LBM_OK;
+}
+
+lbm_status ibm_log_pairs(lbm_ctx* c, float* features, float* targets) {
+  if (!c) return LBM_ERR_ARG;
+  if (!features || !targets) return fail(c, LBM_ERR_ARG, "NULL destination");
+  if (!(c->flags & (IBM_KEEP_FEATURES | IBM_WARM_START)))
+    return fail(c, LBM_ERR_STATE, "the surface was set without IBM_KEEP_FEATURES");
+  if (c->npts == 0 || c->g_valid_step < 0)
+    return fail(c, LBM_ERR_STATE, "no forcing has run for the current points");
+  hipError_t e = launch_export_pairs(c, features, targets);
+  if (e != hipSuccess) return hip_fail(c, e, "export pairs");
   return LBM_OK;
 }
 

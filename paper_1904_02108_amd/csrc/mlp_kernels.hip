@@ -1,0 +1,567 @@
+// Learned warm start of the multi-direct forcing (not part of the paper):
+// per-point neighbour lists, features, the MLP 12 -> 64 -> 64 -> 64 -> 3
+// (SiLU) forward pass, and its training (forward, backward, Adam) on
+// batches of (features, converged correction) pairs.
+//
+// Parameter layout (row-major, out x in):
+//   W1[64][12] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3]
+#include "internal.h"
+
+using namespace lbmd;
+
+namespace {
+
+constexpr int NIN = IBM_MLP_NFEAT, NH = 64, NOUT = 3;
+constexpr int NPARAM = IBM_MLP_NPARAM;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NIN, OFF_W2 = OFF_B1 + NH,
+              OFF_B2 = OFF_W2 + NH * NH, OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NH * NH,
+              OFF_W4 = OFF_B3 + NH, OFF_B4 = OFF_W4 + NOUT * NH;
+static_assert(OFF_B4 + NOUT == NPARAM, "MLP parameter layout");
+constexpr int NNBR = IBM_MLP_NNBR;
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_grad(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// Whole forward pass of one sample with the parameters in LDS (FP32).
+__device__ __forceinline__ void mlp_eval(const float* __restrict__ P, const float x[NIN],
+                                         float y[NOUT]) {
+  float a[NH], b[NH];
+#pragma unroll 4
+  for (int o = 0; o < NH; ++o) {
+    float s = P[OFF_B1 + o];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) s += P[OFF_W1 + o * NIN + i] * x[i];
+    a[o] = silu(s);
+  }
+#pragma unroll 2
+  for (int o = 0; o < NH; ++o) {
+    float s = P[OFF_B2 + o];
+#pragma unroll
+    for (int i = 0; i < NH; ++i) s += P[OFF_W2 + o * NH + i] * a[i];
+    b[o] = silu(s);
+  }
+#pragma unroll 2
+  for (int o = 0; o < NH; ++o) {
+    float s = P[OFF_B3 + o];
+#pragma unroll
+    for (int i = 0; i < NH; ++i) s += P[OFF_W3 + o * NH + i] * b[i];
+    a[o] = silu(s);
+  }
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    float s = P[OFF_B4 + o];
+#pragma unroll
+    for (int i = 0; i < NH; ++i) s += P[OFF_W4 + o * NH + i] * a[i];
+    y[o] = s;
+  }
+}
+
+__device__ __forceinline__ void load_params(const float* __restrict__ theta, float* P) {
+  for (int i = threadIdx.x; i < NPARAM; i += blockDim.x) P[i] = theta[i];
+  __syncthreads();
+}
+
+// y[n][3] = MLP(x[n][12]), one thread per sample.
+__global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ theta, int64_t n,
+                                                     const float* __restrict__ x,
+                                                     float* __restrict__ y) {
+  __shared__ float P[NPARAM];
+  load_params(theta, P);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  float xi[NIN], yo[NOUT];
+#pragma unroll
+  for (int i = 0; i < NIN; ++i) xi[i] = x[k * NIN + i];
+  mlp_eval(P, xi, yo);
+#pragma unroll
+  for (int c = 0; c < NOUT; ++c) y[k * NOUT + c] = yo[c];
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour lists N(k): up to 16 points of k's body nearest to k, at
+// Euclidean distance < 2, ordered by (distance, caller index), stored by
+// caller index (-1 pads).  Distances are taken between the rest positions
+// r (body frame), in FP64 as ((dx^2 + dy^2) + dz^2) with every operation
+// rounded (no fused multiply-add), so the lists are exact and independent of
+// the rotation.  Candidates come from the points binned by owner tile at the
+// current step: a point within distance 2 has its base cell within 3 cells
+// of k's on every axis (rounding of the lattice position included), hence in
+// one of at most three distinct tiles per axis.
+// ---------------------------------------------------------------------------
+struct NbrGeom {
+  int n[3], bc[3], tiles[3];
+};
+
+__device__ __forceinline__ int cell_coord(int v, int n, int bc) {
+  if (bc == LBM_BC_PERIODIC) {
+    v %= n;
+    return v < 0 ? v + n : v;
+  }
+  return min(max(v, 0), n - 1);
+}
+
+// Distinct tiles of the cells base-3 .. base+3 along one axis.
+__device__ __forceinline__ int tile_span(int base, int n, int bc, int out[3]) {
+  int cnt = 0;
+  for (int d = -3; d <= 3; ++d) {
+    const int t = cell_coord(base + d, n, bc) >> TILE_SHIFT;
+    bool fresh = true;
+    for (int j = 0; j < cnt; ++j) fresh = fresh && out[j] != t;
+    if (fresh && cnt < 3) out[cnt++] = t;
+  }
+  return cnt;
+}
+
+__device__ __forceinline__ double rest_dist2(float4 a, float4 b) {
+#pragma clang fp contract(off)
+  const double dx = (double)b.x - (double)a.x;
+  const double dy = (double)b.y - (double)a.y;
+  const double dz = (double)b.z - (double)a.z;
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+__global__ __launch_bounds__(256) void k_neighbours(
+    const uint32_t* __restrict__ start_own, const int4* __restrict__ sp_base,
+    const float4* __restrict__ rest, const int32_t* __restrict__ body_of, int64_t npts,
+    NbrGeom ng, int32_t* __restrict__ nbr) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npts) return;
+  const int4 b = sp_base[k];
+  const int me = b.w;
+  const float4 rk = rest[me];
+  const int body = body_of[me];
+  double bd[NNBR];
+  int bi[NNBR];
+#pragma unroll
+  for (int j = 0; j < NNBR; ++j) {
+    bd[j] = 4.0;  // squared distance bound (distance < 2)
+    bi[j] = INT32_MAX;
+  }
+  int tx[3], ty[3], tz[3];
+  const int nx = tile_span(b.x, ng.n[0], ng.bc[0], tx);
+  const int ny = tile_span(b.y, ng.n[1], ng.bc[1], ty);
+  const int nz = tile_span(b.z, ng.n[2], ng.bc[2], tz);
+  for (int iz = 0; iz < nz; ++iz)
+    for (int iy = 0; iy < ny; ++iy)
+      for (int ix = 0; ix < nx; ++ix) {
+        const uint32_t t = (uint32_t)tx[ix] +
+                           (uint32_t)ng.tiles[0] * ((uint32_t)ty[iy] + (uint32_t)ng.tiles[1] * (uint32_t)tz[iz]);
+        const uint32_t q1 = start_own[t + 1];
+        for (uint32_t q = start_own[t]; q < q1; ++q) {
+          const int id = sp_base[q].w;
+          if (id == me || body_of[id] != body) continue;
+          const double d2 = rest_dist2(rk, rest[id]);
+          // (the sentinel 4.0 must not admit points at distance exactly 2)
+          if (d2 < 4.0 && (d2 < bd[NNBR - 1] || (d2 == bd[NNBR - 1] && id < bi[NNBR - 1]))) {
+            // insertion into the list sorted by (distance, index)
+            double cd = d2;
+            int ci = id;
+#pragma unroll
+            for (int j = 0; j < NNBR; ++j) {
+              const bool before = cd < bd[j] || (cd == bd[j] && ci < bi[j]);
+              const double td = bd[j];
+              const int ti = bi[j];
+              bd[j] = before ? cd : td;
+              bi[j] = before ? ci : ti;
+              cd = before ? td : cd;
+              ci = before ? ti : ci;
+            }
+          }
+        }
+      }
+#pragma unroll
+  for (int j = 0; j < NNBR; ++j) nbr[(int64_t)me * NNBR + j] = bi[j] == INT32_MAX ? -1 : bi[j];
+}
+
+// ---------------------------------------------------------------------------
+// Features of every point after the first sweep (kept in sorted order for
+// logging): g0 (3), u_b (3), mean and component-wise max of g0 over N(k)
+// (3 + 3, zeros for an empty N(k)), all divided by v_ref of k's body.  With
+// theta != nullptr and the forcing not yet converged (*gate == 0) the
+// network's output y gives the warm start du = s v_ref y, which replaces the
+// correction s g0 of the first sweep.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_features_warm(
+    const int4* __restrict__ sp_base, const float4* __restrict__ sp_frac,
+    const float4* __restrict__ sp_g, const float4* __restrict__ sp_ub,
+    const float4* __restrict__ g0_orig, const int32_t* __restrict__ nbr,
+    const int32_t* __restrict__ body_of, const float* __restrict__ vref, int64_t npts,
+    float* __restrict__ feat, const float* __restrict__ theta, const uint32_t* __restrict__ gate,
+    float4* __restrict__ sp_du) {
+  __shared__ float P[NPARAM];
+  const bool predict = theta != nullptr && !*gate;
+  if (predict) load_params(theta, P);
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npts) return;
+  const int orig = sp_base[k].w;
+  const float v = vref[body_of[orig]];
+  const float inv = 1.0f / v;
+  const float4 g = sp_g[k];
+  const float4 ub = sp_ub[k];
+  float m[3] = {0.f, 0.f, 0.f}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int cnt = 0;
+  for (int j = 0; j < NNBR; ++j) {
+    const int q = nbr[(int64_t)orig * NNBR + j];
+    if (q < 0) break;
+    const float4 gq = g0_orig[q];
+    m[0] += gq.x;
+    m[1] += gq.y;
+    m[2] += gq.z;
+    mx[0] = fmaxf(mx[0], gq.x);
+    mx[1] = fmaxf(mx[1], gq.y);
+    mx[2] = fmaxf(mx[2], gq.z);
+    ++cnt;
+  }
+  float x[NIN];
+  x[0] = g.x * inv;
+  x[1] = g.y * inv;
+  x[2] = g.z * inv;
+  x[3] = ub.x * inv;
+  x[4] = ub.y * inv;
+  x[5] = ub.z * inv;
+  for (int c = 0; c < 3; ++c) {
+    x[6 + c] = cnt ? m[c] / (float)cnt * inv : 0.0f;
+    x[9 + c] = cnt ? mx[c] * inv : 0.0f;
+  }
+  for (int i = 0; i < NIN; ++i) feat[k * NIN + i] = x[i];
+  if (predict) {
+    float y[NOUT];
+    mlp_eval(P, x, y);
+    const float sv = sp_frac[k].w * v;
+    sp_du[k] = make_float4(y[0] * sv, y[1] * sv, y[2] * sv, 0.0f);
+  }
+}
+
+// Training pairs in caller order: the features and t = du / (s v_ref)
+// (0 where s = 0).
+__global__ __launch_bounds__(256) void k_export_pairs(
+    const int4* __restrict__ sp_base, const float4* __restrict__ sp_frac,
+    const float* __restrict__ feat, const float4* __restrict__ sp_du,
+    const int32_t* __restrict__ body_of, const float* __restrict__ vref, int64_t npts,
+    float* __restrict__ fout, float* __restrict__ tout) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npts) return;
+  const int orig = sp_base[k].w;
+  for (int i = 0; i < NIN; ++i) fout[(int64_t)orig * NIN + i] = feat[k * NIN + i];
+  const float s = sp_frac[k].w;
+  const float inv = s > 0.0f ? 1.0f / (s * vref[body_of[orig]]) : 0.0f;
+  const float4 d = sp_du[k];
+  tout[(int64_t)orig * 3] = d.x * inv;
+  tout[(int64_t)orig * 3 + 1] = d.y * inv;
+  tout[(int64_t)orig * 3 + 2] = d.z * inv;
+}
+
+// ---------------------------------------------------------------------------
+// Training.  Activations of a batch live in the workspace:
+//   Z1,H1,Z2,H2,Z3,H3: [B][64]; Y: [B][3]; dZ (reused per layer): [B][64]
+// One thread per sample runs each dense layer (weights in LDS); the weight
+// gradients sum outer products over the batch in per-workgroup partials that
+// a second kernel reduces in a fixed order.
+// ---------------------------------------------------------------------------
+struct TrainWS {
+  float *Z1, *H1, *Z2, *H2, *Z3, *H3, *Y, *D3, *D2, *D1;  // D4 is stored in Y's slot of dY
+  float* dY;
+  float* grad;      // [NPARAM]
+  float* partials;  // [n_chunks][NPARAM]
+  double* loss_part;  // [n_blocks]
+  double* small;      // [4]
+  int64_t B, n_chunks;
+};
+
+constexpr int CHUNK = 128;  // samples per weight-gradient workgroup
+
+// Forward of layer l for every sample: Z = W A + b, H = silu(Z) (no SiLU on
+// the output layer, which also writes dL/dy and the squared error).
+template <int IN, int OUT, bool LAST>
+__global__ __launch_bounds__(256) void k_layer_fwd(const float* __restrict__ theta, int offW,
+                                                   int offB, int64_t n, const float* __restrict__ A,
+                                                   float* __restrict__ Z, float* __restrict__ H,
+                                                   const float* __restrict__ T, float* __restrict__ dY,
+                                                   double inv3n, double* __restrict__ loss_part) {
+  __shared__ float W[OUT * IN + OUT];
+  for (int i = threadIdx.x; i < OUT * IN; i += blockDim.x) W[i] = theta[offW + i];
+  for (int i = threadIdx.x; i < OUT; i += blockDim.x) W[OUT * IN + i] = theta[offB + i];
+  __syncthreads();
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double sq = 0.0;
+  if (s < n) {
+    float a[IN];
+#pragma unroll
+    for (int i = 0; i < IN; ++i) a[i] = A[s * IN + i];
+    for (int o = 0; o < OUT; ++o) {
+      float z = W[OUT * IN + o];
+#pragma unroll
+      for (int i = 0; i < IN; ++i) z += W[o * IN + i] * a[i];
+      if (LAST) {
+        const float r = z - T[s * OUT + o];
+        sq += (double)r * r;
+        dY[s * OUT + o] = (float)(2.0 * inv3n) * r;
+      } else {
+        Z[s * OUT + o] = z;
+        H[s * OUT + o] = silu(z);
+      }
+    }
+  }
+  if (LAST) {
+    __shared__ double red[4];
+    const double v = wave_sum(sq);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = (red[0] + red[1] + red[2] + red[3]) * inv3n;
+  }
+}
+
+// Backward data of layer l: D_in = (W^T D_out) * silu'(Z_in).
+template <int IN, int OUT>
+__global__ __launch_bounds__(256) void k_layer_bwd(const float* __restrict__ theta, int offW,
+                                                   int64_t n, const float* __restrict__ Dout,
+                                                   const float* __restrict__ Zin,
+                                                   float* __restrict__ Din) {
+  __shared__ float W[OUT * IN];
+  for (int i = threadIdx.x; i < OUT * IN; i += blockDim.x) W[i] = theta[offW + i];
+  __syncthreads();
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  float d[OUT];
+#pragma unroll
+  for (int o = 0; o < OUT; ++o) d[o] = Dout[s * OUT + o];
+  for (int i = 0; i < IN; ++i) {
+    float acc = 0.f;
+#pragma unroll
+    for (int o = 0; o < OUT; ++o) acc += W[o * IN + i] * d[o];
+    Din[s * IN + i] = acc * silu_grad(Zin[s * IN + i]);
+  }
+}
+
+// Weight and bias gradient partials of one layer: per chunk of CHUNK samples,
+// gW[o][i] = sum_s D[s][o] A[s][i], gb[o] = sum_s D[s][o].
+template <int IN, int OUT>
+__global__ __launch_bounds__(256) void k_layer_wgrad(int64_t n, const float* __restrict__ D,
+                                                     const float* __restrict__ A, int offW,
+                                                     int offB, float* __restrict__ partials) {
+  __shared__ float sD[CHUNK][OUT];
+  __shared__ float sA[CHUNK][IN];
+  const int64_t s0 = (int64_t)blockIdx.x * CHUNK;
+  const int cnt = (int)min<int64_t>(CHUNK, n - s0);
+  for (int i = threadIdx.x; i < CHUNK * OUT; i += blockDim.x) {
+    const int s = i / OUT, o = i % OUT;
+    sD[s][o] = s < cnt ? D[(s0 + s) * OUT + o] : 0.0f;
+  }
+  for (int i = threadIdx.x; i < CHUNK * IN; i += blockDim.x) {
+    const int s = i / IN, c = i % IN;
+    sA[s][c] = s < cnt ? A[(s0 + s) * IN + c] : 0.0f;
+  }
+  __syncthreads();
+  float* part = partials + (int64_t)blockIdx.x * NPARAM;
+  for (int w = threadIdx.x; w < OUT * IN + OUT; w += blockDim.x) {
+    float acc = 0.f;
+    if (w < OUT * IN) {
+      const int o = w / IN, i = w % IN;
+      for (int s = 0; s < CHUNK; ++s) acc += sD[s][o] * sA[s][i];
+      part[offW + w] = acc;
+    } else {
+      const int o = w - OUT * IN;
+      for (int s = 0; s < CHUNK; ++s) acc += sD[s][o];
+      part[offB + o] = acc;
+    }
+  }
+}
+
+// Sum of the chunk partials (fixed order) into grad.
+__global__ __launch_bounds__(256) void k_reduce_grad(const float* __restrict__ partials,
+                                                     int64_t n_chunks, float* __restrict__ grad) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPARAM) return;
+  double s = 0.0;
+  for (int64_t c = 0; c < n_chunks; ++c) s += partials[c * NPARAM + p];
+  grad[p] = (float)s;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_loss(const double* __restrict__ part, int64_t nb,
+                                                     double* out) {
+  double s = 0.0;
+  for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) s += part[b];
+  __shared__ double red[4];
+  const double v = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
+}
+
+// Adam with bias correction (c1 = 1 - beta1^t, c2 = 1 - beta2^t).
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ theta, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, float lr,
+                                              float c1, float c2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= NPARAM) return;
+  const float gp = g[p];
+  const float mp = 0.9f * m[p] + 0.1f * gp;
+  const float vp = 0.999f * v[p] + 0.001f * gp * gp;
+  m[p] = mp;
+  v[p] = vp;
+  theta[p] -= lr * (mp / c1) / (sqrtf(vp / c2) + 1e-8f);
+}
+
+size_t ws_align(size_t v) { return (v + 255) / 256 * 256; }
+
+TrainWS carve_ws(void* ws, int64_t B) {
+  TrainWS w;
+  char* p = (char*)ws;
+  size_t at = 0;
+  auto take = [&](size_t bytes) {
+    char* r = p + at;
+    at = ws_align(at + bytes);
+    return r;
+  };
+  w.B = B;
+  w.n_chunks = (B + CHUNK - 1) / CHUNK;
+  w.Z1 = (float*)take(B * NH * 4);
+  w.H1 = (float*)take(B * NH * 4);
+  w.Z2 = (float*)take(B * NH * 4);
+  w.H2 = (float*)take(B * NH * 4);
+  w.Z3 = (float*)take(B * NH * 4);
+  w.H3 = (float*)take(B * NH * 4);
+  w.D3 = (float*)take(B * NH * 4);
+  w.D2 = (float*)take(B * NH * 4);
+  w.D1 = (float*)take(B * NH * 4);
+  w.dY = (float*)take(B * NOUT * 4);
+  w.Y = nullptr;
+  w.grad = (float*)take((size_t)NPARAM * 4);
+  w.partials = (float*)take((size_t)w.n_chunks * NPARAM * 4);
+  w.loss_part = (double*)take((size_t)((B + 255) / 256) * 8);
+  w.small = (double*)take(4 * 8);
+  return w;
+}
+
+// Loss and gradient of one batch [x, x + B).
+hipError_t batch_grad(const float* theta, int64_t B, const float* x, const float* t, float* grad,
+                      double* loss, const TrainWS& w, hipStream_t st) {
+  const unsigned nb = (unsigned)((B + 255) / 256);
+  const double inv3n = 1.0 / (3.0 * (double)B);
+  k_layer_fwd<NIN, NH, false><<<nb, 256, 0, st>>>(theta, OFF_W1, OFF_B1, B, x, w.Z1, w.H1, nullptr,
+                                                  nullptr, 0.0, nullptr);
+  k_layer_fwd<NH, NH, false><<<nb, 256, 0, st>>>(theta, OFF_W2, OFF_B2, B, w.H1, w.Z2, w.H2, nullptr,
+                                                 nullptr, 0.0, nullptr);
+  k_layer_fwd<NH, NH, false><<<nb, 256, 0, st>>>(theta, OFF_W3, OFF_B3, B, w.H2, w.Z3, w.H3, nullptr,
+                                                 nullptr, 0.0, nullptr);
+  k_layer_fwd<NH, NOUT, true><<<nb, 256, 0, st>>>(theta, OFF_W4, OFF_B4, B, w.H3, nullptr, nullptr,
+                                                  t, w.dY, inv3n, w.loss_part);
+  k_layer_bwd<NH, NOUT><<<nb, 256, 0, st>>>(theta, OFF_W4, B, w.dY, w.Z3, w.D3);
+  k_layer_bwd<NH, NH><<<nb, 256, 0, st>>>(theta, OFF_W3, B, w.D3, w.Z2, w.D2);
+  k_layer_bwd<NH, NH><<<nb, 256, 0, st>>>(theta, OFF_W2, B, w.D2, w.Z1, w.D1);
+  const unsigned nc = (unsigned)((B + CHUNK - 1) / CHUNK);
+  k_layer_wgrad<NH, NOUT><<<nc, 256, 0, st>>>(B, w.dY, w.H3, OFF_W4, OFF_B4, w.partials);
+  k_layer_wgrad<NH, NH><<<nc, 256, 0, st>>>(B, w.D3, w.H2, OFF_W3, OFF_B3, w.partials);
+  k_layer_wgrad<NH, NH><<<nc, 256, 0, st>>>(B, w.D2, w.H1, OFF_W2, OFF_B2, w.partials);
+  k_layer_wgrad<NIN, NH><<<nc, 256, 0, st>>>(B, w.D1, x, OFF_W1, OFF_B1, w.partials);
+  k_reduce_grad<<<(NPARAM + 255) / 256, 256, 0, st>>>(w.partials, (int64_t)nc, grad);
+  if (loss) k_reduce_loss<<<1, 256, 0, st>>>(w.loss_part, nb, loss);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_neighbours(lbm_ctx* c) {
+  NbrGeom ng;
+  const int dims[3] = {c->p.nx, c->p.ny, c->p.nz};
+  for (int a = 0; a < 3; ++a) {
+    ng.n[a] = dims[a];
+    ng.bc[a] = c->p.bc[a];
+    ng.tiles[a] = c->tiles[a];
+  }
+  const unsigned nb = (unsigned)((c->npts + 255) / 256);
+  if (nb == 0) return hipSuccess;
+  k_neighbours<<<nb, 256, 0, c->stream>>>(c->start_own, c->sp_base, c->rest, c->body_of, c->npts,
+                                          ng, c->nbr);
+  return hipGetLastError();
+}
+
+hipError_t launch_features_warm(lbm_ctx* c, bool predict) {
+  const unsigned nb = (unsigned)((c->npts + 255) / 256);
+  if (nb == 0) return hipSuccess;
+  k_features_warm<<<nb, 256, 0, c->stream>>>(c->sp_base, c->sp_frac, c->sp_g, c->sp_ub, c->g0_orig,
+                                             c->nbr, c->body_of, c->vref, c->npts, c->feat,
+                                             predict ? c->theta : nullptr, c->ctl, c->sp_du);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_pairs(lbm_ctx* c, float* feat, float* targets) {
+  const unsigned nb = (unsigned)((c->npts + 255) / 256);
+  if (nb == 0) return hipSuccess;
+  k_export_pairs<<<nb, 256, 0, c->stream>>>(c->sp_base, c->sp_frac, c->feat, c->sp_du, c->body_of,
+                                            c->vref, c->npts, feat, targets);
+  return hipGetLastError();
+}
+
+extern "C" {
+
+size_t mlp_workspace_size(int64_t batch) {
+  if (batch < 1) batch = 1;
+  const int64_t nch = (batch + CHUNK - 1) / CHUNK;
+  size_t s = 0;
+  s += 9 * ws_align((size_t)batch * NH * 4);
+  s += ws_align((size_t)batch * NOUT * 4);
+  s += ws_align((size_t)NPARAM * 4);
+  s += ws_align((size_t)nch * NPARAM * 4);
+  s += ws_align((size_t)((batch + 255) / 256) * 8);
+  s += ws_align(4 * 8);
+  return s;
+}
+
+lbm_status mlp_forward(const float* theta, int64_t n, const float* x, float* y, void* workspace,
+                       void* stream) {
+  (void)workspace;
+  if (!theta || n < 0 || (n > 0 && (!x || !y))) return LBM_ERR_ARG;
+  if (n == 0) return LBM_OK;
+  k_mlp_forward<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(theta, n, x, y);
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+lbm_status mlp_loss_grad(const float* theta, int64_t n, const float* x, const float* t,
+                         float* grad, double* loss_out, void* workspace, void* stream) {
+  if (!theta || n < 1 || !x || !t || !grad || !workspace) return LBM_ERR_ARG;
+  const TrainWS w = carve_ws(workspace, n);
+  hipError_t e = batch_grad(theta, n, x, t, grad, loss_out, w, (hipStream_t)stream);
+  return e == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+lbm_status mlp_train(float* theta, float* m, float* v, int64_t* step_t, int64_t n, const float* x,
+                     const float* t, int64_t batch, int32_t n_epochs, double lr,
+                     double* loss_per_epoch, void* workspace, void* stream) {
+  if (!theta || !m || !v || !step_t || n < 1 || !x || !t || batch < 1 || n_epochs < 0 ||
+      !workspace || !(lr > 0.0))
+    return LBM_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const TrainWS w = carve_ws(workspace, batch);
+  float* grad = w.grad;
+  for (int ep = 0; ep < n_epochs; ++ep) {
+    double acc = 0.0;
+    int64_t nbatches = 0;
+    for (int64_t b0 = 0; b0 < n; b0 += batch) {
+      const int64_t B = std::min<int64_t>(batch, n - b0);
+      hipError_t e = batch_grad(theta, B, x + b0 * NIN, t + b0 * NOUT, grad, w.small, w, st);
+      if (e != hipSuccess) return LBM_ERR_HIP;
+      *step_t += 1;
+      const float c1 = (float)(1.0 - std::pow(0.9, (double)*step_t));
+      const float c2 = (float)(1.0 - std::pow(0.999, (double)*step_t));
+      k_adam<<<(NPARAM + 255) / 256, 256, 0, st>>>(theta, grad, m, v, (float)lr, c1, c2);
+      if (hipGetLastError() != hipSuccess) return LBM_ERR_HIP;
+      if (loss_per_epoch) {
+        double l = 0.0;
+        if (hipMemcpyAsync(&l, w.small, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+          return LBM_ERR_HIP;
+        acc += l;
+      }
+      ++nbatches;
+    }
+    if (loss_per_epoch) loss_per_epoch[ep] = nbatches ? acc / (double)nbatches : 0.0;
+  }
+  return LBM_OK;
+}
+
+}  // extern "C"

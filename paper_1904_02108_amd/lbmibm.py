@@ -29,14 +29,17 @@ LBM_BC_PERIODIC, LBM_BC_BOUNCEBACK = 0, 1
 LBM_STORE_F32, LBM_STORE_F16, LBM_STORE_BF16 = 0, 1, 2
 LBM_FORCE_GUO, LBM_FORCE_SHIFT = 0, 1
 LBM_NBUF = 5
-IBM_INNER_UNWEIGHTED = 1
+IBM_INNER_UNWEIGHTED, IBM_STOP_RESIDUAL, IBM_WARM_START, IBM_KEEP_FEATURES = 1, 2, 4, 8
+IBM_MLP_NPARAM, IBM_MLP_NFEAT, IBM_MLP_NNBR = 9347, 12, 16
 LBM_MAX_ITER = 64
 (LBM_F_RHO, LBM_F_VEL, LBM_F_FORCE, LBM_F_POPS, LBM_F_PT_X, LBM_F_PT_UB, LBM_F_PT_G, LBM_F_PT_DU,
  LBM_F_SUMS, LBM_F_STEP) = (1 << k for k in range(10))
 
 ABI_FUNCTIONS = ("lbm_buffer_sizes", "lbm_create", "lbm_destroy", "lbm_last_error",
                  "ibm_set_points", "ibm_force_iterate", "lbm_step", "lbm_read_fields",
-                 "lbm_write_fields", "lbm_set_timing", "lbm_get_timing")
+                 "lbm_write_fields", "lbm_set_timing", "lbm_get_timing", "ibm_set_mlp",
+                 "ibm_log_pairs", "ibm_last_stats", "mlp_workspace_size", "mlp_forward",
+                 "mlp_loss_grad", "mlp_train")
 
 
 class lbm_params(ct.Structure):
@@ -82,6 +85,18 @@ _lib.lbm_read_fields.argtypes = [_C, ct.c_uint32, ct.POINTER(lbm_fields)]
 _lib.lbm_write_fields.argtypes = [_C, ct.c_uint32, ct.POINTER(lbm_fields)]
 _lib.lbm_set_timing.argtypes = [_C, ct.c_int32]
 _lib.lbm_get_timing.argtypes = [_C, ct.POINTER(ct.c_double)]
+_lib.ibm_set_mlp.argtypes = [_C, ct.c_void_p]
+_lib.ibm_log_pairs.argtypes = [_C, ct.c_void_p, ct.c_void_p]
+_lib.ibm_last_stats.argtypes = [_C, ct.POINTER(ibm_stats)]
+_lib.mlp_workspace_size.argtypes = [ct.c_int64]
+_lib.mlp_workspace_size.restype = ct.c_size_t
+_lib.mlp_forward.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                             ct.c_void_p]
+_lib.mlp_loss_grad.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                               ct.c_void_p, ct.c_void_p, ct.c_void_p]
+_lib.mlp_train.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.POINTER(ct.c_int64),
+                           ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32,
+                           ct.c_double, ct.c_void_p, ct.c_void_p, ct.c_void_p]
 for _f in ("lbm_buffer_sizes", "lbm_create", "ibm_set_points", "ibm_force_iterate", "lbm_step",
            "lbm_read_fields", "lbm_write_fields", "lbm_set_timing", "lbm_get_timing"):
     getattr(_lib, _f).restype = ct.c_int32
@@ -157,14 +172,62 @@ def ibm_set_points(ctx, rest, area, body_off, bodies, n_iter=5, flags=0, eps=0.0
                                int(n_iter), int(flags), float(eps)), ctx)
 
 
+def _stats_dict(s):
+    return {"n_iter": s.n_iter, "sum_s": s.sum_s, "sum_s_ub2": s.sum_s_ub2,
+            "resid": np.array(s.resid[:s.n_iter])}
+
+
 def ibm_force_iterate(ctx, stats=False):
     if stats:
         s = ibm_stats()
         _check(_lib.ibm_force_iterate(ctx, ct.byref(s)), ctx)
-        return {"n_iter": s.n_iter, "sum_s": s.sum_s, "sum_s_ub2": s.sum_s_ub2,
-                "resid": np.array(s.resid[:s.n_iter])}
+        return _stats_dict(s)
     _check(_lib.ibm_force_iterate(ctx, None), ctx)
     return None
+
+
+def ibm_last_stats(ctx):
+    s = ibm_stats()
+    _check(_lib.ibm_last_stats(ctx, ct.byref(s)), ctx)
+    return _stats_dict(s)
+
+
+def ibm_set_mlp(ctx, theta):
+    th = np.ascontiguousarray(theta, dtype=np.float32).reshape(-1)
+    if th.size != IBM_MLP_NPARAM:
+        raise ValueError("theta must hold %d values" % IBM_MLP_NPARAM)
+    _check(_lib.ibm_set_mlp(ctx, th.ctypes.data_as(ct.c_void_p)), ctx)
+
+
+def ibm_log_pairs(ctx, features_ptr, targets_ptr):
+    _check(_lib.ibm_log_pairs(ctx, ct.c_void_p(features_ptr), ct.c_void_p(targets_ptr)), ctx)
+
+
+def mlp_workspace_size(batch):
+    return int(_lib.mlp_workspace_size(int(batch)))
+
+
+def mlp_forward(theta_ptr, n, x_ptr, y_ptr, workspace_ptr, stream_ptr):
+    _check(_lib.mlp_forward(ct.c_void_p(theta_ptr), int(n), ct.c_void_p(x_ptr), ct.c_void_p(y_ptr),
+                            ct.c_void_p(workspace_ptr), ct.c_void_p(stream_ptr)))
+
+
+def mlp_loss_grad(theta_ptr, n, x_ptr, t_ptr, grad_ptr, loss_ptr, workspace_ptr, stream_ptr):
+    _check(_lib.mlp_loss_grad(ct.c_void_p(theta_ptr), int(n), ct.c_void_p(x_ptr),
+                              ct.c_void_p(t_ptr), ct.c_void_p(grad_ptr), ct.c_void_p(loss_ptr),
+                              ct.c_void_p(workspace_ptr), ct.c_void_p(stream_ptr)))
+
+
+def mlp_train(theta_ptr, m_ptr, v_ptr, step_t, n, x_ptr, t_ptr, batch, n_epochs, lr,
+              workspace_ptr, stream_ptr, want_loss=True):
+    """Returns (new Adam step count, per-epoch mean batch losses or None)."""
+    st = ct.c_int64(int(step_t))
+    losses = (ct.c_double * max(int(n_epochs), 1))() if want_loss else None
+    _check(_lib.mlp_train(ct.c_void_p(theta_ptr), ct.c_void_p(m_ptr), ct.c_void_p(v_ptr),
+                          ct.byref(st), int(n), ct.c_void_p(x_ptr), ct.c_void_p(t_ptr), int(batch),
+                          int(n_epochs), float(lr), losses, ct.c_void_p(workspace_ptr),
+                          ct.c_void_p(stream_ptr)))
+    return st.value, (np.array(losses[:int(n_epochs)]) if want_loss else None)
 
 
 def lbm_step(ctx, n_steps=1):
@@ -227,12 +290,32 @@ class Simulation:
         nx, ny, nz = self.shape
         return (nz, ny, nx)
 
-    def set_points(self, rest, area, body_off, bodies, n_iter=5, flags=0):
-        ibm_set_points(self.ctx, rest, area, body_off, bodies, n_iter, flags)
+    def set_points(self, rest, area, body_off, bodies, n_iter=5, flags=0, eps=0.0):
+        ibm_set_points(self.ctx, rest, area, body_off, bodies, n_iter, flags, eps)
         self.n_points = int(np.asarray(rest).reshape(-1, 3).shape[0])
 
     def force_iterate(self, stats=False):
         return ibm_force_iterate(self.ctx, stats)
+
+    def last_stats(self):
+        return ibm_last_stats(self.ctx)
+
+    def set_mlp(self, theta):
+        ibm_set_mlp(self.ctx, theta)
+
+    def log_pairs(self, features=None, targets=None):
+        """Training pairs of the last forcing as device tensors [n, 12] and
+        [n, 3] (written into ``features``/``targets`` when given)."""
+        t = self.torch
+        n = self.n_points
+        if features is None:
+            features = t.empty((n, IBM_MLP_NFEAT), dtype=t.float32, device=self.device)
+        if targets is None:
+            targets = t.empty((n, 3), dtype=t.float32, device=self.device)
+        assert features.is_contiguous() and targets.is_contiguous()
+        assert features.numel() >= n * IBM_MLP_NFEAT and targets.numel() >= n * 3
+        ibm_log_pairs(self.ctx, features.data_ptr(), targets.data_ptr())
+        return features, targets
 
     def step(self, n=1):
         lbm_step(self.ctx, n)

@@ -138,7 +138,9 @@ def config(name, h=None, seed=0, forcing=FORCE_GUO):
         omega 0.01 about z, 5 iterations, 50 steps.
     c1  128^3, x periodic, y/z bounce-back walls, tau 0.55, propeller x4
         (hub r 12, L 24, blades 40x12) at the centre, h 0.7, omega 0.005,
-        5 iterations, 1000 steps.
+        5 iterations, 1000 steps.  seed > 0: axis uniform on the sphere,
+        theta0 ~ U[0, 2 pi), omega ~ U[0.004, 0.006] (training data of the
+        learned warm start; seed 0 is the canonical case).
     c2  256^3 periodic, tau 0.55, 64 propellers of c1 size at 32 + 64 {0..3}^3,
         axes uniform on the sphere, theta0 ~ U[0, 2 pi), omega ~ U[0.002, 0.008]
         (seeded), 5 iterations, 500 steps.  h 0.7 gives the literal sampling
@@ -154,7 +156,14 @@ def config(name, h=None, seed=0, forcing=FORCE_GUO):
     if name == "c1":
         hh = 0.7 if h is None else h
         pts, ar = propeller_surface(12.0, 24.0, 40.0, 12.0, hh)
-        rest, area, off, bodies = _assemble([(pts, ar, (64.0, 64.0, 64.0), (0, 0, 1), 0.0, 0.005)])
+        axis, th0, om = (0.0, 0.0, 1.0), 0.0, 0.005
+        if seed:  # other seeds: random axis and phase, omega near the canonical one
+            rng = _rng(seed)
+            v = rng.normal(size=3)
+            axis = tuple(v / np.linalg.norm(v))
+            th0 = rng.uniform(0.0, 2.0 * math.pi)
+            om = rng.uniform(0.004, 0.006)
+        rest, area, off, bodies = _assemble([(pts, ar, (64.0, 64.0, 64.0), axis, th0, om)])
         return Workload("c1", (128, 128, 128), 0.55, (0, 1, 1), forcing, rest, area, off, bodies,
                         5, 1000, hh)
     if name in ("c2", "c2_dense"):
@@ -219,3 +228,19 @@ def random_points(shape, n, seed, margin=0.0, special=True):
         x[2] = [0.0, 0.0, 0.0] if margin == 0 else x[2]
         x[3] = [nx - 1e-3, ny - 0.5, nz - 1.0] if margin == 0 else x[3]
     return x
+
+
+def mlp_init(seed, scale=1.0):
+    """Initial parameters of the warm-start network (flat layout of the C
+    interface, FP32): weights ~ U(-a, a) with a = scale * sqrt(3 / fan_in)
+    (variance 1 / fan_in), biases 0."""
+    rng = _rng(seed)
+    sizes = [(64, 12), (64,), (64, 64), (64,), (64, 64), (64,), (3, 64), (3,)]
+    parts = []
+    for shp in sizes:
+        if len(shp) == 2:
+            a = scale * math.sqrt(3.0 / shp[1])
+            parts.append(rng.uniform(-a, a, size=shp).ravel())
+        else:
+            parts.append(np.zeros(shp))
+    return np.concatenate(parts).astype(np.float32)

@@ -1,0 +1,293 @@
+"""GPU parity of the residual-stopped forcing and of the learned warm start
+(through the C interface) against the FP64 oracle: the MLP kernels
+(forward, loss gradient, Adam), the features of the first sweep, the sweep
+counts and results of residual-stopped and warm-started forcing, and what a
+network trained on the GPU from plain runs gains over the plain sweep."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_common import rel_linf, sim_for_workload, to_np
+from paper_1904_02108_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+NP = 9347
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1904_02108_amd import lbmibm
+    return lbmibm
+
+
+@pytest.fixture(scope="module")
+def LN(L):
+    from paper_1904_02108_amd import learned
+    return learned
+
+
+def _dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+def _f64(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+# --------------------------------------------------------------- MLP kernels
+@pytest.mark.parametrize("n", [1, 255, 1037])
+def test_mlp_forward(LN, n):
+    rng = np.random.default_rng(n)
+    th = W.mlp_init(n, scale=1.5)
+    th[-3:] = rng.normal(size=3)
+    x = rng.normal(size=(n, 12)).astype(np.float32)
+    net = LN.Network(th)
+    y = to_np(net.forward(_dev(x)))
+    ref = O.mlp_forward(_f64(th), _f64(x))
+    assert rel_linf(y, ref) < 1e-5
+
+
+@pytest.mark.parametrize("n", [1, 300, 777])
+def test_mlp_loss_grad(LN, n):
+    """Loss and gradient of the mean squared error against the oracle's
+    analytic FP64 backpropagation (which is pinned to finite differences)."""
+    rng = np.random.default_rng(10 + n)
+    th = W.mlp_init(20 + n, scale=1.5)
+    x = rng.normal(size=(n, 12)).astype(np.float32)
+    t = rng.normal(size=(n, 3)).astype(np.float32)
+    net = LN.Network(th, max_batch=n)
+    loss, g = net.loss_grad(_dev(x), _dev(t))
+    rl, rg = O.mlp_loss_grad(_f64(th), _f64(x), _f64(t))
+    assert abs(float(to_np(loss)[0]) - rl) <= 1e-5 * rl
+    assert rel_linf(to_np(g), rg) < 1e-4
+
+
+def test_mlp_adam_steps_match_oracle(LN):
+    """Three full-batch Adam steps on the GPU against the oracle's gradient
+    and Adam step: parameters whose gradient is not at rounding level move
+    alike (Adam's first steps move them by about lr each).  Where a
+    component's gradient nearly cancels across the steps, m / sqrt(v) is
+    ill-conditioned, so a few parameters may differ by a small part of lr."""
+    rng = np.random.default_rng(31)
+    n, lr = 512, 1e-3
+    th = W.mlp_init(32)
+    x = rng.normal(size=(n, 12)).astype(np.float32)
+    t = np.tanh(x[:, :3]).astype(np.float32)
+    net = LN.Network(th, max_batch=n)
+    net.train(_dev(x), _dev(t), batch=n, epochs=3, lr=lr)
+    assert net.t == 3
+    ref = _f64(th)
+    m, v = np.zeros(NP), np.zeros(NP)
+    gmax = np.zeros(NP)
+    for s in range(1, 4):
+        _, g = O.mlp_loss_grad(ref, _f64(x), _f64(t))
+        gmax = np.maximum(gmax, np.abs(g))
+        O.adam_step(ref, g, m, v, s, lr)
+    got = net.numpy().astype(np.float64)
+    sig = gmax > 1e-4 * gmax.max()
+    assert sig.sum() > NP // 2
+    d = np.abs(got - ref)
+    assert (d[sig] <= 2e-3 * lr).mean() >= 0.999
+    assert d[sig].max() <= 0.05 * lr
+    assert d.max() <= 6 * lr
+
+
+def test_mlp_training_reduces_loss(LN):
+    rng = np.random.default_rng(41)
+    n = 8192
+    x = rng.normal(size=(n, 12)).astype(np.float32)
+    A = rng.normal(scale=0.3, size=(12, 3))
+    t = np.tanh(x @ A).astype(np.float32)
+    net = LN.Network(W.mlp_init(42), max_batch=256)
+    losses = net.train(_dev(x), _dev(t), batch=256, epochs=20, lr=3e-3)
+    print("epoch losses", losses[0], losses[-1], flush=True)
+    assert losses[-1] < 0.05 * losses[0]
+
+
+# ------------------------------------------------- features, stop, warm start
+def _run_both(L, wl, flags, n_iter, n_steps, eps=0.0, theta=None):
+    """GPU and oracle run n_steps - 1 steps, then one step with outputs."""
+    sim, p, pts = sim_for_workload(L, wl)
+    if theta is not None:
+        sim.set_mlp(theta)
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, n_iter, flags, eps)
+    opts = O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, n_iter, flags, eps,
+                    None if theta is None else _f64(theta))
+    f = O.init_equilibrium(p)
+    sim.step(n_steps - 1)
+    if n_steps > 1:
+        O.run(p, f, opts, 0, n_steps - 1)
+    r = O.step(p, f, opts, n_steps - 1, features=True)
+    sim.step(1)
+    return sim, r
+
+
+def test_features_and_targets(L):
+    """Features of the first sweep and the training targets du / (s v_ref)
+    after 6 steps of C0 (plain, 5 sweeps, features kept)."""
+    wl = W.config("c0")
+    sim, r = _run_both(L, wl, L.IBM_KEEP_FEATURES, 5, 6)
+    fx, ft = sim.log_pairs()
+    fx, ft = to_np(fx), to_np(ft)
+    assert rel_linf(fx, r["feat"]) < 1e-5
+    v = O.vref_points(wl.rest, wl.body_off, wl.bodies)
+    s = wl.area.astype(np.float64)
+    tref = np.where(s[:, None] > 0, r["du"] / (s * v)[:, None], 0.0)
+    assert rel_linf(ft, tref) < 1e-5
+    # the neighbour part of the features is not trivially zero
+    assert np.abs(r["feat"][:, 6:]).max() > 0.1 * np.abs(r["feat"][:, :3]).max()
+
+
+def _eps_between(resid, sum_ub2, k):
+    """A threshold half way (in log) between the residuals R_rel of sweeps
+    k - 1 and k, checked to lie at least 1% away from every sweep's
+    residual, so that rounding cannot move the stopping sweep."""
+    rr = np.sqrt(np.asarray(resid) / sum_ub2)
+    eps = float(np.sqrt(rr[k - 1] * rr[k]))
+    assert np.abs(np.log(rr / eps)).min() > 0.01, (rr, eps)
+    return eps
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_residual_stop_parity(L, k):
+    wl = W.config("c0")
+    pts = O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, 8, 0)
+    p = O.params(wl.shape, wl.tau, bc=wl.bc)
+    f = O.init_equilibrium(p)
+    O.run(p, f, pts, 0, 3)
+    probe = O.step(p, f.copy(), pts, 3)
+    x, ub = O.kinematics(wl.rest, wl.body_off, wl.bodies, 3)
+    sub2 = float((wl.area.astype(np.float64)[:, None] * ub ** 2).sum())
+    eps = _eps_between(probe["resid"], sub2, k)
+    # both sides run 3 plain steps, then the residual-stopped step
+    sim, p2, _ = sim_for_workload(L, wl)
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 8, 0)
+    sim.step(3)
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 8, L.IBM_STOP_RESIDUAL, eps)
+    st = sim.force_iterate(stats=True)
+    ostop = O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, 8, O.IBM_STOP_RESIDUAL, eps)
+    r = O.step(p, f, ostop, 3)
+    assert st["n_iter"] == r["n_sweeps"] == k + 1
+    np.testing.assert_allclose(st["resid"], r["resid"], rtol=1e-4)
+    out = sim.read("force", "pt_du")
+    assert rel_linf(to_np(out["force"]), r["G"]) < 1e-5
+    assert rel_linf(to_np(out["pt_du"]), r["du"]) < 1e-5
+
+
+def test_warm_start_parity(L):
+    """A random network warm-starts C0 at step 5 with a residual stop: the
+    sweeps run, the correction and the force match the oracle."""
+    wl = W.config("c0")
+    th = W.mlp_init(7, scale=0.5)
+    flags = L.IBM_WARM_START | L.IBM_STOP_RESIDUAL
+    p = O.params(wl.shape, wl.tau, bc=wl.bc)
+    # the threshold half way between two residual levels of the oracle's
+    # warm-started step
+    probe_pts = O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, 8, O.IBM_WARM_START, 0.0,
+                         _f64(th))
+    f = O.init_equilibrium(p)
+    O.run(p, f, probe_pts, 0, 5)
+    probe = O.step(p, f, probe_pts, 5)
+    _, ub = O.kinematics(wl.rest, wl.body_off, wl.bodies, 5)
+    sub2 = float((wl.area.astype(np.float64)[:, None] * ub ** 2).sum())
+    eps = _eps_between(probe["resid"], sub2, 3)
+    # GPU and oracle: 5 warm-started steps with eps = 0 (all 8 sweeps), then
+    # one with the threshold
+    sim, _, _ = sim_for_workload(L, wl)
+    sim.set_mlp(th)
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 8, L.IBM_WARM_START)
+    sim.step(5)
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 8, flags, eps)
+    st = sim.force_iterate(stats=True)
+    f = O.init_equilibrium(p)
+    O.run(p, f, probe_pts, 0, 5)
+    stop_pts = O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, 8,
+                        O.IBM_WARM_START | O.IBM_STOP_RESIDUAL, eps, _f64(th))
+    r = O.step(p, f, stop_pts, 5)
+    print("warm-started sweeps", r["n_sweeps"], "of 8", flush=True)
+    assert st["n_iter"] == r["n_sweeps"] >= 2
+    out = sim.read("force", "pt_du", "vel")
+    assert rel_linf(to_np(out["pt_du"]), r["du"]) < 1e-5
+    assert rel_linf(to_np(out["force"]), r["G"]) < 1e-5
+
+
+def test_warm_start_zero_network(L):
+    """A network that predicts 0 wastes one sweep: N warm-started sweeps give
+    the force of N - 1 plain sweeps (GPU against GPU, then the oracle)."""
+    wl = W.config("c0")
+    a, _, _ = sim_for_workload(L, wl)
+    a.set_mlp(np.zeros(NP, dtype=np.float32))
+    a.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 5, L.IBM_WARM_START)
+    b, p, _ = sim_for_workload(L, wl)
+    b.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 4, 0)
+    a.step(4)
+    b.step(4)
+    ga, gb = to_np(a.read("force")["force"]), to_np(b.read("force")["force"])
+    assert rel_linf(ga, gb) < 1e-6
+    f = O.init_equilibrium(p)
+    O.run(p, f, O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, 4, 0), 0, 3)
+    r = O.step(p, f, O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, 4, 0), 3)
+    assert rel_linf(ga, r["G"]) < 1e-5
+
+
+def test_error_paths(L):
+    wl = W.config("c0")
+    sim, _, _ = sim_for_workload(L, wl)
+    with pytest.raises(L.LbmError):   # a warm start needs parameters
+        sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 5, L.IBM_WARM_START)
+        sim.step(1)
+    with pytest.raises(L.LbmError):   # eps without the residual stop
+        sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 5, 0, 0.1)
+    with pytest.raises(L.LbmError):   # warm start with the unweighted sweep
+        sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 5,
+                       L.IBM_WARM_START | L.IBM_INNER_UNWEIGHTED)
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 5, 0)
+    sim.step(1)
+    with pytest.raises(L.LbmError):   # pairs need IBM_KEEP_FEATURES
+        sim.log_pairs()
+    with pytest.raises(L.LbmError):
+        sim.set_mlp(np.full(NP, np.nan, dtype=np.float32))
+
+
+# ----------------------------------------------------------- learned gain
+def test_learned_warm_start_saves_sweeps(L, LN):
+    """Trained on the GPU from plain runs of C1's geometry with other seeds,
+    the warm start reaches the plain method's residual threshold in fewer
+    sweeps on the canonical C1 (held out), and every step still meets the
+    threshold."""
+    import torch
+    train = [W.config("c1", seed=s) for s in (1, 2, 3)]
+    xs, ts = [], []
+    for wl in train:
+        x, t = LN.collect_pairs(wl, 60, n_iter=12, skip=5)
+        xs.append(x)
+        ts.append(t)
+    x = torch.cat(xs)
+    t = torch.cat(ts)
+    perm = torch.randperm(x.shape[0], generator=torch.Generator().manual_seed(0)).to(x.device)
+    x, t = x[perm].contiguous(), t[perm].contiguous()
+    net = LN.Network(W.mlp_init(5), max_batch=1024)
+    losses = net.train(x, t, batch=1024, epochs=8, lr=2e-3)
+    print("pairs", x.shape[0], "loss", losses[0], "->", losses[-1], flush=True)
+    assert losses[-1] < 0.5 * losses[0]
+    wl = W.config("c1")
+    # the plain method's threshold: median R_rel of its 5th sweep
+    plain5 = LN.surface_sim(wl, 0, 5)
+    hist = LN.residual_history(plain5, 30)
+    eps = float(np.median([rr[4] for _, rr in hist[5:]]))
+    plain5.close()
+    res = {}
+    for name, flags, th in (("plain", L.IBM_STOP_RESIDUAL, None),
+                            ("learned", L.IBM_STOP_RESIDUAL | L.IBM_WARM_START, net.numpy())):
+        sim = LN.surface_sim(wl, flags, 12, eps, theta=th)
+        h = LN.residual_history(sim, 30)[5:]
+        sweeps = np.array([n for n, _ in h])
+        final = np.array([rr[n - 1] for n, rr in h])
+        res[name] = (sweeps.mean(), final.max())
+        assert np.all((final <= eps * (1 + 1e-9)) | (sweeps == 12))
+        sim.close()
+    print("eps", eps, "plain sweeps", res["plain"], "learned sweeps", res["learned"], flush=True)
+    assert res["learned"][0] < res["plain"][0]
