@@ -29,6 +29,8 @@ _lib = None
 BC_PERIODIC, BC_BOUNCEBACK = 0, 1
 FORCE_GUO, FORCE_SHIFT = 0, 1
 IBM_INNER_UNWEIGHTED = 1
+IBM_STOP_RESIDUAL = 2
+IBM_WARM_START = 4
 
 
 def build(force: bool = False) -> str:
