@@ -129,9 +129,15 @@ enum {
                                 spread into U and the sweeps continue from it.
                                 Useful with IBM_STOP_RESIDUAL, valid alone;
                                 not with IBM_INNER_UNWEIGHTED.                */
-  IBM_KEEP_FEATURES = 8u     /* compute the features in every forcing so that
+  IBM_KEEP_FEATURES = 8u,    /* compute the features in every forcing so that
                                 ibm_log_pairs can export training pairs       */
+  IBM_MLP_FP32 = 16u         /* evaluate the warm-start network in FP32 on the
+                                vector units; default: BF16 operands on the
+                                matrix cores with FP32 accumulation           */
 };
+
+/* mlp_forward precision */
+enum { MLP_FP32 = 0, MLP_BF16 = 1 };
 
 /* Learned warm start: a per-point MLP 12 -> 64 -> 64 -> 64 -> 3 with SiLU
  * after each hidden layer.  Flat FP32 parameter layout (row-major, out x in):
@@ -258,7 +264,10 @@ lbm_status ibm_log_pairs(lbm_ctx* ctx, float* features, float* targets);
 lbm_status ibm_last_stats(lbm_ctx* ctx, ibm_stats* stats);
 
 /* Stateless MLP kernels on caller device memory, enqueued on `stream`:
- *   mlp_forward:   y[n][3] = MLP(theta; x[n][12]);
+ *   mlp_forward:   y[n][3] = MLP(theta; x[n][12]) in FP32 (precision
+ *                  MLP_FP32, workspace may be NULL) or with BF16 operands
+ *                  and FP32 accumulation on the matrix cores (MLP_BF16,
+ *                  workspace of at least mlp_workspace_size(1) bytes);
  *   mlp_loss_grad: loss = (1 / 3n) sum (y - t)^2 into loss_out (device
  *                  double[1]) and its gradient into grad (device float
  *                  [IBM_MLP_NPARAM]);
@@ -271,7 +280,7 @@ lbm_status ibm_last_stats(lbm_ctx* ctx, ibm_stats* stats);
  * workspace: device memory of mlp_workspace_size(batch) bytes. */
 size_t mlp_workspace_size(int64_t batch);
 lbm_status mlp_forward(const float* theta, int64_t n, const float* x, float* y,
-                       void* workspace, void* stream);
+                       int32_t precision, void* workspace, void* stream);
 lbm_status mlp_loss_grad(const float* theta, int64_t n, const float* x, const float* t,
                          float* grad, double* loss_out, void* workspace, void* stream);
 lbm_status mlp_train(float* theta, float* m, float* v, int64_t* step_t, int64_t n,

@@ -366,37 +366,45 @@ __device__ __forceinline__ void tile_origin(const PointGeom& pg, uint32_t t, int
 }
 
 // Velocity U = sum e f / rho (eq. 1) of the post-stream populations on the
-// flagged 4^3 blocks of every touched tile (the paper's lbm_u_start limited
-// to the cells the supports reach).  512 threads: one wave per 8x8 z-plane.
+// flagged 4^3 blocks (the paper's lbm_u_start limited to the cells the
+// supports reach).  One workgroup per row of force blocks (4 x 4 cell rows in
+// y, z along the whole x extent); threads run along x, so a wave's loads of a
+// population are consecutive words of one cell row (whole cache lines where
+// flagged blocks are contiguous) instead of 8-cell pieces of 8 rows.
+constexpr int MOM_WG = 256;
 template <int S>
-__global__ __launch_bounds__(TILE3) void k_moments_blocks(
+__global__ __launch_bounds__(MOM_WG) void k_moments_rows(
     const typename Store<S>::T* __restrict__ lat, const LatticeGeom g, PointGeom pg,
-    const uint32_t* __restrict__ touch_tiles, const uint32_t* __restrict__ meta,
     const uint8_t* __restrict__ bflag, float* __restrict__ U) {
-  const int64_t e = list_entry(meta[1]);
+  const int64_t e = list_entry((uint32_t)(pg.fblk[1] * pg.fblk[2]));
   if (e < 0) return;
-  int o[3];
-  tile_origin(pg, touch_tiles[e], o);
-  const int x = o[0] + (threadIdx.x & (TILE - 1));
-  const int y = o[1] + ((threadIdx.x >> TILE_SHIFT) & (TILE - 1));
-  const int z = o[2] + (threadIdx.x >> (2 * TILE_SHIFT));
-  if (x >= g.nx || y >= g.ny || z >= g.nz) return;
-  if (!bflag[fblock_of(g, x, y, z)]) return;
-  float f[Q];
-  gather_any<S>(lat, g, x, y, z, f);
-  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+  const int by = (int)(e % pg.fblk[1]), bz = (int)(e / pg.fblk[1]);
+  const uint8_t* frow = bflag + (int64_t)pg.fblk[0] * (by + (int64_t)pg.fblk[1] * bz);
+  int any = 0;
+  for (int bx = threadIdx.x; bx < pg.fblk[0]; bx += MOM_WG) any |= frow[bx];
+  if (!__syncthreads_or(any)) return;
+  for (int r = 0; r < FBLK * FBLK; ++r) {
+    const int y = FBLK * by + (r & (FBLK - 1)), z = FBLK * bz + (r >> FBLK_SHIFT);
+    if (y >= g.ny || z >= g.nz) continue;
+    for (int x = threadIdx.x; x < g.nx; x += MOM_WG) {
+      if (!frow[x >> FBLK_SHIFT]) continue;
+      float f[Q];
+      gather_any<S>(lat, g, x, y, z, f);
+      float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    drho += f[i];
-    jx += EX[i] * f[i];
-    jy += EY[i] * f[i];
-    jz += EZ[i] * f[i];
+      for (int i = 0; i < Q; ++i) {
+        drho += f[i];
+        jx += EX[i] * f[i];
+        jy += EY[i] * f[i];
+        jz += EZ[i] * f[i];
+      }
+      const float inv = 1.0f / (1.0f + drho);
+      const int64_t cell = (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
+      U[cell] = jx * inv;
+      U[g.ncell + cell] = jy * inv;
+      U[2 * g.ncell + cell] = jz * inv;
+    }
   }
-  const float inv = 1.0f / (1.0f + drho);
-  const int64_t cell = (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
-  U[cell] = jx * inv;
-  U[g.ncell + cell] = jy * inv;
-  U[2 * g.ncell + cell] = jz * inv;
 }
 
 // 1-D weights of Peskin's 4-point kernel (§3) for the taps floor(x)-1 ..
@@ -902,18 +910,19 @@ hipError_t launch_forcing(lbm_ctx* c) {
                                             c->start_own, c->sp_base, c->sp_frac, c->sp_ub,
                                             c->bflag, c->pt_partials, c->pt_partials + rs);
   LAUNCH_CHECK();
+  const unsigned mg = (unsigned)(((int64_t)pg.fblk[1] * pg.fblk[2] + 7) / 8 * 8);
   switch (c->p.storage) {
     case LBM_STORE_F16:
-      k_moments_blocks<LBM_STORE_F16><<<lg, TILE3, 0, st>>>(
-          (const _Float16*)c->lat[c->cur], c->geom, pg, c->touch_tiles, c->meta, c->bflag, c->U);
+      k_moments_rows<LBM_STORE_F16><<<mg, MOM_WG, 0, st>>>((const _Float16*)c->lat[c->cur], c->geom,
+                                                           pg, c->bflag, c->U);
       break;
     case LBM_STORE_BF16:
-      k_moments_blocks<LBM_STORE_BF16><<<lg, TILE3, 0, st>>>(
-          (const uint16_t*)c->lat[c->cur], c->geom, pg, c->touch_tiles, c->meta, c->bflag, c->U);
+      k_moments_rows<LBM_STORE_BF16><<<mg, MOM_WG, 0, st>>>((const uint16_t*)c->lat[c->cur], c->geom,
+                                                            pg, c->bflag, c->U);
       break;
     default:
-      k_moments_blocks<LBM_STORE_F32><<<lg, TILE3, 0, st>>>(
-          (const float*)c->lat[c->cur], c->geom, pg, c->touch_tiles, c->meta, c->bflag, c->U);
+      k_moments_rows<LBM_STORE_F32><<<mg, MOM_WG, 0, st>>>((const float*)c->lat[c->cur], c->geom, pg,
+                                                           c->bflag, c->U);
   }
   LAUNCH_CHECK();
   const int uw = (c->flags & IBM_INNER_UNWEIGHTED) ? SW_UNWEIGHTED : 0;
@@ -971,7 +980,11 @@ hipError_t launch_forcing(lbm_ctx* c) {
     k_resid_check<<<1, LBM_BLOCK, 0, st>>>(c->pt_partials + (2 + it) * rs, lg, c->resid_thr, it,
                                            last ? 1 : 0, use_thr, c->ctl);
     TRY(hipGetLastError());
-    if (it == 0 && feats) TRY(launch_features_warm(c, warm));
+    if (it == 0 && feats) {
+      const bool fp32 = (c->flags & IBM_MLP_FP32) != 0;
+      TRY(launch_features_warm(c, warm && fp32));
+      if (warm && !fp32) TRY(launch_warm_mfma(c));
+    }
     if (it == 0 && warm && !last) {
       TRY(sweep(0, SW_SPREAD_DU, c->ctl, nullptr));
       TRY(merge(false, c->ctl));

@@ -69,6 +69,7 @@ struct lbm_ctx {
   float* feat = nullptr;        // [max_points][12] features of the last forcing (sorted)
   float* vref = nullptr;        // [LBM_MAX_BODIES] reference speed per body
   float* theta = nullptr;       // [IBM_MLP_NPARAM] network parameters
+  void* theta_packed = nullptr; // BF16 matrix-core operands of the network
   uint32_t* ctl = nullptr;      // [4] residual stop: converged flag, sweeps run
   double* resid_thr = nullptr;  // [1] eps^2 sum s |u_b|^2
   float* boxbuf = nullptr;          // [max_boxes][3][11^3] spread boxes of owner tiles
@@ -125,3 +126,6 @@ hipError_t launch_export_points(lbm_ctx* c, double* x, float* ub, float* g, floa
 hipError_t launch_neighbours(lbm_ctx* c);
 hipError_t launch_features_warm(lbm_ctx* c, bool predict);
 hipError_t launch_export_pairs(lbm_ctx* c, float* feat, float* targets);
+hipError_t launch_mlp_pack(lbm_ctx* c);
+hipError_t launch_warm_mfma(lbm_ctx* c);
+constexpr size_t MLP_PACKED_BYTES = 22 * 64 * 16;  // 22 operands x 64 lanes x 8 BF16

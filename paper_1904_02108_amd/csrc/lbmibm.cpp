@@ -26,7 +26,7 @@ struct Plan {
   size_t elem, pop_stride, lat_bytes;
   // points
   size_t o_rest, o_body_of, o_key, o_rank, o_base, o_frac, o_ub, o_g, o_du, o_bodies, o_motion;
-  size_t o_nbr, o_g0, o_feat, o_vref, o_theta;
+  size_t o_nbr, o_g0, o_feat, o_vref, o_theta, o_packed;
   size_t o_box;
   int64_t max_boxes;
   // tiles
@@ -152,6 +152,7 @@ void make_plan(const lbm_params* p, Plan& pl) {
   pl.o_feat = pc.take(M * IBM_MLP_NFEAT * sizeof(float));
   pl.o_vref = pc.take((size_t)LBM_MAX_BODIES * sizeof(float));
   pl.o_theta = pc.take((size_t)IBM_MLP_NPARAM * sizeof(float));
+  pl.o_packed = pc.take(MLP_PACKED_BYTES);
   pl.size[LBM_BUF_POINTS] = pc.at;
 
   const size_t NT = (size_t)pl.ntiles;
@@ -354,6 +355,7 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->feat = (float*)(P + pl.o_feat);
   c->vref = (float*)(P + pl.o_vref);
   c->theta = (float*)(P + pl.o_theta);
+  c->theta_packed = (void*)(P + pl.o_packed);
   c->boxbuf = (float*)(F + pl.o_box);
   c->max_boxes = pl.max_boxes;
   char* T = (char*)bufs[LBM_BUF_TILES];
@@ -429,7 +431,8 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
     return fail(c, LBM_ERR_ARG, "nbodies must be in [1, 65536]");
   if (n_iter < 1 || n_iter > c->p.max_iter)
     return fail(c, LBM_ERR_ARG, "n_iter must be in [1, max_iter]");
-  const uint32_t known = IBM_INNER_UNWEIGHTED | IBM_STOP_RESIDUAL | IBM_WARM_START | IBM_KEEP_FEATURES;
+  const uint32_t known =
+      IBM_INNER_UNWEIGHTED | IBM_STOP_RESIDUAL | IBM_WARM_START | IBM_KEEP_FEATURES | IBM_MLP_FP32;
   if (flags & ~known) return fail(c, LBM_ERR_ARG, "unknown flags");
   if ((flags & IBM_WARM_START) && (flags & IBM_INNER_UNWEIGHTED))
     return fail(c, LBM_ERR_ARG, "IBM_WARM_START needs the weighted inner sweep");
@@ -521,6 +524,7 @@ lbm_status ibm_set_mlp(lbm_ctx* c, const float* theta) {
   for (int i = 0; i < IBM_MLP_NPARAM; ++i)
     if (!std::isfinite(theta[i])) return fail(c, LBM_ERR_ARG, "theta must be finite");
   HIP_TRY(c, hipMemcpyAsync(c->theta, theta, sizeof(float) * IBM_MLP_NPARAM, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_mlp_pack(c));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->theta_set = true;
   return LBM_OK;

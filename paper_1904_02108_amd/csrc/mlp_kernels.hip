@@ -81,6 +81,205 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ t
 }
 
 // ---------------------------------------------------------------------------
+// BF16 matrix-core form of the forward pass (FP32 accumulation), for batches
+// of points: one wave evaluates 32 points with 22 MFMA 32x32x16 operations.
+// Each layer is computed transposed, H_out^T[64 x 32] = W[64 x K] H_in^T[K x 32],
+// so a lane's accumulator registers (one point, 16 hidden units per 32-unit
+// block) are directly the B operand of the next layer once converted to
+// BF16.  The K order inside a chunk is therefore the accumulator's row order;
+// the packed weights (A operands) use the same order, so the sum over K is
+// unchanged.  Accumulator register r of lane l (half h = l / 32) holds row
+// 8 (r / 4) + 4 h + r % 4 of its 32-row block; the A and B operands hold K
+// elements 8 h .. 8 h + 7 of a 16-wide chunk (row / column l % 32).
+// Packed operand list (64 lanes x 8 BF16 each):
+//   0-1: layer 1, output block b;       2-9: layer 2, (b_out, b_in, chunk);
+//   10-17: layer 3, same;               18-21: layer 4 (rows 0-2), (b_in, chunk).
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int N_MFMA = 22;
+
+__device__ __forceinline__ uint32_t bf16_bits(float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (u >> 16) | 0x40u;
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return u >> 16;
+}
+
+__device__ __forceinline__ bf16x8 pack8(const float* v) {
+  u32x4 w;
+  w.x = bf16_bits(v[0]) | (bf16_bits(v[1]) << 16);
+  w.y = bf16_bits(v[2]) | (bf16_bits(v[3]) << 16);
+  w.z = bf16_bits(v[4]) | (bf16_bits(v[5]) << 16);
+  w.w = bf16_bits(v[6]) | (bf16_bits(v[7]) << 16);
+  return __builtin_bit_cast(bf16x8, w);
+}
+
+// Hidden unit held by element e of the B operand of chunk c of input block b
+// in lane half h (the accumulator row of register 8 c + e).
+__device__ __forceinline__ int chunk_unit(int b, int c, int h, int e) {
+  return 32 * b + 16 * c + 8 * (e >> 2) + 4 * h + (e & 3);
+}
+
+// theta (FP32 flat layout) -> packed[N_MFMA][64] A operands.
+__global__ __launch_bounds__(64) void k_mlp_pack(const float* __restrict__ theta,
+                                                 u32x4* __restrict__ packed) {
+  const int m = blockIdx.x, l = threadIdx.x, i = l & 31, h = l >> 5;
+  float w[8];
+  for (int e = 0; e < 8; ++e) {
+    float v = 0.0f;
+    if (m < 2) {
+      const int k = 8 * h + e;
+      v = k < NIN ? theta[OFF_W1 + (32 * m + i) * NIN + k] : 0.0f;
+    } else if (m < 18) {
+      const int q = (m - 2) & 7, off = m < 10 ? OFF_W2 : OFF_W3;
+      const int bo = q >> 2, bi = (q >> 1) & 1, c = q & 1;
+      v = theta[off + (32 * bo + i) * NH + chunk_unit(bi, c, h, e)];
+    } else {
+      const int q = m - 18, bi = q >> 1, c = q & 1;
+      v = i < NOUT ? theta[OFF_W4 + i * NH + chunk_unit(bi, c, h, e)] : 0.0f;
+    }
+    w[e] = v;
+  }
+  const bf16x8 a = pack8(w);
+  packed[m * 64 + l] = __builtin_bit_cast(u32x4, a);
+}
+
+struct MfmaWeights {
+  u32x4 A[N_MFMA * 64];
+  float bias[3 * NH + NOUT];
+};
+
+__device__ __forceinline__ void load_mfma_weights(const u32x4* __restrict__ packed,
+                                                  const float* __restrict__ theta, MfmaWeights& W) {
+  for (int i = threadIdx.x; i < N_MFMA * 64; i += blockDim.x) W.A[i] = packed[i];
+  for (int i = threadIdx.x; i < NH; i += blockDim.x) {
+    W.bias[i] = theta[OFF_B1 + i];
+    W.bias[NH + i] = theta[OFF_B2 + i];
+    W.bias[2 * NH + i] = theta[OFF_B3 + i];
+  }
+  if (threadIdx.x < NOUT) W.bias[3 * NH + threadIdx.x] = theta[OFF_B4 + threadIdx.x];
+  __syncthreads();
+}
+
+// Bias and SiLU on the two 32-row accumulator blocks of a hidden layer, then
+// conversion to the four B operands of the next layer.
+__device__ __forceinline__ void hidden_to_operands(const f32x16 acc[2], const float* bias, int h,
+                                                   bf16x8 B[4]) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    float a[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a[r] = silu(acc[b][r] + bias[32 * b + 8 * (r >> 2) + 4 * h + (r & 3)]);
+    B[2 * b] = pack8(a);
+    B[2 * b + 1] = pack8(a + 8);
+  }
+}
+
+// Forward pass of the 32 points of one wave: x8 holds features 8 h .. 8 h + 7
+// of point l % 32 (zeros beyond 12); on lanes 0-31 y receives the outputs.
+__device__ __forceinline__ void mlp_group_mfma(const MfmaWeights& W, const float x8[8], float y[3]) {
+  const int l = __lane_id(), h = l >> 5;
+  const f32x16 zero = {};
+  bf16x8 B[4];
+  f32x16 acc[2];
+  const bf16x8 X = pack8(x8);
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+    acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+        __builtin_bit_cast(bf16x8, W.A[b * 64 + l]), X, zero, 0, 0, 0);
+  hidden_to_operands(acc, W.bias, h, B);
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer) {
+    const int m0 = 2 + 8 * layer;
+#pragma unroll
+    for (int bo = 0; bo < 2; ++bo) {
+      f32x16 a = zero;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        a = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            __builtin_bit_cast(bf16x8, W.A[(m0 + 4 * bo + q) * 64 + l]), B[q], a, 0, 0, 0);
+      acc[bo] = a;
+    }
+    hidden_to_operands(acc, W.bias + NH * (layer + 1), h, B);
+  }
+  f32x16 o = zero;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, W.A[(18 + q) * 64 + l]),
+                                                B[q], o, 0, 0, 0);
+  y[0] = o[0] + W.bias[3 * NH];
+  y[1] = o[1] + W.bias[3 * NH + 1];
+  y[2] = o[2] + W.bias[3 * NH + 2];
+}
+
+// Features of point k, elements 8 h .. 8 h + 7 (zeros past the 12th).
+__device__ __forceinline__ void load_x8(const float* __restrict__ x, int64_t k, int64_t n, int h,
+                                        float x8[8]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int f = 8 * h + e;
+    x8[e] = (k < n && f < NIN) ? x[k * NIN + f] : 0.0f;
+  }
+}
+
+constexpr int MFMA_WG = 256;  // 4 waves, 32 points each per group
+
+__global__ __launch_bounds__(MFMA_WG) void k_mlp_forward_mfma(const u32x4* __restrict__ packed,
+                                                              const float* __restrict__ theta,
+                                                              int64_t n, const float* __restrict__ x,
+                                                              float* __restrict__ y) {
+  __shared__ MfmaWeights W;
+  load_mfma_weights(packed, theta, W);
+  const int l = __lane_id(), h = l >> 5, wave = threadIdx.x >> 6;
+  const int64_t groups = (n + 31) / 32;
+  for (int64_t g = (int64_t)blockIdx.x * (MFMA_WG / 64) + wave; g < groups;
+       g += (int64_t)gridDim.x * (MFMA_WG / 64)) {
+    const int64_t k = 32 * g + (l & 31);
+    float x8[8], yo[3];
+    load_x8(x, k, n, h, x8);
+    mlp_group_mfma(W, x8, yo);
+    if (h == 0 && k < n) {
+      y[k * NOUT] = yo[0];
+      y[k * NOUT + 1] = yo[1];
+      y[k * NOUT + 2] = yo[2];
+    }
+  }
+}
+
+// Warm start from the stored features (sorted order): du = s v_ref y, unless
+// the forcing has already converged (*gate).
+__global__ __launch_bounds__(MFMA_WG) void k_warm_mfma(
+    const u32x4* __restrict__ packed, const float* __restrict__ theta, int64_t n,
+    const float* __restrict__ feat, const int4* __restrict__ sp_base,
+    const float4* __restrict__ sp_frac, const int32_t* __restrict__ body_of,
+    const float* __restrict__ vref, const uint32_t* __restrict__ gate, float4* __restrict__ sp_du) {
+  __shared__ MfmaWeights W;
+  if (*gate) return;
+  load_mfma_weights(packed, theta, W);
+  const int l = __lane_id(), h = l >> 5, wave = threadIdx.x >> 6;
+  const int64_t groups = (n + 31) / 32;
+  for (int64_t g = (int64_t)blockIdx.x * (MFMA_WG / 64) + wave; g < groups;
+       g += (int64_t)gridDim.x * (MFMA_WG / 64)) {
+    const int64_t k = 32 * g + (l & 31);
+    float x8[8], yo[3];
+    load_x8(feat, k, n, h, x8);
+    mlp_group_mfma(W, x8, yo);
+    if (h == 0 && k < n) {
+      const float sv = sp_frac[k].w * vref[body_of[sp_base[k].w]];
+      sp_du[k] = make_float4(yo[0] * sv, yo[1] * sv, yo[2] * sv, 0.0f);
+    }
+  }
+}
+
+unsigned mfma_grid(int64_t n) {
+  const int64_t groups = (n + 31) / 32;
+  const int64_t wgs = (groups + MFMA_WG / 64 - 1) / (MFMA_WG / 64);
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(wgs, 2048));
+}
+
+// ---------------------------------------------------------------------------
 // Neighbour lists N(k): up to 16 points of k's body nearest to k, at
 // Euclidean distance < 2, ordered by (distance, caller index), stored by
 // caller index (-1 pads).  Distances are taken between the rest positions
@@ -489,6 +688,19 @@ hipError_t launch_features_warm(lbm_ctx* c, bool predict) {
   return hipGetLastError();
 }
 
+hipError_t launch_mlp_pack(lbm_ctx* c) {
+  k_mlp_pack<<<N_MFMA, 64, 0, c->stream>>>(c->theta, (u32x4*)c->theta_packed);
+  return hipGetLastError();
+}
+
+hipError_t launch_warm_mfma(lbm_ctx* c) {
+  if (c->npts == 0) return hipSuccess;
+  k_warm_mfma<<<mfma_grid(c->npts), MFMA_WG, 0, c->stream>>>(
+      (const u32x4*)c->theta_packed, c->theta, c->npts, c->feat, c->sp_base, c->sp_frac,
+      c->body_of, c->vref, c->ctl, c->sp_du);
+  return hipGetLastError();
+}
+
 hipError_t launch_export_pairs(lbm_ctx* c, float* feat, float* targets) {
   const unsigned nb = (unsigned)((c->npts + 255) / 256);
   if (nb == 0) return hipSuccess;
@@ -512,12 +724,20 @@ size_t mlp_workspace_size(int64_t batch) {
   return s;
 }
 
-lbm_status mlp_forward(const float* theta, int64_t n, const float* x, float* y, void* workspace,
-                       void* stream) {
-  (void)workspace;
+lbm_status mlp_forward(const float* theta, int64_t n, const float* x, float* y, int32_t precision,
+                       void* workspace, void* stream) {
   if (!theta || n < 0 || (n > 0 && (!x || !y))) return LBM_ERR_ARG;
+  if (precision != MLP_FP32 && precision != MLP_BF16) return LBM_ERR_ARG;
+  if (precision == MLP_BF16 && !workspace) return LBM_ERR_ARG;
   if (n == 0) return LBM_OK;
-  k_mlp_forward<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(theta, n, x, y);
+  hipStream_t st = (hipStream_t)stream;
+  if (precision == MLP_FP32) {
+    k_mlp_forward<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(theta, n, x, y);
+  } else {
+    u32x4* packed = (u32x4*)workspace;
+    k_mlp_pack<<<N_MFMA, 64, 0, st>>>(theta, packed);
+    k_mlp_forward_mfma<<<mfma_grid(n), MFMA_WG, 0, st>>>(packed, theta, n, x, y);
+  }
   return hipGetLastError() == hipSuccess ? LBM_OK : LBM_ERR_HIP;
 }
 

@@ -29,7 +29,9 @@ LBM_BC_PERIODIC, LBM_BC_BOUNCEBACK = 0, 1
 LBM_STORE_F32, LBM_STORE_F16, LBM_STORE_BF16 = 0, 1, 2
 LBM_FORCE_GUO, LBM_FORCE_SHIFT = 0, 1
 LBM_NBUF = 5
-IBM_INNER_UNWEIGHTED, IBM_STOP_RESIDUAL, IBM_WARM_START, IBM_KEEP_FEATURES = 1, 2, 4, 8
+IBM_INNER_UNWEIGHTED, IBM_STOP_RESIDUAL, IBM_WARM_START, IBM_KEEP_FEATURES, IBM_MLP_FP32 = (
+    1, 2, 4, 8, 16)
+MLP_FP32, MLP_BF16 = 0, 1
 IBM_MLP_NPARAM, IBM_MLP_NFEAT, IBM_MLP_NNBR = 9347, 12, 16
 LBM_MAX_ITER = 64
 (LBM_F_RHO, LBM_F_VEL, LBM_F_FORCE, LBM_F_POPS, LBM_F_PT_X, LBM_F_PT_UB, LBM_F_PT_G, LBM_F_PT_DU,
@@ -90,8 +92,8 @@ _lib.ibm_log_pairs.argtypes = [_C, ct.c_void_p, ct.c_void_p]
 _lib.ibm_last_stats.argtypes = [_C, ct.POINTER(ibm_stats)]
 _lib.mlp_workspace_size.argtypes = [ct.c_int64]
 _lib.mlp_workspace_size.restype = ct.c_size_t
-_lib.mlp_forward.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p,
-                             ct.c_void_p]
+_lib.mlp_forward.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int32,
+                             ct.c_void_p, ct.c_void_p]
 _lib.mlp_loss_grad.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                ct.c_void_p, ct.c_void_p, ct.c_void_p]
 _lib.mlp_train.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.POINTER(ct.c_int64),
@@ -207,9 +209,9 @@ def mlp_workspace_size(batch):
     return int(_lib.mlp_workspace_size(int(batch)))
 
 
-def mlp_forward(theta_ptr, n, x_ptr, y_ptr, workspace_ptr, stream_ptr):
+def mlp_forward(theta_ptr, n, x_ptr, y_ptr, precision, workspace_ptr, stream_ptr):
     _check(_lib.mlp_forward(ct.c_void_p(theta_ptr), int(n), ct.c_void_p(x_ptr), ct.c_void_p(y_ptr),
-                            ct.c_void_p(workspace_ptr), ct.c_void_p(stream_ptr)))
+                            int(precision), ct.c_void_p(workspace_ptr), ct.c_void_p(stream_ptr)))
 
 
 def mlp_loss_grad(theta_ptr, n, x_ptr, t_ptr, grad_ptr, loss_ptr, workspace_ptr, stream_ptr):

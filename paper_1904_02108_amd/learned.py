@@ -51,10 +51,10 @@ class Network:
                                      lr, ws.data_ptr(), self._stream())
         return losses
 
-    def forward(self, x):
+    def forward(self, x, precision=L.MLP_FP32):
         y = self.torch.empty((x.shape[0], 3), dtype=self.torch.float32, device=self.device)
-        L.mlp_forward(self.theta.data_ptr(), x.shape[0], x.data_ptr(), y.data_ptr(), 0,
-                      self._stream())
+        L.mlp_forward(self.theta.data_ptr(), x.shape[0], x.data_ptr(), y.data_ptr(), precision,
+                      self._workspace(1).data_ptr(), self._stream())
         return y
 
     def loss_grad(self, x, t):
@@ -80,12 +80,14 @@ def surface_sim(wl, flags, n_iter, eps=0.0, theta=None, device="cuda"):
     return sim
 
 
-def collect_pairs(wl, n_steps, n_iter=10, skip=0, flags=0, eps=0.0, device="cuda"):
+def collect_pairs(wl, n_steps, n_iter=10, skip=0, flags=0, eps=0.0, device="cuda", limit=50.0):
     """Training pairs from a plain run of ``wl``: the first-sweep features
     and the final correction of every step after ``skip`` warm-up steps.
     Returns device tensors x [m,12], t [m,3] with m = n_points * (steps
-    kept): a run whose flow stops being finite keeps only the steps before
-    the first non-finite pair."""
+    kept).  Features and targets are velocities over the body's reference
+    speed, of order one while the flow is sound; a run keeps only the steps
+    before the first one with a value that is not finite or exceeds
+    ``limit`` in magnitude (a diverging flow)."""
     import torch
     sim = surface_sim(wl, flags | L.IBM_KEEP_FEATURES, n_iter, eps, device=device)
     n = wl.n_points
@@ -98,8 +100,9 @@ def collect_pairs(wl, n_steps, n_iter=10, skip=0, flags=0, eps=0.0, device="cuda
         sim.log_pairs(x[k * n:(k + 1) * n], t[k * n:(k + 1) * n])
     torch.cuda.synchronize(device)
     sim.close()
-    ok = (torch.isfinite(x.view(n_steps, -1)).all(dim=1) &
-          torch.isfinite(t.view(n_steps, -1)).all(dim=1)).cpu().numpy()
+    xv, tv = x.view(n_steps, -1), t.view(n_steps, -1)
+    ok = (torch.isfinite(xv).all(dim=1) & torch.isfinite(tv).all(dim=1) &
+          (xv.abs().amax(dim=1) <= limit) & (tv.abs().amax(dim=1) <= limit)).cpu().numpy()
     good = int(np.argmin(ok)) if not ok.all() else n_steps
     return x[:good * n], t[:good * n]
 

@@ -50,6 +50,24 @@ def test_mlp_forward(LN, n):
     assert rel_linf(y, ref) < 1e-5
 
 
+@pytest.mark.parametrize("n", [1, 31, 33, 5000])
+def test_mlp_forward_bf16(L, LN, n):
+    """Matrix-core form (BF16 operands, FP32 accumulation): within the error
+    of rounding inputs, weights and activations to 8 significant bits."""
+    rng = np.random.default_rng(50 + n)
+    th = W.mlp_init(60 + n, scale=1.5)
+    th[-3:] = rng.normal(size=3)
+    x = rng.normal(size=(n, 12)).astype(np.float32)
+    net = LN.Network(th)
+    y = to_np(net.forward(_dev(x), precision=L.MLP_BF16))
+    ref = O.mlp_forward(_f64(th), _f64(x))
+    err = rel_linf(y, ref)
+    print("bf16 forward rel err", err, flush=True)
+    assert err < 2e-2
+    # and it is the BF16 path: FP32 gives a far smaller error
+    assert rel_linf(to_np(net.forward(_dev(x))), ref) < 1e-5
+
+
 @pytest.mark.parametrize("n", [1, 300, 777])
 def test_mlp_loss_grad(LN, n):
     """Loss and gradient of the mean squared error against the oracle's
@@ -182,7 +200,7 @@ def test_warm_start_parity(L):
     sweeps run, the correction and the force match the oracle."""
     wl = W.config("c0")
     th = W.mlp_init(7, scale=0.5)
-    flags = L.IBM_WARM_START | L.IBM_STOP_RESIDUAL
+    flags = L.IBM_WARM_START | L.IBM_STOP_RESIDUAL | L.IBM_MLP_FP32
     p = O.params(wl.shape, wl.tau, bc=wl.bc)
     # the threshold half way between two residual levels of the oracle's
     # warm-started step
@@ -198,7 +216,7 @@ def test_warm_start_parity(L):
     # one with the threshold
     sim, _, _ = sim_for_workload(L, wl)
     sim.set_mlp(th)
-    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 8, L.IBM_WARM_START)
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 8, L.IBM_WARM_START | L.IBM_MLP_FP32)
     sim.step(5)
     sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 8, flags, eps)
     st = sim.force_iterate(stats=True)
@@ -212,6 +230,25 @@ def test_warm_start_parity(L):
     out = sim.read("force", "pt_du", "vel")
     assert rel_linf(to_np(out["pt_du"]), r["du"]) < 1e-5
     assert rel_linf(to_np(out["force"]), r["G"]) < 1e-5
+
+
+def test_warm_start_bf16_against_fp32(L):
+    """The default matrix-core network in the warm start against the FP32
+    one (which matches the oracle): C0, 6 steps of 6 sweeps."""
+    wl = W.config("c0")
+    th = W.mlp_init(8, scale=0.7)
+    th[-3:] = [0.02, -0.01, 0.03]
+    out = {}
+    for name, flags in (("bf16", L.IBM_WARM_START), ("fp32", L.IBM_WARM_START | L.IBM_MLP_FP32)):
+        sim, _, _ = sim_for_workload(L, wl)
+        sim.set_mlp(th)
+        sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 6, flags)
+        sim.step(6)
+        out[name] = {k: to_np(v) for k, v in sim.read("force", "pt_du").items()}
+    e_du = rel_linf(out["bf16"]["pt_du"], out["fp32"]["pt_du"])
+    e_G = rel_linf(out["bf16"]["force"], out["fp32"]["force"])
+    print("bf16 vs fp32 warm start: du", e_du, "G", e_G, flush=True)
+    assert 0 < e_du < 2e-2 and e_G < 2e-2
 
 
 def test_warm_start_zero_network(L):
