@@ -102,7 +102,7 @@ def copy_bandwidth(torch, nbytes, reps=5):
             "GBs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
-def learned_leg(torch, L, W, n_pairs_steps=150, epochs=10, eval_steps=40, warm=5):
+def learned_leg(torch, L, W, name="c1", n_pairs_steps=150, epochs=10, eval_steps=40, warm=5):
     """C4: the warm-start network trained on the GPU from plain runs of the
     single-propeller geometry with other seeds (1-8), then the canonical
     single-propeller case (seed 0, held out) run three ways: plain with a
@@ -115,7 +115,7 @@ def learned_leg(torch, L, W, n_pairs_steps=150, epochs=10, eval_steps=40, warm=5
     t0 = time.perf_counter()
     xs, ts, kept = [], [], []
     for seed in range(1, 9):
-        wl_s = W.config("c1", seed=seed)
+        wl_s = W.config(name, seed=seed)
         x, t = LN.collect_pairs(wl_s, n_pairs_steps, n_iter=12, skip=5)
         kept.append(int(x.shape[0]) // wl_s.n_points)
         xs.append(x)
@@ -133,7 +133,7 @@ def learned_leg(torch, L, W, n_pairs_steps=150, epochs=10, eval_steps=40, warm=5
     t_train = time.perf_counter() - t0
     n_pairs = int(x.shape[0])
     del x, t, perm
-    wl = W.config("c1")
+    wl = W.config(name)
     sim = LN.surface_sim(wl, 0, 5)
     hist = LN.residual_history(sim, 40)
     eps = float(np.median([rr[4] for _, rr in hist[warm:]]))
@@ -175,7 +175,8 @@ def learned_leg(torch, L, W, n_pairs_steps=150, epochs=10, eval_steps=40, warm=5
         sim.close()
     pe, le = variants["plain_eps"], variants["learned_eps"]
     return {
-        "workload": "c1 (seed 0, held out); training pairs from c1 seeds 1-8",
+        "workload": "%s (seed 0, held out, %d points); training pairs from %s seeds 1-8"
+                    % (name, wl.n_points, name),
         "eps_resid_rel": eps,
         "train_pairs": n_pairs, "steps_kept_per_seed": kept, "epochs": epochs, "loss_per_epoch": [float(v) for v in losses],
         "s_collect": round(t_collect, 2), "s_train": round(t_train, 2),
@@ -192,7 +193,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2_dense", choices=["c0", "c1", "c2", "c2_dense"])
+    ap.add_argument("--workload", default="c2_dense", choices=["c0", "c1", "c1_dense", "c2", "c2_dense"])
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--forcing", default="guo", choices=["guo", "shift"])
     ap.add_argument("--cpu-steps", type=int, default=1)
@@ -279,8 +280,10 @@ def main():
     del sim
     torch.cuda.empty_cache()
     if not args.no_learned:
-        out["learned"] = learned_leg(torch, L, W)
-        torch.cuda.empty_cache()
+        out["learned"] = {}
+        for name, n_steps in (("c1", 150), ("c1_dense", 60)):
+            out["learned"][name] = learned_leg(torch, L, W, name, n_pairs_steps=n_steps)
+            torch.cuda.empty_cache()
     if args.copy_calibration:
         out["copy_calibration"] = copy_bandwidth(torch, bpc * wl.n_cells // 2)
     if not args.no_cpu_baseline and args.cpu_steps > 0:

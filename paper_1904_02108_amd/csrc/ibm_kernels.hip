@@ -203,98 +203,143 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_point_count(
   }
 }
 
-// Pass 2 (one workgroup): exclusive scan of the owner counts, the compact
-// lists of tiles that own points / are touched (with each owner tile's slot
-// in its list), and clearing of the counters and force-block flags for this
-// step.  Tiles are taken in chunks
-// of SCAN_THREADS * SCAN_PER; each thread owns SCAN_PER consecutive tiles,
-// waves scan their thread totals with shuffles, one wave scans the wave
-// totals, and a running carry joins the chunks.
-constexpr int SCAN_THREADS = 1024;
-constexpr int SCAN_PER = 16;
-constexpr int SCAN_WAVES = SCAN_THREADS / 64;
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(
-    uint32_t* __restrict__ cnt_own, uint32_t* __restrict__ cnt_touch,
-    uint32_t* __restrict__ start_own, int32_t* __restrict__ own_slot,
-    uint32_t* __restrict__ own_tiles, uint32_t* __restrict__ touch_tiles,
-    uint32_t* __restrict__ meta, uint32_t* __restrict__ bflag_words, int64_t nbflag_words,
-    int64_t ntiles) {
-  __shared__ uint32_t wtot[3][SCAN_WAVES];
-  __shared__ uint32_t carry[3];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid < 3) carry[tid] = 0u;
+// Pass 2: exclusive scan of the owner counts and the compact lists of tiles
+// that own points / are touched (with each owner tile's slot in its list),
+// in three launches: chunk totals, a scan of the chunk totals (which also
+// writes the list lengths, to the device and to pinned host memory for the
+// next forcing's grid sizes), and the chunk rescans that write the outputs
+// and clear the counters and this step's force-block flags.  A chunk is
+// SCAN_WG threads x SCAN_PER consecutive tiles (the count arrays are padded
+// with zeros to whole chunks).
+constexpr int SCAN_WG = 256, SCAN_PER = 8, SCAN_CHUNK = SCAN_WG * SCAN_PER;
+constexpr int SCAN_WAVES = SCAN_WG / 64;
+
+__device__ __forceinline__ void load_counts(const uint32_t* __restrict__ cnt_own,
+                                            const uint32_t* __restrict__ cnt_touch, int64_t t0,
+                                            uint32_t a[SCAN_PER], uint32_t b[SCAN_PER],
+                                            uint32_t s[3]) {
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; j += 4) {
+    const uint4 va = *reinterpret_cast<const uint4*>(cnt_own + t0 + j);
+    const uint4 vb = *reinterpret_cast<const uint4*>(cnt_touch + t0 + j);
+    a[j] = va.x; a[j + 1] = va.y; a[j + 2] = va.z; a[j + 3] = va.w;
+    b[j] = vb.x; b[j + 1] = vb.y; b[j + 2] = vb.z; b[j + 3] = vb.w;
+  }
+  s[0] = s[1] = s[2] = 0u;
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) {
+    s[0] += a[j];
+    s[1] += a[j] ? 1u : 0u;
+    s[2] += b[j] ? 1u : 0u;
+  }
+}
+
+// Workgroup-wide exclusive scan of three values per thread; tot: the sums.
+template <int NW>
+__device__ __forceinline__ void block_scan3(const uint32_t s[3], uint32_t ex[3], uint32_t tot[3]) {
+  __shared__ uint32_t wtot[3][NW];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t inc[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    uint32_t v = s[q];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t u = __shfl_up(v, off, 64);
+      if (lane >= off) v += u;
+    }
+    inc[q] = v;
+    if (lane == 63) wtot[q][wv] = v;
+  }
   __syncthreads();
-  for (int64_t c0 = 0; c0 < ntiles; c0 += (int64_t)SCAN_THREADS * SCAN_PER) {
-    const int64_t t0 = c0 + (int64_t)tid * SCAN_PER;
-    uint32_t a[SCAN_PER], b[SCAN_PER];
-    // the count arrays are padded with zeros to a whole number of chunks
 #pragma unroll
-    for (int j = 0; j < SCAN_PER; j += 4) {
-      const uint4 va = *reinterpret_cast<const uint4*>(cnt_own + t0 + j);
-      const uint4 vb = *reinterpret_cast<const uint4*>(cnt_touch + t0 + j);
-      a[j] = va.x; a[j + 1] = va.y; a[j + 2] = va.z; a[j + 3] = va.w;
-      b[j] = vb.x; b[j + 1] = vb.y; b[j + 2] = vb.z; b[j + 3] = vb.w;
+  for (int q = 0; q < 3; ++q) {
+    uint32_t base = 0u, all = 0u;
+    for (int w = 0; w < NW; ++w) {
+      base += w < wv ? wtot[q][w] : 0u;
+      all += wtot[q][w];
     }
-    uint32_t s[3] = {0u, 0u, 0u};
+    ex[q] = base + inc[q] - s[q];
+    tot[q] = all;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(SCAN_WG) void k_scan_totals(const uint32_t* __restrict__ cnt_own,
+                                                         const uint32_t* __restrict__ cnt_touch,
+                                                         uint32_t* __restrict__ chunk) {
+  const int64_t t0 = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+  uint32_t a[SCAN_PER], b[SCAN_PER], s[3], ex[3], tot[3];
+  load_counts(cnt_own, cnt_touch, t0, a, b, s);
+  block_scan3<SCAN_WAVES>(s, ex, tot);
+  if (threadIdx.x < 3) chunk[3 * blockIdx.x + threadIdx.x] = tot[threadIdx.x];
+}
+
+constexpr int SCAN2_WG = 1024;
+__global__ __launch_bounds__(SCAN2_WG) void k_scan_chunks(uint32_t* __restrict__ chunk, int64_t nch,
+                                                          uint32_t* __restrict__ start_own,
+                                                          int64_t ntiles, uint32_t* __restrict__ meta,
+                                                          uint32_t* __restrict__ meta_host) {
+  __shared__ uint32_t carry[3];
+  if (threadIdx.x < 3) carry[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < nch; c0 += SCAN2_WG) {
+    const int64_t c = c0 + threadIdx.x;
+    uint32_t s[3], ex[3], tot[3];
 #pragma unroll
-    for (int j = 0; j < SCAN_PER; ++j) {
-      s[0] += a[j];
-      s[1] += a[j] ? 1u : 0u;
-      s[2] += b[j] ? 1u : 0u;
-    }
-    uint32_t inc[3];
+    for (int q = 0; q < 3; ++q) s[q] = c < nch ? chunk[3 * c + q] : 0u;
+    block_scan3<SCAN2_WG / 64>(s, ex, tot);
+    if (c < nch)
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      uint32_t v = s[q];
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t u = __shfl_up(v, off, 64);
-        if (lane >= off) v += u;
-      }
-      inc[q] = v;
-      if (lane == 63) wtot[q][wv] = v;
-    }
+      for (int q = 0; q < 3; ++q) chunk[3 * c + q] = carry[q] + ex[q];
     __syncthreads();
-    if (wv == 0) {
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        uint32_t v = lane < SCAN_WAVES ? wtot[q][lane] : 0u;
-#pragma unroll
-        for (int off = 1; off < SCAN_WAVES; off <<= 1) {
-          const uint32_t u = __shfl_up(v, off, 64);
-          if (lane >= off) v += u;
-        }
-        if (lane < SCAN_WAVES) wtot[q][lane] = v;  // inclusive over waves
-      }
-    }
-    __syncthreads();
-    uint32_t run[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-      run[q] = carry[q] + (wv ? wtot[q][wv - 1] : 0u) + inc[q] - s[q];
-#pragma unroll
-    for (int j = 0; j < SCAN_PER; ++j) {
-      const int64_t t = t0 + j;
-      if (t < ntiles) {
-        start_own[t] = run[0];
-        own_slot[t] = a[j] ? (int32_t)run[1] : -1;
-        if (a[j]) own_tiles[run[1]++] = (uint32_t)t;
-        if (b[j]) touch_tiles[run[2]++] = (uint32_t)t;
-        run[0] += a[j];
-        cnt_own[t] = 0u;
-        cnt_touch[t] = 0u;
-      }
-    }
-    __syncthreads();
-    if (tid < 3) carry[tid] += wtot[tid][SCAN_WAVES - 1];
+    if (threadIdx.x < 3) carry[threadIdx.x] += tot[threadIdx.x];
     __syncthreads();
   }
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     start_own[ntiles] = carry[0];
     meta[0] = carry[1];
     meta[1] = carry[2];
+    if (meta_host) {  // zero-copy: a plain (vector) store to pinned host memory
+      meta_host[0] = carry[1];
+      meta_host[1] = carry[2];
+    }
   }
-  for (int64_t w = tid; w < nbflag_words; w += SCAN_THREADS) bflag_words[w] = 0u;
+}
+
+__global__ __launch_bounds__(SCAN_WG) void k_scan_write(
+    uint32_t* __restrict__ cnt_own, uint32_t* __restrict__ cnt_touch,
+    const uint32_t* __restrict__ chunk, int64_t ntiles, uint32_t* __restrict__ start_own,
+    int32_t* __restrict__ own_slot, uint32_t* __restrict__ own_tiles,
+    uint32_t* __restrict__ touch_tiles, uint32_t* __restrict__ bflag_words, int64_t nbflag_words) {
+  const int64_t t0 = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+  uint32_t a[SCAN_PER], b[SCAN_PER], s[3], ex[3], tot[3];
+  load_counts(cnt_own, cnt_touch, t0, a, b, s);
+  block_scan3<SCAN_WAVES>(s, ex, tot);
+  uint32_t run[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) run[q] = chunk[3 * blockIdx.x + q] + ex[q];
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; ++j) {
+    const int64_t t = t0 + j;
+    if (t < ntiles) {
+      start_own[t] = run[0];
+      own_slot[t] = a[j] ? (int32_t)run[1] : -1;
+      if (a[j]) own_tiles[run[1]++] = (uint32_t)t;
+      if (b[j]) touch_tiles[run[2]++] = (uint32_t)t;
+      run[0] += a[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < SCAN_PER; j += 4)
+    if (t0 + j < ntiles) {
+      *reinterpret_cast<uint4*>(cnt_own + t0 + j) = make_uint4(0u, 0u, 0u, 0u);
+      *reinterpret_cast<uint4*>(cnt_touch + t0 + j) = make_uint4(0u, 0u, 0u, 0u);
+    }
+  // this chunk's share of the force-block flags
+  const int64_t per = (nbflag_words + gridDim.x - 1) / gridDim.x;
+  const int64_t w1 = min(nbflag_words, per * (blockIdx.x + 1));
+  for (int64_t w = per * blockIdx.x + threadIdx.x; w < w1; w += SCAN_WG) bflag_words[w] = 0u;
 }
 
 // Pass 3: move every point again (same arithmetic), store it at its slot in
@@ -359,6 +404,21 @@ __device__ __forceinline__ int64_t list_entry(uint32_t n_active) {
   return e < n_active ? (int64_t)e : -1;
 }
 
+// Owner / touched tile entries of this workgroup in a launch of any
+// multiple of 8 workgroups: XCD x takes the contiguous run
+// [x chunk, (x + 1) chunk) of the list and its workgroups stride through it.
+struct ListRange {
+  uint32_t e, end, step;
+};
+__device__ __forceinline__ ListRange list_range(uint32_t n) {
+  const uint32_t chunk = (n + 7u) / 8u, xcd = blockIdx.x & 7u;
+  ListRange r;
+  r.e = xcd * chunk + (blockIdx.x >> 3);
+  r.end = min(n, (xcd + 1u) * chunk);
+  r.step = gridDim.x >> 3;
+  return r;
+}
+
 __device__ __forceinline__ void tile_origin(const PointGeom& pg, uint32_t t, int o[3]) {
   o[0] = (int)(t % (uint32_t)pg.tiles[0]) * TILE;
   o[1] = (int)((t / (uint32_t)pg.tiles[0]) % (uint32_t)pg.tiles[1]) * TILE;
@@ -366,44 +426,37 @@ __device__ __forceinline__ void tile_origin(const PointGeom& pg, uint32_t t, int
 }
 
 // Velocity U = sum e f / rho (eq. 1) of the post-stream populations on the
-// flagged 4^3 blocks (the paper's lbm_u_start limited to the cells the
-// supports reach).  One workgroup per row of force blocks (4 x 4 cell rows in
-// y, z along the whole x extent); threads run along x, so a wave's loads of a
-// population are consecutive words of one cell row (whole cache lines where
-// flagged blocks are contiguous) instead of 8-cell pieces of 8 rows.
-constexpr int MOM_WG = 256;
+// flagged 4^3 blocks of every touched tile (the paper's lbm_u_start limited
+// to the cells the supports reach).  512 threads: one wave per 8x8 z-plane.
 template <int S>
-__global__ __launch_bounds__(MOM_WG) void k_moments_rows(
+__global__ __launch_bounds__(TILE3) void k_moments_blocks(
     const typename Store<S>::T* __restrict__ lat, const LatticeGeom g, PointGeom pg,
+    const uint32_t* __restrict__ touch_tiles, const uint32_t* __restrict__ meta,
     const uint8_t* __restrict__ bflag, float* __restrict__ U) {
-  const int64_t e = list_entry((uint32_t)(pg.fblk[1] * pg.fblk[2]));
-  if (e < 0) return;
-  const int by = (int)(e % pg.fblk[1]), bz = (int)(e / pg.fblk[1]);
-  const uint8_t* frow = bflag + (int64_t)pg.fblk[0] * (by + (int64_t)pg.fblk[1] * bz);
-  int any = 0;
-  for (int bx = threadIdx.x; bx < pg.fblk[0]; bx += MOM_WG) any |= frow[bx];
-  if (!__syncthreads_or(any)) return;
-  for (int r = 0; r < FBLK * FBLK; ++r) {
-    const int y = FBLK * by + (r & (FBLK - 1)), z = FBLK * bz + (r >> FBLK_SHIFT);
-    if (y >= g.ny || z >= g.nz) continue;
-    for (int x = threadIdx.x; x < g.nx; x += MOM_WG) {
-      if (!frow[x >> FBLK_SHIFT]) continue;
-      float f[Q];
-      gather_any<S>(lat, g, x, y, z, f);
-      float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+  const ListRange lr = list_range(meta[1]);
+  for (uint32_t e = lr.e; e < lr.end; e += lr.step) {
+    int o[3];
+    tile_origin(pg, touch_tiles[e], o);
+    const int x = o[0] + (threadIdx.x & (TILE - 1));
+    const int y = o[1] + ((threadIdx.x >> TILE_SHIFT) & (TILE - 1));
+    const int z = o[2] + (threadIdx.x >> (2 * TILE_SHIFT));
+    if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
+    if (!bflag[fblock_of(g, x, y, z)]) continue;
+    float f[Q];
+    gather_any<S>(lat, g, x, y, z, f);
+    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        drho += f[i];
-        jx += EX[i] * f[i];
-        jy += EY[i] * f[i];
-        jz += EZ[i] * f[i];
-      }
-      const float inv = 1.0f / (1.0f + drho);
-      const int64_t cell = (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
-      U[cell] = jx * inv;
-      U[g.ncell + cell] = jy * inv;
-      U[2 * g.ncell + cell] = jz * inv;
+    for (int i = 0; i < Q; ++i) {
+      drho += f[i];
+      jx += EX[i] * f[i];
+      jy += EY[i] * f[i];
+      jz += EZ[i] * f[i];
     }
+    const float inv = 1.0f / (1.0f + drho);
+    const int64_t cell = (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
+    U[cell] = jx * inv;
+    U[g.ncell + cell] = jy * inv;
+    U[2 * g.ncell + cell] = jz * inv;
   }
 }
 
@@ -428,15 +481,22 @@ __device__ __forceinline__ void peskin4(float r, float w[4]) {
 //               sweep) or du (last sweep, or a predicted warm start), and
 //               box(X) = sum_k v(k) W_k(X) over the tile's points     (Alg. 2)
 // With neither spread bit only the interpolation runs; with SW_INTERP clear
-// only the spread.  A nonzero *gate (the forcing has converged) makes the
-// whole launch a no-op.  g_orig (nullable) receives g in the caller's order.
+// only the spread.  g_orig (nullable) receives g in the caller's order.
 // U is staged over the 11^3 box [o-1, o+10)^3 that holds every tap of the
 // tile's points (coordinates wrapped on periodic axes).  The box sum is
-// accumulated in LDS in 32-bit fixed point with the unit B / 2^30, where
+// accumulated in LDS in fixed point with the unit B / 2^30, where
 // B = (1/8) sum_k max_c |v_k,c| bounds every box cell (a tap weight is at
 // most 1/8): no overflow is possible and integer addition makes the sum
-// independent of the order of the atomics.  The box is stored as FP32 in
-// the tile's slot of boxbuf.  FP64 partial of s |g|^2 per workgroup.
+// independent of the order of the atomics.  Components x and y share one
+// 64-bit atomic (x sign-extended in the low word, y in the high word: the
+// 64-bit sum is exactly sum_y 2^32 + sum_x, and |sum_x| < 2^31 recovers
+// both), z has its own 32-bit one.  The box is stored as FP32 in the tile's
+// slot of boxbuf.
+//
+// Each workgroup takes a stride of the owner-tile list (contiguous per XCD;
+// one tile per workgroup unless the list is longer than the grid).  A
+// nonzero *gate (the forcing has converged) makes the launch a no-op.  Each
+// workgroup writes its FP64 partial of s |g|^2 when interpolating.
 constexpr float FIX_ONE = 1073741824.0f;  // 2^30
 enum : int {
   SW_INTERP = 1,
@@ -445,6 +505,9 @@ enum : int {
   SW_SPREAD_DU = 8,
   SW_UNWEIGHTED = 16,
 };
+
+
+
 __global__ __launch_bounds__(WG) void k_sweep_tiles(
     const uint32_t* __restrict__ own_tiles, const uint32_t* __restrict__ meta,
     const uint32_t* __restrict__ start_own, const int4* __restrict__ sp_base,
@@ -453,90 +516,171 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
     float* __restrict__ boxbuf, PointGeom pg, int mode, double* __restrict__ part_res,
     const uint32_t* __restrict__ gate, float4* __restrict__ g_orig) {
   // U of the box during the interpolation, then (same storage) the integer
-  // accumulator of the spread
-  __shared__ float sU[3][BOX3];
-  int (*acc)[BOX3] = reinterpret_cast<int (*)[BOX3]>(sU);
+  // accumulators of the spread: x and y packed in 64 bits, z in 32 bits
+  __shared__ __align__(16) float sU[3][BOX3];
+  unsigned long long* accxy = reinterpret_cast<unsigned long long*>(&sU[0][0]);
+  int* accz = reinterpret_cast<int*>(&sU[0][0]) + 2 * BOX3;
   __shared__ float fred[WG / 64];
   __shared__ double dred[WG / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (gate && *gate) return;  // the forcing has already converged
   const bool interp = mode & SW_INTERP;
   const bool spread_g = mode & SW_SPREAD_G, spread_du = mode & SW_SPREAD_DU;
+  const bool spread = spread_g || spread_du;
   const bool inner_weighted = !(mode & SW_UNWEIGHTED);
-  const int64_t e = list_entry(meta[0]);
-  if (e < 0) {  // idle workgroup: empty residual partial
-    if (interp && threadIdx.x == 0) part_res[blockIdx.x] = 0.0;
-    return;
-  }
-  const uint32_t t = own_tiles[e];
-  int o[3];
-  tile_origin(pg, t, o);
+  double res = 0.0;  // this thread's part of sum s |g|^2 over the workgroup's tiles
+  const ListRange lr = list_range(meta[0]);
+  for (uint32_t e = lr.e; e < lr.end; e += lr.step) {
+    const uint32_t t = own_tiles[e];
+    int o[3];
+    tile_origin(pg, t, o);
+    __syncthreads();  // the previous tile's box has been stored
 #pragma unroll 2
-  for (int i = threadIdx.x; interp && i < BOX3; i += WG) {
-    const int bx = i % BOX, by = (i / BOX) % BOX, bz = i / (BOX * BOX);
-    const int cx = tap_coord(o[0] - 1 + bx, pg.n[0], pg.bc[0]);
-    const int cy = tap_coord(o[1] - 1 + by, pg.n[1], pg.bc[1]);
-    const int cz = tap_coord(o[2] - 1 + bz, pg.n[2], pg.bc[2]);
-    const int64_t c = (int64_t)cx + (int64_t)pg.n[0] * ((int64_t)cy + (int64_t)pg.n[1] * cz);
-    sU[0][i] = U[c];
-    sU[1][i] = U[pg.ncell + c];
-    sU[2][i] = U[2 * pg.ncell + c];
-  }
-  __syncthreads();
-  const uint32_t p0 = start_own[t], p1 = start_own[t + 1];
-  // pass 1: interpolation, deficit, correction (or, spreading only, the
-  // bound of the spread vector)
-  float bsum = 0.0f;
-  double res = 0.0;
-  for (uint32_t k = p0 + threadIdx.x; !interp && k < p1; k += WG) {
-    const float4 fr = sp_frac[k];
-    const float4 v = spread_du ? sp_du[k] : sp_g[k];
-    const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
-    bsum += vs * fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
-  }
-  for (uint32_t k = p0 + threadIdx.x; interp && k < p1; k += WG) {
-    const int4 b = sp_base[k];
-    const float4 fr = sp_frac[k];
-    float wx[4], wy[4], wz[4];
-    peskin4(fr.x, wx);
-    peskin4(fr.y, wy);
-    peskin4(fr.z, wz);
-    // box index of tap (-1, -1, -1): the box starts one cell before the tile
-    const int l0 = (b.x - o[0]) + BOX * ((b.y - o[1]) + BOX * (b.z - o[2]));
-    float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+    for (int i = threadIdx.x; interp && i < BOX3; i += WG) {
+      const int bx = i % BOX, by = (i / BOX) % BOX, bz = i / (BOX * BOX);
+      const int cx = tap_coord(o[0] - 1 + bx, pg.n[0], pg.bc[0]);
+      const int cy = tap_coord(o[1] - 1 + by, pg.n[1], pg.bc[1]);
+      const int cz = tap_coord(o[2] - 1 + bz, pg.n[2], pg.bc[2]);
+      const int64_t c = (int64_t)cx + (int64_t)pg.n[0] * ((int64_t)cy + (int64_t)pg.n[1] * cz);
+      sU[0][i] = U[c];
+      sU[1][i] = U[pg.ncell + c];
+      sU[2][i] = U[2 * pg.ncell + c];
+    }
+    __syncthreads();
+    const uint32_t p0 = start_own[t], p1 = start_own[t + 1];
+    // pass 1: interpolation, deficit, correction (or, spreading only, the
+    // bound of the spread vector)
+    float bsum = 0.0f;
+    for (uint32_t k = p0 + threadIdx.x; !interp && k < p1; k += WG) {
+      const float4 fr = sp_frac[k];
+      const float4 v = spread_du ? sp_du[k] : sp_g[k];
+      const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
+      bsum += vs * fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
+    }
+    for (uint32_t k = p0 + threadIdx.x; interp && k < p1; k += WG) {
+      const int4 b = sp_base[k];
+      const float4 fr = sp_frac[k];
+      float wx[4], wy[4], wz[4];
+      peskin4(fr.x, wx);
+      peskin4(fr.y, wy);
+      peskin4(fr.z, wz);
+      // box index of tap (-1, -1, -1): the box starts one cell before the tile
+      const int l0 = (b.x - o[0]) + BOX * ((b.y - o[1]) + BOX * (b.z - o[2]));
+      float u0 = 0.f, u1 = 0.f, u2 = 0.f;
 #pragma unroll 1
-    for (int cz = 0; cz < 4; ++cz) {
-      const float wzc = cz == 0 ? wz[0] : (cz == 1 ? wz[1] : (cz == 2 ? wz[2] : wz[3]));
+      for (int cz = 0; cz < 4; ++cz) {
+        const float wzc = cz == 0 ? wz[0] : (cz == 1 ? wz[1] : (cz == 2 ? wz[2] : wz[3]));
 #pragma unroll
-      for (int cy = 0; cy < 4; ++cy) {
-        const float wyz = wzc * wy[cy];
-        const int row = l0 + BOX * (cy + BOX * cz);
+        for (int cy = 0; cy < 4; ++cy) {
+          const float wyz = wzc * wy[cy];
+          const int row = l0 + BOX * (cy + BOX * cz);
 #pragma unroll
-        for (int cx = 0; cx < 4; ++cx) {
-          const float w = wyz * wx[cx];
-          u0 += w * sU[0][row + cx];
-          u1 += w * sU[1][row + cx];
-          u2 += w * sU[2][row + cx];
+          for (int cx = 0; cx < 4; ++cx) {
+            const float w = wyz * wx[cx];
+            u0 += w * sU[0][row + cx];
+            u1 += w * sU[1][row + cx];
+            u2 += w * sU[2][row + cx];
+          }
+        }
+      }
+      const float4 ub = sp_ub[k];
+      const float g0 = ub.x - u0, g1 = ub.y - u1, g2 = ub.z - u2;
+      float4 du = (mode & SW_FIRST) ? make_float4(0.f, 0.f, 0.f, 0.f) : sp_du[k];
+      du.x += fr.w * g0;
+      du.y += fr.w * g1;
+      du.z += fr.w * g2;
+      du.w = 0.0f;
+      sp_g[k] = make_float4(g0, g1, g2, 0.0f);
+      sp_du[k] = du;
+      if (g_orig) g_orig[b.w] = make_float4(g0, g1, g2, 0.0f);
+      res += (double)fr.w * ((double)g0 * g0 + (double)g1 * g1 + (double)g2 * g2);
+      const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
+      const float v0 = spread_du ? du.x : vs * g0, v1 = spread_du ? du.y : vs * g1,
+                  v2 = spread_du ? du.z : vs * g2;
+      bsum += fmaxf(fabsf(v0), fmaxf(fabsf(v1), fabsf(v2)));
+    }
+    if (!spread) continue;
+    // block bound B (FP32, fixed order)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) bsum += __shfl_xor(bsum, off, 64);
+    if (lane == 0) fred[wave] = bsum;
+    __syncthreads();  // also: the interpolation's reads of sU are done
+    float B = 0.0f;
+#pragma unroll
+    for (int w = 0; w < WG / 64; ++w) B += fred[w];
+    B *= 0.125f;
+    const float scale = B > 0.0f ? FIX_ONE / B : 0.0f;
+    for (int i = threadIdx.x; i < BOX3; i += WG) {
+      accxy[i] = 0ull;
+      accz[i] = 0;
+    }
+    __syncthreads();
+    // pass 2: spread into the box (every tap of an owned point is inside
+    // it).  Neighbouring slots hold neighbouring points, which add into the
+    // same LDS words tap after tap; a stride coprime to the point count deals
+    // them to the lanes in scattered order, and each lane starts at its own
+    // z-plane.
+    const uint32_t L = p1 - p0;
+    const uint32_t P = (L % 97u) ? 97u : 89u;
+    const uint32_t step = L ? (uint32_t)(((uint64_t)WG * P) % L) : 0u;
+    uint32_t pos = L ? (uint32_t)(((uint64_t)threadIdx.x * P) % L) : 0u;
+    const int zrot = lane & 3;
+    for (uint32_t i = threadIdx.x; i < L; i += WG) {
+      const uint32_t k = p0 + pos;
+      pos += step;
+      if (pos >= L) pos -= L;
+      const int4 b = sp_base[k];
+      const float4 fr = sp_frac[k];
+      float v0, v1, v2;
+      if (spread_du) {
+        const float4 du = sp_du[k];
+        v0 = du.x * scale;
+        v1 = du.y * scale;
+        v2 = du.z * scale;
+      } else {
+        const float4 g = sp_g[k];
+        const float vs = (inner_weighted ? fr.w : 1.0f) * scale;
+        v0 = g.x * vs;
+        v1 = g.y * vs;
+        v2 = g.z * vs;
+      }
+      float wx[4], wy[4], wz[4];
+      peskin4(fr.x, wx);
+      peskin4(fr.y, wy);
+      peskin4(fr.z, wz);
+      const int l0 = (b.x - o[0]) + BOX * ((b.y - o[1]) + BOX * (b.z - o[2]));
+#pragma unroll 1
+      for (int jz = 0; jz < 4; ++jz) {
+        const int cz = (jz + zrot) & 3;
+        const float wzc = cz == 0 ? wz[0] : (cz == 1 ? wz[1] : (cz == 2 ? wz[2] : wz[3]));
+#pragma unroll
+        for (int cy = 0; cy < 4; ++cy) {
+          const float wyz = wzc * wy[cy];
+          const int row = l0 + BOX * (cy + BOX * cz);
+#pragma unroll
+          for (int cx = 0; cx < 4; ++cx) {
+            const float w = wyz * wx[cx];
+            const long long ix = __float2int_rn(w * v0), iy = __float2int_rn(w * v1);
+            atomicAdd(&accxy[row + cx],
+                      (unsigned long long)ix + ((unsigned long long)iy << 32));
+            atomicAdd(&accz[row + cx], __float2int_rn(w * v2));
+          }
         }
       }
     }
-    const float4 ub = sp_ub[k];
-    const float g0 = ub.x - u0, g1 = ub.y - u1, g2 = ub.z - u2;
-    float4 du = (mode & SW_FIRST) ? make_float4(0.f, 0.f, 0.f, 0.f) : sp_du[k];
-    du.x += fr.w * g0;
-    du.y += fr.w * g1;
-    du.z += fr.w * g2;
-    du.w = 0.0f;
-    sp_g[k] = make_float4(g0, g1, g2, 0.0f);
-    sp_du[k] = du;
-    if (g_orig) g_orig[b.w] = make_float4(g0, g1, g2, 0.0f);
-    res += (double)fr.w * ((double)g0 * g0 + (double)g1 * g1 + (double)g2 * g2);
-    const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
-    const float v0 = spread_du ? du.x : vs * g0, v1 = spread_du ? du.y : vs * g1,
-                v2 = spread_du ? du.z : vs * g2;
-    bsum += fmaxf(fabsf(v0), fmaxf(fabsf(v1), fabsf(v2)));
+    __syncthreads();
+    const float unit = B / FIX_ONE;
+    float* box = boxbuf + (int64_t)e * 3 * BOX3;
+    for (int i = threadIdx.x; i < BOX3; i += WG) {
+      const unsigned long long sxy = accxy[i];
+      const int sx = (int)(uint32_t)sxy;
+      const int sy = (int)(uint32_t)((sxy - (unsigned long long)(long long)sx) >> 32);
+      box[i] = (float)sx * unit;
+      box[BOX3 + i] = (float)sy * unit;
+      box[2 * BOX3 + i] = (float)accz[i] * unit;
+    }
   }
-  if (!spread_g && !spread_du) {  // interpolation only: the residual partial
+  if (interp) {  // this workgroup's residual partial (zero if it had no tile)
     const double rv = wave_sum(res);
     if (lane == 0) dred[wave] = rv;
     __syncthreads();
@@ -545,88 +689,6 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
       for (int w = 0; w < WG / 64; ++w) sres += dred[w];
       part_res[blockIdx.x] = sres;
     }
-    return;
-  }
-  // block sums: bound B (FP32) and residual (FP64)
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) bsum += __shfl_xor(bsum, off, 64);
-  const double rv = wave_sum(res);
-  if (lane == 0) {
-    fred[wave] = bsum;
-    dred[wave] = rv;
-  }
-  __syncthreads();
-  float B = 0.0f;
-#pragma unroll
-  for (int w = 0; w < WG / 64; ++w) B += fred[w];
-  B *= 0.125f;
-  if (interp && threadIdx.x == 0) {
-    double sres = 0.0;
-    for (int w = 0; w < WG / 64; ++w) sres += dred[w];
-    part_res[blockIdx.x] = sres;
-  }
-  const float scale = B > 0.0f ? FIX_ONE / B : 0.0f;
-  // the interpolation is done (barrier above): clear the accumulator
-  for (int i = threadIdx.x; i < 3 * BOX3; i += WG) (&acc[0][0])[i] = 0;
-  __syncthreads();
-  // pass 2: spread into the box (every tap of an owned point is inside it).
-  // Neighbouring slots hold neighbouring points, which add into the same LDS
-  // words tap after tap; a stride coprime to the point count deals them to
-  // the lanes in scattered order, and each lane starts at its own z-plane.
-  const uint32_t L = p1 - p0;
-  const uint32_t P = (L % 97u) ? 97u : 89u;
-  const uint32_t step = L ? (uint32_t)(((uint64_t)WG * P) % L) : 0u;
-  uint32_t pos = L ? (uint32_t)(((uint64_t)threadIdx.x * P) % L) : 0u;
-  const int zrot = lane & 3;
-  for (uint32_t i = threadIdx.x; i < L; i += WG) {
-    const uint32_t k = p0 + pos;
-    pos += step;
-    if (pos >= L) pos -= L;
-    const int4 b = sp_base[k];
-    const float4 fr = sp_frac[k];
-    float v0, v1, v2;
-    if (spread_du) {
-      const float4 du = sp_du[k];
-      v0 = du.x * scale;
-      v1 = du.y * scale;
-      v2 = du.z * scale;
-    } else {
-      const float4 g = sp_g[k];
-      const float vs = (inner_weighted ? fr.w : 1.0f) * scale;
-      v0 = g.x * vs;
-      v1 = g.y * vs;
-      v2 = g.z * vs;
-    }
-    float wx[4], wy[4], wz[4];
-    peskin4(fr.x, wx);
-    peskin4(fr.y, wy);
-    peskin4(fr.z, wz);
-    const int l0 = (b.x - o[0]) + BOX * ((b.y - o[1]) + BOX * (b.z - o[2]));
-#pragma unroll 1
-    for (int jz = 0; jz < 4; ++jz) {
-      const int cz = (jz + zrot) & 3;
-      const float wzc = cz == 0 ? wz[0] : (cz == 1 ? wz[1] : (cz == 2 ? wz[2] : wz[3]));
-#pragma unroll
-      for (int cy = 0; cy < 4; ++cy) {
-        const float wyz = wzc * wy[cy];
-        const int row = l0 + BOX * (cy + BOX * cz);
-#pragma unroll
-        for (int cx = 0; cx < 4; ++cx) {
-          const float w = wyz * wx[cx];
-          atomicAdd(&acc[0][row + cx], __float2int_rn(w * v0));
-          atomicAdd(&acc[1][row + cx], __float2int_rn(w * v1));
-          atomicAdd(&acc[2][row + cx], __float2int_rn(w * v2));
-        }
-      }
-    }
-  }
-  __syncthreads();
-  const float unit = B / FIX_ONE;
-  float* box = boxbuf + (int64_t)e * 3 * BOX3;
-  for (int i = threadIdx.x; i < BOX3; i += WG) {
-    box[i] = (float)acc[0][i] * unit;
-    box[BOX3 + i] = (float)acc[1][i] * unit;
-    box[2 * BOX3 + i] = (float)acc[2][i] * unit;
   }
 }
 
@@ -664,97 +726,99 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
   __shared__ int16_t ct[3][TILE][MAXCOV], cb[3][TILE][MAXCOV];
   __shared__ int cn[3][TILE];
   if (gate && *gate) return;  // the forcing has already converged
-  const int64_t e = list_entry(meta[1]);
-  if (e < 0) return;
-  const uint32_t t = touch_tiles[e];
-  int o[3], tc[3];
-  tile_origin(pg, t, o);
-  for (int a = 0; a < 3; ++a) tc[a] = o[a] / TILE;
-  // Fast path: on every axis the tile and both neighbours are full tiles
-  // without a wrap, so the boxes covering local coordinate l are the own
-  // tile (position l + 1), the previous tile when l <= 1 (position l + 9)
-  // and the next tile when l == 7 (position 0).
-  bool simple = true;
-  for (int a = 0; a < 3; ++a)
-    simple = simple && tc[a] >= 1 && (tc[a] + 2) * TILE <= pg.n[a];
-  if (!simple) {  // general covering tables (short axes, seams, short tiles)
-    if (threadIdx.x < 3 * TILE) {
-      const int a = threadIdx.x / TILE, l = threadIdx.x % TILE;
-      const int x = o[a] + l;
-      cn[a][l] = x < pg.n[a] ? covering(x, pg.n[a], pg.bc[a], pg.tiles[a], ct[a][l], cb[a][l]) : 0;
-    }
-    __syncthreads();
-  }
-  for (int cell = threadIdx.x; cell < TILE3; cell += MERGE_WG) {
-    const int lx = cell & (TILE - 1), ly = (cell >> TILE_SHIFT) & (TILE - 1),
-              lz = cell >> (2 * TILE_SHIFT);
-    const int x = o[0] + lx, y = o[1] + ly, z = o[2] + lz;
-    if (x >= pg.n[0] || y >= pg.n[1] || z >= pg.n[2]) continue;
-    // only cells of flagged force blocks can receive a contribution, and
-    // only there is G read by the stream-collide
-    if (!bflag[(int64_t)(x >> FBLK_SHIFT) +
-               (int64_t)pg.fblk[0] * ((int64_t)(y >> FBLK_SHIFT) + (int64_t)pg.fblk[1] * (z >> FBLK_SHIFT))])
-      continue;
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-    if (simple) {
-      const int l[3] = {lx, ly, lz};
-      int nd[3][2], nb[3][2], nn[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        nd[a][0] = 0;
-        nb[a][0] = l[a] + 1;
-        nn[a] = 1;
-        nd[a][1] = 0;
-        nb[a][1] = 0;
-        if (l[a] <= 1) {
-          nd[a][1] = -1;
-          nb[a][1] = l[a] + 9;
-          nn[a] = 2;
-        } else if (l[a] == TILE - 1) {
-          nd[a][1] = 1;
-          nn[a] = 2;
-        }
+  const ListRange lr = list_range(meta[1]);
+  for (uint32_t e = lr.e; e < lr.end; e += lr.step) {
+    __syncthreads();  // the previous tile's covering tables are no longer read
+    const uint32_t t = touch_tiles[e];
+    int o[3], tc[3];
+    tile_origin(pg, t, o);
+    for (int a = 0; a < 3; ++a) tc[a] = o[a] / TILE;
+    // Fast path: on every axis the tile and both neighbours are full tiles
+    // without a wrap, so the boxes covering local coordinate l are the own
+    // tile (position l + 1), the previous tile when l <= 1 (position l + 9)
+    // and the next tile when l == 7 (position 0).
+    bool simple = true;
+    for (int a = 0; a < 3; ++a)
+      simple = simple && tc[a] >= 1 && (tc[a] + 2) * TILE <= pg.n[a];
+    if (!simple) {  // general covering tables (short axes, seams, short tiles)
+      if (threadIdx.x < 3 * TILE) {
+        const int a = threadIdx.x / TILE, l = threadIdx.x % TILE;
+        const int x = o[a] + l;
+        cn[a][l] = x < pg.n[a] ? covering(x, pg.n[a], pg.bc[a], pg.tiles[a], ct[a][l], cb[a][l]) : 0;
       }
-#pragma unroll
-      for (int jz = 0; jz < 2; ++jz)
-#pragma unroll
-        for (int jy = 0; jy < 2; ++jy)
-#pragma unroll
-          for (int jx = 0; jx < 2; ++jx) {
-            if (jx >= nn[0] || jy >= nn[1] || jz >= nn[2]) continue;
-            const int32_t slot =
-                own_slot[tile_index(pg, tc[0] + nd[0][jx], tc[1] + nd[1][jy], tc[2] + nd[2][jz])];
-            if (slot < 0) continue;
-            const int bi = nb[0][jx] + BOX * (nb[1][jy] + BOX * nb[2][jz]);
-            const float* box = boxbuf + (int64_t)slot * 3 * BOX3;
-            s0 += box[bi];
-            s1 += box[BOX3 + bi];
-            s2 += box[2 * BOX3 + bi];
-          }
-    } else {
-      const int nx_ = cn[0][lx], ny_ = cn[1][ly], nz_ = cn[2][lz];
-      for (int jz = 0; jz < nz_; ++jz)
-        for (int jy = 0; jy < ny_; ++jy)
-          for (int jx = 0; jx < nx_; ++jx) {
-            const uint32_t A = tile_index(pg, ct[0][lx][jx], ct[1][ly][jy], ct[2][lz][jz]);
-            const int32_t slot = own_slot[A];
-            if (slot < 0) continue;
-            const int bi = cb[0][lx][jx] + BOX * (cb[1][ly][jy] + BOX * cb[2][lz][jz]);
-            const float* box = boxbuf + (int64_t)slot * 3 * BOX3;
-            s0 += box[bi];
-            s1 += box[BOX3 + bi];
-            s2 += box[2 * BOX3 + bi];
-          }
+      __syncthreads();
     }
-    const int64_t c = (int64_t)x + (int64_t)pg.n[0] * ((int64_t)y + (int64_t)pg.n[1] * z);
-    if (mode == 2) {
-      target[c] = s0;
-      target[pg.ncell + c] = s1;
-      target[2 * pg.ncell + c] = s2;
-    } else if (s0 != 0.0f || s1 != 0.0f || s2 != 0.0f) {
-      target[c] += s0;
-      target[pg.ncell + c] += s1;
-      target[2 * pg.ncell + c] += s2;
+    for (int cell = threadIdx.x; cell < TILE3; cell += MERGE_WG) {
+      const int lx = cell & (TILE - 1), ly = (cell >> TILE_SHIFT) & (TILE - 1),
+                lz = cell >> (2 * TILE_SHIFT);
+      const int x = o[0] + lx, y = o[1] + ly, z = o[2] + lz;
+      if (x >= pg.n[0] || y >= pg.n[1] || z >= pg.n[2]) continue;
+      // only cells of flagged force blocks can receive a contribution, and
+      // only there is G read by the stream-collide
+      if (!bflag[(int64_t)(x >> FBLK_SHIFT) +
+                 (int64_t)pg.fblk[0] * ((int64_t)(y >> FBLK_SHIFT) + (int64_t)pg.fblk[1] * (z >> FBLK_SHIFT))])
+        continue;
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+      if (simple) {
+        const int l[3] = {lx, ly, lz};
+        int nd[3][2], nb[3][2], nn[3];
+  #pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          nd[a][0] = 0;
+          nb[a][0] = l[a] + 1;
+          nn[a] = 1;
+          nd[a][1] = 0;
+          nb[a][1] = 0;
+          if (l[a] <= 1) {
+            nd[a][1] = -1;
+            nb[a][1] = l[a] + 9;
+            nn[a] = 2;
+          } else if (l[a] == TILE - 1) {
+            nd[a][1] = 1;
+            nn[a] = 2;
+          }
+        }
+  #pragma unroll
+        for (int jz = 0; jz < 2; ++jz)
+  #pragma unroll
+          for (int jy = 0; jy < 2; ++jy)
+  #pragma unroll
+            for (int jx = 0; jx < 2; ++jx) {
+              if (jx >= nn[0] || jy >= nn[1] || jz >= nn[2]) continue;
+              const int32_t slot =
+                  own_slot[tile_index(pg, tc[0] + nd[0][jx], tc[1] + nd[1][jy], tc[2] + nd[2][jz])];
+              if (slot < 0) continue;
+              const int bi = nb[0][jx] + BOX * (nb[1][jy] + BOX * nb[2][jz]);
+              const float* box = boxbuf + (int64_t)slot * 3 * BOX3;
+              s0 += box[bi];
+              s1 += box[BOX3 + bi];
+              s2 += box[2 * BOX3 + bi];
+            }
+      } else {
+        const int nx_ = cn[0][lx], ny_ = cn[1][ly], nz_ = cn[2][lz];
+        for (int jz = 0; jz < nz_; ++jz)
+          for (int jy = 0; jy < ny_; ++jy)
+            for (int jx = 0; jx < nx_; ++jx) {
+              const uint32_t A = tile_index(pg, ct[0][lx][jx], ct[1][ly][jy], ct[2][lz][jz]);
+              const int32_t slot = own_slot[A];
+              if (slot < 0) continue;
+              const int bi = cb[0][lx][jx] + BOX * (cb[1][ly][jy] + BOX * cb[2][lz][jz]);
+              const float* box = boxbuf + (int64_t)slot * 3 * BOX3;
+              s0 += box[bi];
+              s1 += box[BOX3 + bi];
+              s2 += box[2 * BOX3 + bi];
+            }
+      }
+      const int64_t c = (int64_t)x + (int64_t)pg.n[0] * ((int64_t)y + (int64_t)pg.n[1] * z);
+      if (mode == 2) {
+        target[c] = s0;
+        target[pg.ncell + c] = s1;
+        target[2 * pg.ncell + c] = s2;
+      } else if (s0 != 0.0f || s1 != 0.0f || s2 != 0.0f) {
+        target[c] += s0;
+        target[pg.ncell + c] += s1;
+        target[2 * pg.ncell + c] += s2;
+      }
     }
   }
 }
@@ -786,7 +850,10 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_reduce_rows(const double* __restr
 // cleared control block.  k_resid_check after sweep `it`: unless already
 // converged, R = sum_k s |g|^2 of the sweep is compared with thr; R <= thr,
 // or the last allowed sweep, ends the forcing.  Comparing squared sums keeps
-// a body at rest (both sums zero) converged without a division.
+// a body at rest (both sums zero) converged without a division.  (A check
+// inside the sweep by its last workgroup would need a device-scope release
+// fence in every workgroup, which writes back the L2 and costs more than
+// this launch.)
 __global__ __launch_bounds__(LBM_BLOCK) void k_resid_threshold(const double* __restrict__ part_sub2,
                                                                int64_t nblk, double eps2,
                                                                double* __restrict__ thr,
@@ -824,6 +891,7 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_resid_check(const double* __restr
     if (last || (use_thr && t <= *thr)) ctl[0] = 1u;
   }
 }
+
 
 // Sorted point arrays back to the caller's order.
 __global__ __launch_bounds__(LBM_BLOCK) void k_export_points(
@@ -884,7 +952,26 @@ PointGeom point_geom(const lbm_ctx* c) {
 
 // Grid of the compact-list kernels: a multiple of 8 workgroups (one per XCD
 // slot) covering every tile.
-int64_t forcing_list_grid(const lbm_ctx* c) { return (c->ntiles + 7) / 8 * 8; }
+// Workgroups of the sweep, merge and U pre-pass launches over the owner
+// (list 0) or touched (list 1) tiles: a multiple of 8, each XCD striding
+// through its contiguous part of the list, so any size is correct.  The
+// lists' lengths are known on the device only; the host sizes the grids from
+// the previous forcing's lengths (copied asynchronously to pinned memory and
+// used once that copy has completed) with a quarter of headroom, so that
+// idle or gated-off launches do not dispatch a workgroup per tile of the
+// grid.  Without a previous length every tile gets a workgroup (up to
+// LBM_TILE_GRID_MAX).
+#ifndef LBM_TILE_GRID_MAX
+#define LBM_TILE_GRID_MAX 32768
+#endif
+int64_t tile_grid(const lbm_ctx* c, int list) {
+  const int64_t full = std::min<int64_t>((c->ntiles + 7) / 8 * 8, LBM_TILE_GRID_MAX);
+  if (!c->prev_len_valid) return full;
+  const int64_t want = (int64_t)c->prev_len[list] + c->prev_len[list] / 4 + 64;
+  return std::min<int64_t>(full, (want + 7) / 8 * 8);
+}
+
+int64_t forcing_list_grid(const lbm_ctx* c) { return c->own_grid; }
 
 // The forcing of one time step: motion, binning, U near the surface,
 // n_iter sweeps of interpolation + correction with n_iter - 1 intermediate
@@ -893,7 +980,15 @@ hipError_t launch_forcing(lbm_ctx* c) {
   const PointGeom pg = point_geom(c);
   const int64_t n = c->npts;
   const unsigned nb = (unsigned)((n + LBM_BLOCK - 1) / LBM_BLOCK);
-  const unsigned lg = (unsigned)forcing_list_grid(c);
+  if (c->meta_pending && hipEventQuery(c->meta_event) == hipSuccess) {
+    c->prev_len[0] = c->meta_host[0];
+    c->prev_len[1] = c->meta_host[1];
+    c->prev_len_valid = true;
+    c->meta_pending = false;
+  }
+  const unsigned lg = (unsigned)tile_grid(c, 0);
+  const unsigned tg = (unsigned)tile_grid(c, 1);
+  c->own_grid = lg;
   const int64_t rs = c->part_row;  // row stride of pt_partials
   hipStream_t st = c->stream;
 
@@ -902,27 +997,38 @@ hipError_t launch_forcing(lbm_ctx* c) {
   k_point_count<<<nb, LBM_BLOCK, 0, st>>>(c->rest, c->body_of, c->motion, n, pg, c->key, c->rank,
                                           c->cnt_own, c->cnt_touch);
   LAUNCH_CHECK();
-  k_scan_tiles<<<1, SCAN_THREADS, 0, st>>>(c->cnt_own, c->cnt_touch, c->start_own, c->own_slot,
-                                           c->own_tiles, c->touch_tiles, c->meta,
-                                           (uint32_t*)c->bflag, c->nbflag_words, c->ntiles);
-  LAUNCH_CHECK();
+  {
+    const int64_t nch = (c->ntiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    // a pending host copy of the lengths is not overwritten before it is read
+    uint32_t* mh = c->meta_pending ? nullptr : c->meta_host_dev;
+    k_scan_totals<<<(unsigned)nch, SCAN_WG, 0, st>>>(c->cnt_own, c->cnt_touch, c->chunk_tot);
+    LAUNCH_CHECK();
+    k_scan_chunks<<<1, SCAN2_WG, 0, st>>>(c->chunk_tot, nch, c->start_own, c->ntiles, c->meta, mh);
+    LAUNCH_CHECK();
+    if (mh && hipEventRecord(c->meta_event, st) == hipSuccess) c->meta_pending = true;
+    k_scan_write<<<(unsigned)nch, SCAN_WG, 0, st>>>(c->cnt_own, c->cnt_touch, c->chunk_tot,
+                                                    c->ntiles, c->start_own, c->own_slot,
+                                                    c->own_tiles, c->touch_tiles,
+                                                    (uint32_t*)c->bflag, c->nbflag_words);
+    LAUNCH_CHECK();
+  }
   k_point_scatter<<<nb, LBM_BLOCK, 0, st>>>(c->rest, c->body_of, c->motion, n, pg, c->key, c->rank,
                                             c->start_own, c->sp_base, c->sp_frac, c->sp_ub,
                                             c->bflag, c->pt_partials, c->pt_partials + rs);
   LAUNCH_CHECK();
-  const unsigned mg = (unsigned)(((int64_t)pg.fblk[1] * pg.fblk[2] + 7) / 8 * 8);
+  const unsigned mg = tg;
   switch (c->p.storage) {
     case LBM_STORE_F16:
-      k_moments_rows<LBM_STORE_F16><<<mg, MOM_WG, 0, st>>>((const _Float16*)c->lat[c->cur], c->geom,
-                                                           pg, c->bflag, c->U);
+      k_moments_blocks<LBM_STORE_F16><<<mg, TILE3, 0, st>>>(
+          (const _Float16*)c->lat[c->cur], c->geom, pg, c->touch_tiles, c->meta, c->bflag, c->U);
       break;
     case LBM_STORE_BF16:
-      k_moments_rows<LBM_STORE_BF16><<<mg, MOM_WG, 0, st>>>((const uint16_t*)c->lat[c->cur], c->geom,
-                                                            pg, c->bflag, c->U);
+      k_moments_blocks<LBM_STORE_BF16><<<mg, TILE3, 0, st>>>(
+          (const uint16_t*)c->lat[c->cur], c->geom, pg, c->touch_tiles, c->meta, c->bflag, c->U);
       break;
     default:
-      k_moments_rows<LBM_STORE_F32><<<mg, MOM_WG, 0, st>>>((const float*)c->lat[c->cur], c->geom, pg,
-                                                           c->bflag, c->U);
+      k_moments_blocks<LBM_STORE_F32><<<mg, TILE3, 0, st>>>(
+          (const float*)c->lat[c->cur], c->geom, pg, c->touch_tiles, c->meta, c->bflag, c->U);
   }
   LAUNCH_CHECK();
   const int uw = (c->flags & IBM_INNER_UNWEIGHTED) ? SW_UNWEIGHTED : 0;
@@ -939,7 +1045,7 @@ hipError_t launch_forcing(lbm_ctx* c) {
     return hipGetLastError();
   };
   auto merge = [&](bool final_, const uint32_t* gate) {
-    k_merge_tiles<<<lg, MERGE_WG, 0, st>>>(c->touch_tiles, c->meta, c->own_slot, c->boxbuf,
+    k_merge_tiles<<<tg, MERGE_WG, 0, st>>>(c->touch_tiles, c->meta, c->own_slot, c->boxbuf,
                                         c->bflag, final_ ? c->G : c->U, pg, final_ ? 2 : 0, gate);
     return hipGetLastError();
   };
@@ -960,9 +1066,9 @@ hipError_t launch_forcing(lbm_ctx* c) {
     }
     return hipSuccess;
   }
-  // Residual-stopped and/or warm-started: every launch of sweeps 1.. is gated
-  // by the device flag ctl[0], so the sequence runs without host round trips;
-  // the final spread of du into G always runs.
+  // Residual-stopped and/or warm-started: every launch after sweep 0 is
+  // gated by the device flag ctl[0], so the sequence runs without host round
+  // trips; the final spread of du into G always runs.
   const bool warm = (c->flags & IBM_WARM_START) != 0;
   const int use_thr = (c->flags & IBM_STOP_RESIDUAL) ? 1 : 0;
   const int64_t na = (n + LBM_BLOCK - 1) / LBM_BLOCK;

@@ -62,6 +62,7 @@ struct lbm_ctx {
   uint32_t* own_tiles = nullptr;   // compact list of tiles owning points
   uint32_t* touch_tiles = nullptr; // compact list of touched tiles
   uint32_t* meta = nullptr;        // [4]: list lengths
+  uint32_t* chunk_tot = nullptr;   // [scan chunks][3] totals, then offsets
   uint8_t* bflag = nullptr;        // [nbflag_words * 4] force-block flags
   // learned warm start
   int32_t* nbr = nullptr;       // [max_points][16] neighbour lists (caller order)
@@ -93,6 +94,16 @@ struct lbm_ctx {
   int64_t g_valid_step = -1;
   bool g_prescribed = false;
   bool have_sums = false;  // a stream-collide has written the sum partials
+
+  // lengths of the owner / touched tile lists of a previous forcing, copied
+  // asynchronously to pinned host memory, to size the tile grids
+  uint32_t* meta_host = nullptr;      // pinned, mapped host memory
+  uint32_t* meta_host_dev = nullptr;  // its device address
+  hipEvent_t meta_event = nullptr;
+  bool meta_pending = false;
+  bool prev_len_valid = false;
+  uint32_t prev_len[2] = {0, 0};
+  int64_t own_grid = 8;  // workgroups of the last forcing's sweep launches
 
   // timing
   bool timing = false;

@@ -31,7 +31,7 @@ struct Plan {
   int64_t max_boxes;
   // tiles
   size_t o_cnt_own, o_cnt_touch, o_start_own, o_own_slot, o_own_tiles, o_touch_tiles, o_meta,
-      o_bflag;
+      o_bflag, o_chunk;
   int64_t nblocks4, nbflag_words;
   int fblk[3];
   // scratch
@@ -166,6 +166,7 @@ void make_plan(const lbm_params* p, Plan& pl) {
   pl.o_touch_tiles = tc.take(NT * 4);
   pl.o_meta = tc.take(4 * 4);
   pl.o_bflag = tc.take((size_t)pl.nbflag_words * 4);
+  pl.o_chunk = tc.take((NTpad / 2048) * 3 * 4);  // totals of the 2048-tile scan chunks
   pl.size[LBM_BUF_TILES] = tc.at;
 
   {  // blocks of the stream-collide launch (see stream_collide_shape)
@@ -370,6 +371,7 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->touch_tiles = (uint32_t*)(T + pl.o_touch_tiles);
   c->meta = (uint32_t*)(T + pl.o_meta);
   c->bflag = (uint8_t*)(T + pl.o_bflag);
+  c->chunk_tot = (uint32_t*)(T + pl.o_chunk);
   char* S = (char*)bufs[LBM_BUF_SCRATCH];
   c->sum_partials = (double*)(S + pl.o_sum_part);
   c->n_cell_blocks = pl.n_cell_blocks;
@@ -390,8 +392,14 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->G, 0u, 3 * c->ncell);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->sum_partials, 0u, 8 * c->n_cell_blocks);
   if (e == hipSuccess) e = launch_init_equilibrium(c);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&c->meta_host, 4 * sizeof(uint32_t), hipHostMallocMapped);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->meta_host_dev, c->meta_host, 0);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->meta_event, hipEventDisableTiming);
   if (e != hipSuccess) {
     g_create_error = std::string("initialisation: ") + hipGetErrorString(e);
+    if (c->meta_host) (void)hipHostFree(c->meta_host);
+    if (c->meta_event) (void)hipEventDestroy(c->meta_event);
     delete c;
     return LBM_ERR_HIP;
   }
@@ -403,6 +411,11 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
 void lbm_destroy(lbm_ctx* c) {
   if (!c) return;
   for (auto& ev : c->ev_pool) (void)hipEventDestroy(ev);
+  if (c->meta_event) {
+    (void)hipEventSynchronize(c->meta_event);
+    (void)hipEventDestroy(c->meta_event);
+  }
+  if (c->meta_host) (void)hipHostFree(c->meta_host);
   delete c;
 }
 
@@ -497,6 +510,8 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
   c->flags = flags;
   c->eps = (flags & IBM_STOP_RESIDUAL) ? eps : 0.0f;
   c->nbr_valid = false;
+  c->meta_pending = false;  // the stream has been synchronised above
+  c->prev_len_valid = false;
   c->g_valid_step = -1;
   c->g_prescribed = false;
   return LBM_OK;

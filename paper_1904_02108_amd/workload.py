@@ -140,7 +140,9 @@ def config(name, h=None, seed=0, forcing=FORCE_GUO):
         (hub r 12, L 24, blades 40x12) at the centre, h 0.7, omega 0.005,
         5 iterations, 1000 steps.  seed > 0: axis uniform on the sphere,
         theta0 ~ U[0, 2 pi), omega ~ U[0.004, 0.006] (training data of the
-        learned warm start; seed 0 is the canonical case).
+        learned warm start; seed 0 is the canonical case).  c1_dense: the
+        same at h 0.41 (about 25k points, the load the configuration
+        quotes for one propeller, as c2_dense is for 64).
     c2  256^3 periodic, tau 0.55, 64 propellers of c1 size at 32 + 64 {0..3}^3,
         axes uniform on the sphere, theta0 ~ U[0, 2 pi), omega ~ U[0.002, 0.008]
         (seeded), 5 iterations, 500 steps.  h 0.7 gives the literal sampling
@@ -153,8 +155,8 @@ def config(name, h=None, seed=0, forcing=FORCE_GUO):
         rest, area, off, bodies = _assemble([(pts, ar, (16.0, 16.0, 16.0), (0, 0, 1), 0.0, 0.01)])
         return Workload("c0", (32, 32, 32), 0.6, (0, 0, 0), forcing, rest, area, off, bodies,
                         5, 50, hh)
-    if name == "c1":
-        hh = 0.7 if h is None else h
+    if name in ("c1", "c1_dense"):
+        hh = (0.7 if name == "c1" else 0.41) if h is None else h
         pts, ar = propeller_surface(12.0, 24.0, 40.0, 12.0, hh)
         axis, th0, om = (0.0, 0.0, 1.0), 0.0, 0.005
         if seed:  # other seeds: random axis and phase, omega near the canonical one
@@ -164,7 +166,7 @@ def config(name, h=None, seed=0, forcing=FORCE_GUO):
             th0 = rng.uniform(0.0, 2.0 * math.pi)
             om = rng.uniform(0.004, 0.006)
         rest, area, off, bodies = _assemble([(pts, ar, (64.0, 64.0, 64.0), axis, th0, om)])
-        return Workload("c1", (128, 128, 128), 0.55, (0, 1, 1), forcing, rest, area, off, bodies,
+        return Workload(name, (128, 128, 128), 0.55, (0, 1, 1), forcing, rest, area, off, bodies,
                         5, 1000, hh)
     if name in ("c2", "c2_dense"):
         hh = (0.7 if name == "c2" else 0.41) if h is None else h
