@@ -425,6 +425,20 @@ __device__ __forceinline__ void tile_origin(const PointGeom& pg, uint32_t t, int
   o[2] = (int)(t / ((uint32_t)pg.tiles[0] * (uint32_t)pg.tiles[1])) * TILE;
 }
 
+// U (the forcing's velocity scratch) is stored tile-major: tile t holds its
+// 512 cells (x fastest) for component 0, then 1, then 2, so that a tile's
+// U is 6 KB of consecutive words.
+__device__ __forceinline__ int64_t u_index(uint32_t tile, int comp, int local) {
+  return ((int64_t)tile * 3 + comp) * TILE3 + local;
+}
+__device__ __forceinline__ int64_t u_index_cell(const PointGeom& pg, int x, int y, int z, int comp) {
+  const uint32_t t = (uint32_t)(x >> TILE_SHIFT) +
+                     (uint32_t)pg.tiles[0] * ((uint32_t)(y >> TILE_SHIFT) +
+                                              (uint32_t)pg.tiles[1] * (uint32_t)(z >> TILE_SHIFT));
+  const int l = (x & (TILE - 1)) + TILE * ((y & (TILE - 1)) + TILE * (z & (TILE - 1)));
+  return u_index(t, comp, l);
+}
+
 // Velocity U = sum e f / rho (eq. 1) of the post-stream populations on the
 // flagged 4^3 blocks of every touched tile (the paper's lbm_u_start limited
 // to the cells the supports reach).  512 threads: one wave per 8x8 z-plane.
@@ -453,10 +467,10 @@ __global__ __launch_bounds__(TILE3) void k_moments_blocks(
       jz += EZ[i] * f[i];
     }
     const float inv = 1.0f / (1.0f + drho);
-    const int64_t cell = (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
-    U[cell] = jx * inv;
-    U[g.ncell + cell] = jy * inv;
-    U[2 * g.ncell + cell] = jz * inv;
+    const uint32_t t = touch_tiles[e];
+    U[u_index(t, 0, threadIdx.x)] = jx * inv;
+    U[u_index(t, 1, threadIdx.x)] = jy * inv;
+    U[u_index(t, 2, threadIdx.x)] = jz * inv;
   }
 }
 
@@ -541,10 +555,10 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
       const int cx = tap_coord(o[0] - 1 + bx, pg.n[0], pg.bc[0]);
       const int cy = tap_coord(o[1] - 1 + by, pg.n[1], pg.bc[1]);
       const int cz = tap_coord(o[2] - 1 + bz, pg.n[2], pg.bc[2]);
-      const int64_t c = (int64_t)cx + (int64_t)pg.n[0] * ((int64_t)cy + (int64_t)pg.n[1] * cz);
+      const int64_t c = u_index_cell(pg, cx, cy, cz, 0);
       sU[0][i] = U[c];
-      sU[1][i] = U[pg.ncell + c];
-      sU[2][i] = U[2 * pg.ncell + c];
+      sU[1][i] = U[c + TILE3];
+      sU[2][i] = U[c + 2 * TILE3];
     }
     __syncthreads();
     const uint32_t p0 = start_own[t], p1 = start_own[t + 1];
@@ -809,15 +823,16 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
               s2 += box[2 * BOX3 + bi];
             }
       }
-      const int64_t c = (int64_t)x + (int64_t)pg.n[0] * ((int64_t)y + (int64_t)pg.n[1] * z);
-      if (mode == 2) {
+      if (mode == 2) {  // G, in the lattice layout read by the stream-collide
+        const int64_t c = (int64_t)x + (int64_t)pg.n[0] * ((int64_t)y + (int64_t)pg.n[1] * z);
         target[c] = s0;
         target[pg.ncell + c] = s1;
         target[2 * pg.ncell + c] = s2;
-      } else if (s0 != 0.0f || s1 != 0.0f || s2 != 0.0f) {
+      } else if (s0 != 0.0f || s1 != 0.0f || s2 != 0.0f) {  // U, tile-major
+        const int64_t c = u_index(t, 0, cell);
         target[c] += s0;
-        target[pg.ncell + c] += s1;
-        target[2 * pg.ncell + c] += s2;
+        target[c + TILE3] += s1;
+        target[c + 2 * TILE3] += s2;
       }
     }
   }

@@ -27,7 +27,7 @@ struct Plan {
   // points
   size_t o_rest, o_body_of, o_key, o_rank, o_base, o_frac, o_ub, o_g, o_du, o_bodies, o_motion;
   size_t o_nbr, o_g0, o_feat, o_vref, o_theta, o_packed;
-  size_t o_box;
+  size_t o_box, o_G;
   int64_t max_boxes;
   // tiles
   size_t o_cnt_own, o_cnt_touch, o_start_own, o_own_slot, o_own_tiles, o_touch_tiles, o_meta,
@@ -118,10 +118,6 @@ void make_plan(const lbm_params* p, Plan& pl) {
   pl.pop_stride = align_up((size_t)pl.ncell * pl.elem) / pl.elem;
   pl.lat_bytes = pl.pop_stride * pl.elem * lbmd::Q;
   pl.size[LBM_BUF_LATTICE] = 2 * pl.lat_bytes;
-  // U, G, and the spread boxes of the tiles that own points (at most one per
-  // tile and one per point)
-  pl.size[LBM_BUF_FIELDS] = 2 * align_up(3 * (size_t)pl.ncell * sizeof(float));
-
   const size_t M = (size_t)std::max<int64_t>(p->max_points, 1);
   const int dims[3] = {p->nx, p->ny, p->nz};
   for (int a = 0; a < 3; ++a) {
@@ -129,6 +125,10 @@ void make_plan(const lbm_params* p, Plan& pl) {
     pl.fblk[a] = (dims[a] + lbmd::FBLK - 1) / lbmd::FBLK;
   }
   pl.ntiles = (int64_t)pl.tiles[0] * pl.tiles[1] * pl.tiles[2];
+  // U (tile-major, whole tiles), G (lattice layout), and the spread boxes of
+  // the tiles that own points (at most one per tile and one per point)
+  pl.o_G = align_up((size_t)pl.ntiles * 3 * lbmd::TILE * lbmd::TILE * lbmd::TILE * sizeof(float));
+  pl.size[LBM_BUF_FIELDS] = pl.o_G + align_up(3 * (size_t)pl.ncell * sizeof(float));
   pl.max_boxes = std::max<int64_t>(1, std::min<int64_t>(pl.ntiles, p->max_points));
   pl.o_box = pl.size[LBM_BUF_FIELDS];
   pl.size[LBM_BUF_FIELDS] += align_up((size_t)pl.max_boxes * 3 * 11 * 11 * 11 * sizeof(float));
@@ -338,7 +338,7 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->lat[1] = L + pl.lat_bytes;
   char* F = (char*)bufs[LBM_BUF_FIELDS];
   c->U = (float*)F;
-  c->G = (float*)(F + align_up(3 * (size_t)pl.ncell * sizeof(float)));
+  c->G = (float*)(F + pl.o_G);
   char* P = (char*)bufs[LBM_BUF_POINTS];
   c->rest = (float4*)(P + pl.o_rest);
   c->body_of = (int32_t*)(P + pl.o_body_of);
@@ -388,7 +388,7 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   if (e == hipSuccess) e = launch_fill_u32(c, c->meta, 0u, 4);
   if (e == hipSuccess) e = launch_fill_u32(c, c->ctl, 0u, 4);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->bflag, 0u, c->nbflag_words);
-  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->U, 0u, 3 * c->ncell);
+  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->U, 0u, pl.o_G / sizeof(float));
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->G, 0u, 3 * c->ncell);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->sum_partials, 0u, 8 * c->n_cell_blocks);
   if (e == hipSuccess) e = launch_init_equilibrium(c);
