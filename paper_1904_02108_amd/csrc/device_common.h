@@ -31,18 +31,28 @@ __host__ __device__ constexpr double wgt_d(int i) {
 template <int S>
 struct Store;
 
+// load_nt / store_nt: the same access with a non-temporal (streaming) hint,
+// for the stream-collide's lattice reads and writes.
 template <>
 struct Store<LBM_STORE_F32> {
   using T = float;
   static __device__ __forceinline__ float load(const T* p) { return *p; }
+  static __device__ __forceinline__ float load_nt(const T* p) { return __builtin_nontemporal_load(p); }
   static __device__ __forceinline__ void store(T* p, float v) { *p = v; }
+  static __device__ __forceinline__ void store_nt(T* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 
 template <>
 struct Store<LBM_STORE_F16> {
   using T = _Float16;
   static __device__ __forceinline__ float load(const T* p) { return (float)*p; }
+  static __device__ __forceinline__ float load_nt(const T* p) {
+    return (float)__builtin_nontemporal_load(p);
+  }
   static __device__ __forceinline__ void store(T* p, float v) { *p = (_Float16)v; }
+  static __device__ __forceinline__ void store_nt(T* p, float v) {
+    __builtin_nontemporal_store((_Float16)v, p);
+  }
 };
 
 template <>
@@ -51,14 +61,19 @@ struct Store<LBM_STORE_BF16> {
   static __device__ __forceinline__ float load(const T* p) {
     return __uint_as_float(((uint32_t)*p) << 16);
   }
-  static __device__ __forceinline__ void store(T* p, float v) {
+  static __device__ __forceinline__ float load_nt(const T* p) {
+    return __uint_as_float(((uint32_t)__builtin_nontemporal_load(p)) << 16);
+  }
+  static __device__ __forceinline__ uint16_t bits(float v) {
     uint32_t u = __float_as_uint(v);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
-      *p = (uint16_t)((u >> 16) | 0x40u);  // keep NaN quiet
-      return;
-    }
-    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-    *p = (uint16_t)(u >> 16);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+      return (uint16_t)((u >> 16) | 0x40u);  // keep NaN quiet
+    u += 0x7fffu + ((u >> 16) & 1u);        // round to nearest even
+    return (uint16_t)(u >> 16);
+  }
+  static __device__ __forceinline__ void store(T* p, float v) { *p = bits(v); }
+  static __device__ __forceinline__ void store_nt(T* p, float v) {
+    __builtin_nontemporal_store(bits(v), p);
   }
 };
 
@@ -165,23 +180,26 @@ __device__ __forceinline__ PullIdx pull_index(const LatticeGeom& g, int x, int y
 
 // Pull gather away from walls: 19 loads at uniform per-population bases plus
 // 32-bit cell offsets.
-template <int S>
+template <int S, bool NT = false>
 __device__ __forceinline__ void gather_fast(const typename Store<S>::T* __restrict__ lat,
                                             const LatticeGeom& g, const PullIdx& p, float f[Q]) {
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const typename Store<S>::T* base = lat + (int64_t)i * g.stride;
-    f[i] = Store<S>::load(base + (p.xs[EX[i] + 1] + p.ys[EY[i] + 1] + p.zs[EZ[i] + 1]));
+    const typename Store<S>::T* q =
+        lat + (int64_t)i * g.stride + (p.xs[EX[i] + 1] + p.ys[EY[i] + 1] + p.zs[EZ[i] + 1]);
+    f[i] = NT ? Store<S>::load_nt(q) : Store<S>::load(q);
   }
 }
 
-// Pull gather at any cell: the fast form away from walls, the general one next to them.
-template <int S>
+// Pull gather at any cell: the fast form away from walls, the general one
+// next to them.  NT: streaming loads (the stream-collide reads each value
+// once per step, from the L2 at most a few times).
+template <int S, bool NT = false>
 __device__ __forceinline__ void gather_any(const typename Store<S>::T* __restrict__ lat,
                                            const LatticeGeom& g, int x, int y, int z, float f[Q]) {
   const PullIdx p = pull_index(g, x, y, z);
   if (p.fast)
-    gather_fast<S>(lat, g, p, f);
+    gather_fast<S, NT>(lat, g, p, f);
   else
     gather_pull<S>(lat, g, x, y, z, f);
 }

@@ -23,20 +23,25 @@ __device__ __forceinline__ void cell_xyz(const LatticeGeom& g, int64_t cell, int
 // velocity-shift or Guo forcing, store the post-collision offsets.  Each
 // workgroup also writes FP64 partial sums of (rho - 1, rho U).
 // ---------------------------------------------------------------------------
+#ifndef LBM_SC_ROWS
+#define LBM_SC_ROWS 1
+#endif
 template <int S, int FORCING>
 __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
     const typename Store<S>::T* __restrict__ src, typename Store<S>::T* __restrict__ dst,
     const LatticeGeom g, const float* __restrict__ G, const uint8_t* __restrict__ flags,
     double* __restrict__ partials) {
-  // 3-D launch: blockDim.x spans x, blockDim.y spans y, one z-plane per block row
+  // 3-D launch: blockDim.x spans x, blockDim.y spans y, one z-plane per block
+  // row; each workgroup takes LBM_SC_ROWS consecutive block rows along y
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int r = 0; r < LBM_SC_ROWS; ++r) {
+  const int y = (blockIdx.y * LBM_SC_ROWS + r) * blockDim.y + threadIdx.y;
   if (x < g.nx && y < g.ny) {
     const uint32_t cell = (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
     float f[Q];
-    gather_any<S>(src, g, x, y, z, f);
+    gather_any<S, true>(src, g, x, y, z, f);
   float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -77,12 +82,13 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
         const float eF = EX[i] * fx + EY[i] * fy + EZ[i] * fz;
         post += guo * wgt(i) * (3.0f * (eF - uF) + 9.0f * eu * eF);
       }
-      Store<S>::store(dst + (int64_t)i * g.stride + cell, post);
+      Store<S>::store_nt(dst + (int64_t)i * g.stride + cell, post);
     }
-    part[0] = drho;
-    part[1] = jx;
-    part[2] = jy;
-    part[3] = jz;
+    part[0] += drho;
+    part[1] += jx;
+    part[2] += jy;
+    part[3] += jz;
+  }
   }
   __shared__ double red[4][LBM_BLOCK / 64];
   const int tid = threadIdx.x + blockDim.x * threadIdx.y;
@@ -249,7 +255,8 @@ void stream_collide_shape(const lbm_ctx* c, dim3& grid, dim3& block) {
   if (bx > LBM_BLOCK) bx = LBM_BLOCK;
   const int by = LBM_BLOCK / bx;
   block = dim3(bx, by, 1);
-  grid = dim3((c->p.nx + bx - 1) / bx, (c->p.ny + by - 1) / by, c->p.nz);
+  const int rows = (c->p.ny + by - 1) / by;
+  grid = dim3((c->p.nx + bx - 1) / bx, (rows + LBM_SC_ROWS - 1) / LBM_SC_ROWS, c->p.nz);
 }
 
 namespace {
