@@ -322,13 +322,26 @@ __device__ __forceinline__ double rest_dist2(float4 a, float4 b) {
   return (dx * dx + dy * dy) + dz * dz;
 }
 
+// Lattice-frame separation of two binned points along one axis (nearest
+// image on periodic axes).
+__device__ __forceinline__ float lat_sep(int b0, float f0, int b1, float f1, int n, int bc) {
+  float d = (float)(b1 - b0) + (f1 - f0);
+  if (bc == LBM_BC_PERIODIC) {
+    const float h = 0.5f * (float)n;
+    if (d > h) d -= (float)n;
+    else if (d < -h) d += (float)n;
+  }
+  return fabsf(d);
+}
+
 __global__ __launch_bounds__(256) void k_neighbours(
     const uint32_t* __restrict__ start_own, const int4* __restrict__ sp_base,
-    const float4* __restrict__ rest, const int32_t* __restrict__ body_of, int64_t npts,
-    NbrGeom ng, int32_t* __restrict__ nbr) {
+    const float4* __restrict__ sp_frac, const float4* __restrict__ rest,
+    const int32_t* __restrict__ body_of, int64_t npts, NbrGeom ng, int32_t* __restrict__ nbr) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= npts) return;
   const int4 b = sp_base[k];
+  const float4 fk = sp_frac[k];
   const int me = b.w;
   const float4 rk = rest[me];
   const int body = body_of[me];
@@ -349,8 +362,17 @@ __global__ __launch_bounds__(256) void k_neighbours(
         const uint32_t t = (uint32_t)tx[ix] +
                            (uint32_t)ng.tiles[0] * ((uint32_t)ty[iy] + (uint32_t)ng.tiles[1] * (uint32_t)tz[iz]);
         const uint32_t q1 = start_own[t + 1];
+#pragma unroll 4
         for (uint32_t q = start_own[t]; q < q1; ++q) {
-          const int id = sp_base[q].w;
+          // cheap filter in the lattice frame (the rigid motion keeps
+          // distances; 1e-3 covers the rounding of the FP32 fractions)
+          const int4 qb = sp_base[q];
+          const float4 qf = sp_frac[q];
+          if (lat_sep(b.x, fk.x, qb.x, qf.x, ng.n[0], ng.bc[0]) >= 2.001f ||
+              lat_sep(b.y, fk.y, qb.y, qf.y, ng.n[1], ng.bc[1]) >= 2.001f ||
+              lat_sep(b.z, fk.z, qb.z, qf.z, ng.n[2], ng.bc[2]) >= 2.001f)
+            continue;
+          const int id = qb.w;
           if (id == me || body_of[id] != body) continue;
           const double d2 = rest_dist2(rk, rest[id]);
           // (the sentinel 4.0 must not admit points at distance exactly 2)
@@ -674,8 +696,8 @@ hipError_t launch_neighbours(lbm_ctx* c) {
   }
   const unsigned nb = (unsigned)((c->npts + 255) / 256);
   if (nb == 0) return hipSuccess;
-  k_neighbours<<<nb, 256, 0, c->stream>>>(c->start_own, c->sp_base, c->rest, c->body_of, c->npts,
-                                          ng, c->nbr);
+  k_neighbours<<<nb, 256, 0, c->stream>>>(c->start_own, c->sp_base, c->sp_frac, c->rest,
+                                          c->body_of, c->npts, ng, c->nbr);
   return hipGetLastError();
 }
 
