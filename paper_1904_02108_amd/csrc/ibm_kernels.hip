@@ -562,6 +562,7 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
     }
     __syncthreads();
     const uint32_t p0 = start_own[t], p1 = start_own[t + 1];
+    const uint32_t P = p1 - p0;
     // pass 1: interpolation, deficit, correction (or, spreading only, the
     // bound of the spread vector)
     float bsum = 0.0f;
@@ -571,7 +572,8 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
       const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
       bsum += vs * fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
     }
-    for (uint32_t k = p0 + threadIdx.x; interp && k < p1; k += WG) {
+    for (uint32_t i = threadIdx.x; interp && i < P; i += WG) {
+      const uint32_t k = p0 + i;
       const int4 b = sp_base[k];
       const float4 fr = sp_frac[k];
       float wx[4], wy[4], wz[4];
@@ -634,10 +636,10 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
     // same LDS words tap after tap; a stride coprime to the point count deals
     // them to the lanes in scattered order, and each lane starts at its own
     // z-plane.
-    const uint32_t L = p1 - p0;
-    const uint32_t P = (L % 97u) ? 97u : 89u;
-    const uint32_t step = L ? (uint32_t)(((uint64_t)WG * P) % L) : 0u;
-    uint32_t pos = L ? (uint32_t)(((uint64_t)threadIdx.x * P) % L) : 0u;
+    const uint32_t L = P;
+    const uint32_t stride = (L % 97u) ? 97u : 89u;
+    const uint32_t step = L ? (uint32_t)(((uint64_t)WG * stride) % L) : 0u;
+    uint32_t pos = L ? (uint32_t)(((uint64_t)threadIdx.x * stride) % L) : 0u;
     const int zrot = lane & 3;
     for (uint32_t i = threadIdx.x; i < L; i += WG) {
       const uint32_t k = p0 + pos;
@@ -739,6 +741,7 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
     const uint32_t* __restrict__ gate) {
   __shared__ int16_t ct[3][TILE][MAXCOV], cb[3][TILE][MAXCOV];
   __shared__ int cn[3][TILE];
+  __shared__ int32_t nslot[27];
   if (gate && *gate) return;  // the forcing has already converged
   const ListRange lr = list_range(meta[1]);
   for (uint32_t e = lr.e; e < lr.end; e += lr.step) {
@@ -754,7 +757,13 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
     bool simple = true;
     for (int a = 0; a < 3; ++a)
       simple = simple && tc[a] >= 1 && (tc[a] + 2) * TILE <= pg.n[a];
-    if (!simple) {  // general covering tables (short axes, seams, short tiles)
+    if (simple) {  // list slots of the 27 tiles around this one
+      if (threadIdx.x < 27) {
+        const int dx = threadIdx.x % 3 - 1, dy = (threadIdx.x / 3) % 3 - 1, dz = threadIdx.x / 9 - 1;
+        nslot[threadIdx.x] = own_slot[tile_index(pg, tc[0] + dx, tc[1] + dy, tc[2] + dz)];
+      }
+      __syncthreads();
+    } else {  // general covering tables (short axes, seams, short tiles)
       if (threadIdx.x < 3 * TILE) {
         const int a = threadIdx.x / TILE, l = threadIdx.x % TILE;
         const int x = o[a] + l;
@@ -799,8 +808,7 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
   #pragma unroll
             for (int jx = 0; jx < 2; ++jx) {
               if (jx >= nn[0] || jy >= nn[1] || jz >= nn[2]) continue;
-              const int32_t slot =
-                  own_slot[tile_index(pg, tc[0] + nd[0][jx], tc[1] + nd[1][jy], tc[2] + nd[2][jz])];
+              const int32_t slot = nslot[(nd[0][jx] + 1) + 3 * (nd[1][jy] + 1) + 9 * (nd[2][jz] + 1)];
               if (slot < 0) continue;
               const int bi = nb[0][jx] + BOX * (nb[1][jy] + BOX * nb[2][jz]);
               const float* box = boxbuf + (int64_t)slot * 3 * BOX3;
