@@ -252,7 +252,7 @@ lbm_status lbm_write_fields(lbm_ctx* ctx, uint32_t mask, const lbm_fields* src);
 lbm_status ibm_set_mlp(lbm_ctx* ctx, const float* theta);
 
 /* Training pairs of the last forcing (after ibm_force_iterate or lbm_step)
- * of a surface set with IBM_KEEP_FEATURES or IBM_WARM_START: features
+ * of a surface set with IBM_KEEP_FEATURES: features
  * [n][12] (those of the first sweep) and the target du / (s v_ref) [n][3]
  * of the final correction du, in the order given to ibm_set_points, into
  * caller device memory (enqueued on the context's stream).  LBM_ERR_STATE

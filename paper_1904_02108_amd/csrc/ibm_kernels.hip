@@ -166,7 +166,7 @@ __device__ __forceinline__ uint32_t agg_increment(uint32_t* counters, uint32_t k
   return slot;
 }
 
-// Pass 1: owner tile and rank of each point; count of points per touched tile.
+// Pass 1: owner tile and rank of each point; flags of the touched tiles.
 __global__ __launch_bounds__(LBM_BLOCK) void k_point_count(
     const float4* __restrict__ rest, const int32_t* __restrict__ body_of,
     const BodyMotion* __restrict__ motion, int64_t npts, PointGeom pg, uint32_t* __restrict__ key,
@@ -189,18 +189,12 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_point_count(
     sy = span_axis(ps.base[1], pg.n[1], pg.bc[1], TILE_SHIFT);
     sz = span_axis(ps.base[2], pg.n[2], pg.bc[2], TILE_SHIFT);
   }
-  // spans of at most two tiles per axis (every grid with tiles of >= 3
-  // cells); the third tile of a short last tile comes in the second loop
-  const bool wide = __ballot(valid && (sx.n > 2 || sy.n > 2 || sz.n > 2)) != 0;
-  const int jn = wide ? 27 : 8;
-  for (int j = 0; j < jn; ++j) {
-    const int jx = wide ? j % 3 : (j & 1), jy = wide ? (j / 3) % 3 : ((j >> 1) & 1),
-              jz = wide ? j / 9 : (j >> 2);
-    const bool v = valid && jx < sx.n && jy < sy.n && jz < sz.n;
-    if (!__ballot(v)) continue;
-    const uint32_t t = v ? tile_index(pg, sx.at(jx), sy.at(jy), sz.at(jz)) : 0u;
-    agg_increment(cnt_touch, t, v);
-  }
+  // the tiles the support reaches are only flagged (the scan needs whether a
+  // tile is touched, not how often): idempotent stores, no atomics
+  if (valid)
+    for (int jz = 0; jz < sz.n; ++jz)
+      for (int jy = 0; jy < sy.n; ++jy)
+        for (int jx = 0; jx < sx.n; ++jx) cnt_touch[tile_index(pg, sx.at(jx), sy.at(jy), sz.at(jz))] = 1u;
 }
 
 // Pass 2: exclusive scan of the owner counts and the compact lists of tiles
@@ -1110,9 +1104,12 @@ hipError_t launch_forcing(lbm_ctx* c) {
                                            last ? 1 : 0, use_thr, c->ctl);
     TRY(hipGetLastError());
     if (it == 0 && feats) {
+      // features stored (for logging, or for the FP32 network), else
+      // computed inside the matrix-core warm-start kernel
       const bool fp32 = (c->flags & IBM_MLP_FP32) != 0;
-      TRY(launch_features_warm(c, warm && fp32));
-      if (warm && !fp32) TRY(launch_warm_mfma(c));
+      const bool keep = (c->flags & IBM_KEEP_FEATURES) != 0;
+      if (keep || fp32) TRY(launch_features_warm(c, warm && fp32));
+      if (warm && !fp32) TRY(launch_warm_mfma(c, keep));
     }
     if (it == 0 && warm && !last) {
       TRY(sweep(0, SW_SPREAD_DU, c->ctl, nullptr));

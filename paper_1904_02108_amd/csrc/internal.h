@@ -56,7 +56,7 @@ struct lbm_ctx {
   int64_t nblocks4 = 0;        // number of 4^3 force blocks
   int64_t nbflag_words = 0;    // bflag size in 32-bit words
   uint32_t* cnt_own = nullptr;     // [ntiles] points owned per tile (pass 1)
-  uint32_t* cnt_touch = nullptr;   // [ntiles] points touching each tile (pass 1)
+  uint32_t* cnt_touch = nullptr;   // [ntiles] 1 where a support reaches the tile (pass 1)
   uint32_t* start_own = nullptr;   // [ntiles + 1]
   int32_t* own_slot = nullptr;     // [ntiles] index in own_tiles, or -1
   uint32_t* own_tiles = nullptr;   // compact list of tiles owning points
@@ -138,5 +138,5 @@ hipError_t launch_neighbours(lbm_ctx* c);
 hipError_t launch_features_warm(lbm_ctx* c, bool predict);
 hipError_t launch_export_pairs(lbm_ctx* c, float* feat, float* targets);
 hipError_t launch_mlp_pack(lbm_ctx* c);
-hipError_t launch_warm_mfma(lbm_ctx* c);
+hipError_t launch_warm_mfma(lbm_ctx* c, bool from_stored_features);
 constexpr size_t MLP_PACKED_BYTES = 22 * 64 * 16;  // 22 operands x 64 lanes x 8 BF16

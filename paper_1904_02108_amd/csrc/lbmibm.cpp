@@ -548,7 +548,7 @@ lbm_status ibm_set_mlp(lbm_ctx* c, const float* theta) {
 lbm_status ibm_log_pairs(lbm_ctx* c, float* features, float* targets) {
   if (!c) return LBM_ERR_ARG;
   if (!features || !targets) return fail(c, LBM_ERR_ARG, "NULL destination");
-  if (!(c->flags & (IBM_KEEP_FEATURES | IBM_WARM_START)))
+  if (!(c->flags & IBM_KEEP_FEATURES))
     return fail(c, LBM_ERR_STATE, "the surface was set without IBM_KEEP_FEATURES");
   if (c->npts == 0 || c->g_valid_step < 0)
     return fail(c, LBM_ERR_STATE, "no forcing has run for the current points");

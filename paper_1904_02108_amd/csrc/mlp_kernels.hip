@@ -248,13 +248,66 @@ __global__ __launch_bounds__(MFMA_WG) void k_mlp_forward_mfma(const u32x4* __res
   }
 }
 
-// Warm start from the stored features (sorted order): du = s v_ref y, unless
-// the forcing has already converged (*gate).
+// Elements 8 h .. 8 h + 7 of the features of point k (sorted order; the same
+// definition as k_features_warm): g0, u_b, mean and component-wise max of g0
+// over N(k), divided by v_ref.
+__device__ __forceinline__ void features8(int64_t k, int64_t n, int h,
+                                          const int4* __restrict__ sp_base,
+                                          const float4* __restrict__ sp_g,
+                                          const float4* __restrict__ sp_ub,
+                                          const float4* __restrict__ g0_orig,
+                                          const int32_t* __restrict__ nbr,
+                                          const int32_t* __restrict__ body_of,
+                                          const float* __restrict__ vref, float x8[8]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) x8[e] = 0.0f;
+  if (k >= n) return;
+  const int orig = sp_base[k].w;
+  const float inv = 1.0f / vref[body_of[orig]];
+  float m[3] = {0.f, 0.f, 0.f}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int cnt = 0;
+  for (int j = 0; j < NNBR; ++j) {
+    const int q = nbr[(int64_t)orig * NNBR + j];
+    if (q < 0) break;
+    const float4 gq = g0_orig[q];
+    m[0] += gq.x;
+    m[1] += gq.y;
+    m[2] += gq.z;
+    mx[0] = fmaxf(mx[0], gq.x);
+    mx[1] = fmaxf(mx[1], gq.y);
+    mx[2] = fmaxf(mx[2], gq.z);
+    ++cnt;
+  }
+  const float mean[3] = {cnt ? m[0] / (float)cnt * inv : 0.0f, cnt ? m[1] / (float)cnt * inv : 0.0f,
+                         cnt ? m[2] / (float)cnt * inv : 0.0f};
+  if (h == 0) {
+    const float4 g = sp_g[k], ub = sp_ub[k];
+    x8[0] = g.x * inv;
+    x8[1] = g.y * inv;
+    x8[2] = g.z * inv;
+    x8[3] = ub.x * inv;
+    x8[4] = ub.y * inv;
+    x8[5] = ub.z * inv;
+    x8[6] = mean[0];
+    x8[7] = mean[1];
+  } else {
+    x8[0] = mean[2];
+    x8[1] = cnt ? mx[0] * inv : 0.0f;
+    x8[2] = cnt ? mx[1] * inv : 0.0f;
+    x8[3] = cnt ? mx[2] * inv : 0.0f;
+  }
+}
+
+// Warm start: du = s v_ref y, unless the forcing has already converged
+// (*gate).  Features from the stored array (feat != nullptr, sorted order) or
+// computed here from the first deficit.
 __global__ __launch_bounds__(MFMA_WG) void k_warm_mfma(
     const u32x4* __restrict__ packed, const float* __restrict__ theta, int64_t n,
     const float* __restrict__ feat, const int4* __restrict__ sp_base,
     const float4* __restrict__ sp_frac, const int32_t* __restrict__ body_of,
-    const float* __restrict__ vref, const uint32_t* __restrict__ gate, float4* __restrict__ sp_du) {
+    const float* __restrict__ vref, const uint32_t* __restrict__ gate, float4* __restrict__ sp_du,
+    const float4* __restrict__ sp_g, const float4* __restrict__ sp_ub,
+    const float4* __restrict__ g0_orig, const int32_t* __restrict__ nbr) {
   __shared__ MfmaWeights W;
   if (*gate) return;
   load_mfma_weights(packed, theta, W);
@@ -264,7 +317,10 @@ __global__ __launch_bounds__(MFMA_WG) void k_warm_mfma(
        g += (int64_t)gridDim.x * (MFMA_WG / 64)) {
     const int64_t k = 32 * g + (l & 31);
     float x8[8], yo[3];
-    load_x8(feat, k, n, h, x8);
+    if (feat)
+      load_x8(feat, k, n, h, x8);
+    else
+      features8(k, n, h, sp_base, sp_g, sp_ub, g0_orig, nbr, body_of, vref, x8);
     mlp_group_mfma(W, x8, yo);
     if (h == 0 && k < n) {
       const float sv = sp_frac[k].w * vref[body_of[sp_base[k].w]];
@@ -715,11 +771,12 @@ hipError_t launch_mlp_pack(lbm_ctx* c) {
   return hipGetLastError();
 }
 
-hipError_t launch_warm_mfma(lbm_ctx* c) {
+hipError_t launch_warm_mfma(lbm_ctx* c, bool from_stored_features) {
   if (c->npts == 0) return hipSuccess;
   k_warm_mfma<<<mfma_grid(c->npts), MFMA_WG, 0, c->stream>>>(
-      (const u32x4*)c->theta_packed, c->theta, c->npts, c->feat, c->sp_base, c->sp_frac,
-      c->body_of, c->vref, c->ctl, c->sp_du);
+      (const u32x4*)c->theta_packed, c->theta, c->npts, from_stored_features ? c->feat : nullptr,
+      c->sp_base, c->sp_frac, c->body_of, c->vref, c->ctl, c->sp_du, c->sp_g, c->sp_ub, c->g0_orig,
+      c->nbr);
   return hipGetLastError();
 }
 

@@ -251,6 +251,22 @@ def test_warm_start_bf16_against_fp32(L):
     assert 0 < e_du < 2e-2 and e_G < 2e-2
 
 
+def test_warm_start_fused_features(L):
+    """Without IBM_KEEP_FEATURES the matrix-core warm start computes the
+    features itself; the result equals the one from the stored features."""
+    wl = W.config("c0")
+    th = W.mlp_init(9, scale=0.7)
+    out = {}
+    for name, flags in (("fused", L.IBM_WARM_START),
+                        ("stored", L.IBM_WARM_START | L.IBM_KEEP_FEATURES)):
+        sim, _, _ = sim_for_workload(L, wl)
+        sim.set_mlp(th)
+        sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 4, flags)
+        sim.step(4)
+        out[name] = to_np(sim.read("pt_du")["pt_du"])
+    assert rel_linf(out["fused"], out["stored"]) < 1e-6
+
+
 def test_warm_start_zero_network(L):
     """A network that predicts 0 wastes one sweep: N warm-started sweeps give
     the force of N - 1 plain sweeps (GPU against GPU, then the oracle)."""
