@@ -186,6 +186,7 @@ def learned_leg(torch, L, W, name="c1", n_pairs_steps=150, epochs=10, eval_steps
             "ms_per_step": round(ms, 4),
             "ms_forcing": round(tm["ms_forcing"] / max(tm["n_forcing"], 1), 4),
             "ms_fluid": round(tm["ms_fluid"] / max(tm["n_fluid"], 1), 4),
+            "ms_step_beyond_fluid": round(ms - tm["ms_fluid"] / max(tm["n_fluid"], 1), 4),
             "MLUPS": round(wl.n_cells / (ms * 1e-3) / 1e6, 2),
             "point_updates_per_s": round(wl.n_points / (ms * 1e-3), 1),
         }
@@ -199,8 +200,10 @@ def learned_leg(torch, L, W, name="c1", n_pairs_steps=150, epochs=10, eval_steps
         "s_collect": round(t_collect, 2), "s_train": round(t_train, 2),
         "variants": variants,
         "sweeps_saved": round(pe["mean_sweeps"] - le["mean_sweeps"], 3),
-        "forcing_speedup_vs_plain_eps": round(pe["ms_forcing"] / le["ms_forcing"], 3),
-        "forcing_speedup_vs_plain_5": round(variants["plain_5"]["ms_forcing"] / le["ms_forcing"], 3),
+        # forcing = the step beyond the fluid (binning included)
+        "forcing_speedup_vs_plain_eps": round(pe["ms_step_beyond_fluid"] / le["ms_step_beyond_fluid"], 3),
+        "forcing_speedup_vs_plain_5": round(variants["plain_5"]["ms_step_beyond_fluid"] /
+                                            le["ms_step_beyond_fluid"], 3),
         "step_speedup_vs_plain_eps": round(pe["ms_per_step"] / le["ms_per_step"], 3),
     }
 
@@ -282,8 +285,12 @@ def main():
         "point_updates_per_s": round(wl.n_points * K / (ms * 1e-3), 1),
         "hbm_frac_full_step": round(mlups * 1e6 * bpc / (HBM_PEAK_GBS * 1e9), 4),
         "ms_fluid": round(fluid_ms, 4),
+        # forcing kernels after the binning (the next step's binning runs on a
+        # second stream beside the stream-collide); the whole step beyond the
+        # fluid is ms_per_step - ms_fluid
         "ms_forcing": round(forcing_ms, 4),
-        "forcing_over_fluid": round(forcing_ms / fluid_ms, 3),
+        "ms_step_beyond_fluid": round(ms_step - fluid_ms, 4),
+        "forcing_over_fluid": round((ms_step - fluid_ms) / fluid_ms, 3),
         "mass_sum": float(sums[0]),
         "mass_rel_drift": float(abs(sums[0] - wl.n_cells) / wl.n_cells),
         "finite": bool(all(map(lambda v: v == v and abs(v) != float("inf"), sums))),
