@@ -71,7 +71,8 @@ enum { ORC_FORCE_GUO = 0, ORC_FORCE_SHIFT = 1 };
 enum {
   ORC_IBM_INNER_UNWEIGHTED = 1,
   ORC_IBM_STOP_RESIDUAL = 2, /* stop once sum s|g|^2 <= eps^2 sum s|u_b|^2 */
-  ORC_IBM_WARM_START = 4     /* learned warm start after the first sweep  */
+  ORC_IBM_WARM_START = 4,    /* learned warm start after the first sweep  */
+  ORC_IBM_WARM_PREV = 32     /* warm start from the previous step's du    */
 };
 enum { ORC_OK = 0, ORC_ERR_DOMAIN = -5 };
 
@@ -517,7 +518,8 @@ void orc_mlp_forward(const double* theta, int64_t n, const double* x, double* y)
  * With ORC_IBM_WARM_START (an extension, not in the paper) the first sweep
  * that does not stop replaces its correction: du(k) = s(k) v(k) y(k), with
  * y = MLP(theta; features of k) and v(k) the reference speed of k's body,
- * and U_1 = U_0 + spread of du.
+ * and U_1 = U_0 + spread of du.  ORC_IBM_WARM_PREV does the same with the
+ * previous step's final du(k) of the same point (when there is one).
  * U0 is not modified.  resid[it] = sum_k s(k) |g_it(k)|^2.
  * G_out: [3][ncell] overwritten.  du_out, g_out: [n][3] (nullable);
  * feat_out [n][12] (nullable, needs nbr and v_pt); n_sweeps (nullable).
@@ -529,6 +531,7 @@ typedef struct {
   const double* theta; /* MLP parameters (ORC_IBM_WARM_START) */
   const int32_t* nbr;  /* [n][16] neighbour lists (features) */
   const double* v_pt;  /* [n] reference speed of each point's body */
+  const double* du_prev; /* [n][3] previous step's du (ORC_IBM_WARM_PREV; NULL: none) */
 } orc_ibm_opts;
 
 static int ibm_core(const orc_params* p, int64_t npts, const double* x,
@@ -538,6 +541,7 @@ static int ibm_core(const orc_params* p, int64_t npts, const double* x,
   const int64_t n = ncells(p);
   const int64_t m = npts > 0 ? npts : 1;
   const int warm = (o->flags & ORC_IBM_WARM_START) != 0;
+  const int warm_prev = (o->flags & ORC_IBM_WARM_PREV) && o->du_prev;
   const int want_feat = warm || feat_out;
   double* u = (double*)malloc(sizeof(double) * 3 * m);
   double* g = (double*)malloc(sizeof(double) * 3 * m);
@@ -573,6 +577,9 @@ static int ibm_core(const orc_params* p, int64_t npts, const double* x,
       orc_mlp_forward(o->theta, npts, feat, y);
       for (int64_t k = 0; k < npts; ++k)
         for (int a = 0; a < 3; ++a) du[3 * k + a] = s[k] * o->v_pt[k] * y[3 * k + a];
+      err = orc_spread(p, npts, x, du, U);
+    } else if (it == 0 && warm_prev) {
+      memcpy(du, o->du_prev, sizeof(double) * 3 * npts);
       err = orc_spread(p, npts, x, du, U);
     } else {
       for (int64_t k = 0; k < npts; ++k)
@@ -638,6 +645,7 @@ typedef struct {
   const orc_body* bodies;
   double eps;           /* ORC_IBM_STOP_RESIDUAL threshold */
   const double* theta;  /* ORC_IBM_WARM_START parameters */
+  const double* du_prev; /* ORC_IBM_WARM_PREV: du of the step before the first (nullable) */
 } orc_points;
 
 typedef struct {
@@ -657,6 +665,8 @@ typedef struct {
   double *fn, *rho, *U, *G, *x, *ub;
   int32_t* nbr;  /* neighbour lists, found once per run when needed */
   double* v_pt;
+  double* du_prev;  /* the last step's du within a run (ORC_IBM_WARM_PREV) */
+  int have_prev;
 } orc_ws;
 
 static void ws_alloc(orc_ws* w, int64_t n, int64_t m) {
@@ -669,6 +679,8 @@ static void ws_alloc(orc_ws* w, int64_t n, int64_t m) {
   w->ub = (double*)malloc(sizeof(double) * 3 * m);
   w->nbr = NULL;
   w->v_pt = NULL;
+  w->du_prev = (double*)malloc(sizeof(double) * 3 * m);
+  w->have_prev = 0;
 }
 
 static void ws_free(orc_ws* w) {
@@ -680,6 +692,7 @@ static void ws_free(orc_ws* w) {
   free(w->ub);
   free(w->nbr);
   free(w->v_pt);
+  free(w->du_prev);
 }
 
 /* Neighbour lists and per-point reference speeds of the warm start. */
@@ -717,10 +730,17 @@ static int step_into(const orc_params* p, const double* f, const orc_points* pts
     o.theta = pts->theta;
     o.nbr = w->nbr;
     o.v_pt = w->v_pt;
-    err = ibm_core(p, m, w->x, w->ub, pts->area, w->U, &o, w->G,
-                   out ? out->du : NULL, out ? out->g : NULL,
-                   out ? out->resid : NULL, out ? out->feat : NULL,
-                   out ? out->n_sweeps : NULL);
+    o.du_prev = w->have_prev ? w->du_prev : pts->du_prev;
+    double* du_new = (double*)malloc(sizeof(double) * 3 * m);
+    err = ibm_core(p, m, w->x, w->ub, pts->area, w->U, &o, w->G, du_new,
+                   out ? out->g : NULL, out ? out->resid : NULL,
+                   out ? out->feat : NULL, out ? out->n_sweeps : NULL);
+    if (err == ORC_OK) {
+      if (out && out->du) memcpy(out->du, du_new, sizeof(double) * 3 * m);
+      memcpy(w->du_prev, du_new, sizeof(double) * 3 * m);
+      w->have_prev = 1;
+    }
+    free(du_new);
     if (out && out->x) memcpy(out->x, w->x, sizeof(double) * 3 * m);
     if (out && out->ub) memcpy(out->ub, w->ub, sizeof(double) * 3 * m);
     G = w->G;

@@ -31,6 +31,7 @@ FORCE_GUO, FORCE_SHIFT = 0, 1
 IBM_INNER_UNWEIGHTED = 1
 IBM_STOP_RESIDUAL = 2
 IBM_WARM_START = 4
+IBM_WARM_PREV = 32
 
 
 def build(force: bool = False) -> str:
@@ -55,12 +56,13 @@ class _Points(ct.Structure):
     _fields_ = [("npts", ct.c_int64), ("rest", ct.c_void_p), ("area", ct.c_void_p),
                 ("body_off", ct.c_void_p), ("nbodies", ct.c_int32), ("n_iter", ct.c_int32),
                 ("flags", ct.c_int32), ("pad_", ct.c_int32), ("bodies", ct.c_void_p),
-                ("eps", ct.c_double), ("theta", ct.c_void_p)]
+                ("eps", ct.c_double), ("theta", ct.c_void_p), ("du_prev", ct.c_void_p)]
 
 
 class _IbmOpts(ct.Structure):
     _fields_ = [("n_iter", ct.c_int32), ("flags", ct.c_int32), ("eps", ct.c_double),
-                ("theta", ct.c_void_p), ("nbr", ct.c_void_p), ("v_pt", ct.c_void_p)]
+                ("theta", ct.c_void_p), ("nbr", ct.c_void_p), ("v_pt", ct.c_void_p),
+                ("du_prev", ct.c_void_p)]
 
 
 class _StepOut(ct.Structure):
@@ -241,9 +243,10 @@ def ibm(p, x, ub, s, U0, n_iter=5, flags=0):
 
 
 def ibm_ex(p, x, ub, s, U0, n_iter=5, flags=0, eps=0.0, theta=None, nbr=None, v_pt=None,
-           features=False):
+           features=False, du_prev=None):
     """Forcing with every option: residual stop (flags 2, eps), warm start
-    (flags 4, theta, nbr [n,16] int32, v_pt [n]); features=True also returns
+    (flags 4, theta, nbr [n,16] int32, v_pt [n]), warm start from a previous
+    correction (flags 32, du_prev [n,3]); features=True also returns
     the features of the first sweep (needs nbr and v_pt).  Returns a dict
     with G, du, g (last sweep), resid [n_sweeps], n_sweeps, feat."""
     lib = _load()
@@ -264,6 +267,9 @@ def ibm_ex(p, x, ub, s, U0, n_iter=5, flags=0, eps=0.0, theta=None, nbr=None, v_
     if v_pt is not None:
         keep.append(_f64(v_pt))
         o.v_pt = _ptr(keep[-1])
+    if du_prev is not None:
+        keep.append(_f64(du_prev).reshape(-1, 3))
+        o.du_prev = _ptr(keep[-1])
     res = {"G": np.zeros((3,) + grid_shape(p)), "du": np.zeros((n, 3)), "g": np.zeros((n, 3))}
     resid = np.zeros(max(int(n_iter), 1))
     ns = np.zeros(1, dtype=np.int32)
@@ -327,7 +333,8 @@ def features(g0, ub, nbr, v_pt):
 class Points:
     """Lagrangian surface description handed to the step functions."""
 
-    def __init__(self, rest, area, body_off, bodies, n_iter=5, flags=0, eps=0.0, theta=None):
+    def __init__(self, rest, area, body_off, bodies, n_iter=5, flags=0, eps=0.0, theta=None,
+                 du_prev=None):
         self.rest = _f64(rest).reshape(-1, 3)
         self.area = _f64(area).reshape(-1)
         self.body_off = np.ascontiguousarray(body_off, dtype=np.int64)
@@ -336,9 +343,11 @@ class Points:
         self.flags = int(flags)
         self.eps = float(eps)
         self.theta = None if theta is None else _f64(theta).reshape(-1)
+        self.du_prev = None if du_prev is None else _f64(du_prev).reshape(-1, 3)
         self.c = _Points(self.rest.shape[0], _ptr(self.rest), _ptr(self.area),
                          _ptr(self.body_off), self.bodies.shape[0], self.n_iter,
-                         self.flags, 0, _ptr(self.bodies), self.eps, _ptr(self.theta))
+                         self.flags, 0, _ptr(self.bodies), self.eps, _ptr(self.theta),
+                         _ptr(self.du_prev))
 
     @property
     def n(self):
