@@ -128,12 +128,22 @@ enum {
                                 the body's reference speed; the prediction is
                                 spread into U and the sweeps continue from it.
                                 Useful with IBM_STOP_RESIDUAL, valid alone;
-                                not with IBM_INNER_UNWEIGHTED.                */
+                                not with IBM_INNER_UNWEIGHTED or
+                                IBM_WARM_PREV.                               */
   IBM_KEEP_FEATURES = 8u,    /* compute the features in every forcing so that
                                 ibm_log_pairs can export training pairs       */
-  IBM_MLP_FP32 = 16u         /* evaluate the warm-start network in FP32 on the
+  IBM_MLP_FP32 = 16u,        /* evaluate the warm-start network in FP32 on the
                                 vector units; default: BF16 operands on the
                                 matrix cores with FP32 accumulation           */
+  IBM_WARM_PREV = 32u        /* warm start from the previous forcing (not in
+                                the paper; the non-learned baseline of
+                                IBM_WARM_START): after the first deficit g0,
+                                the final du of the same point in the last
+                                forcing replaces s g0, is spread into U and
+                                the sweeps continue from it.  The first
+                                forcing after ibm_set_points or a write of
+                                LBM_F_POPS has no previous du and runs the
+                                plain first sweep.  Not with IBM_WARM_START. */
 };
 
 /* mlp_forward precision */

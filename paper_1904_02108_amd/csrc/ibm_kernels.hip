@@ -512,6 +512,8 @@ enum : int {
   SW_SPREAD_G = 4,
   SW_SPREAD_DU = 8,
   SW_UNWEIGHTED = 16,
+  SW_LOAD_PREV = 32,  // spreading du: take it from du_prev (caller order) into sp_du
+  SW_SAVE_DU = 64,    // spreading du: also store it into du_prev (caller order)
 };
 
 
@@ -522,7 +524,7 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
     const float4* __restrict__ sp_frac, const float4* __restrict__ sp_ub,
     float4* __restrict__ sp_g, float4* __restrict__ sp_du, const float* __restrict__ U,
     float* __restrict__ boxbuf, PointGeom pg, int mode, double* __restrict__ part_res,
-    const uint32_t* __restrict__ gate, float4* __restrict__ g_orig) {
+    const uint32_t* __restrict__ gate, float4* __restrict__ g_orig, float4* __restrict__ du_prev) {
   // U of the box during the interpolation, then (same storage) the integer
   // accumulators of the spread: x and y packed in 64 bits, z in 32 bits
   __shared__ __align__(16) float sU[3][BOX3];
@@ -536,6 +538,8 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
   const bool spread_g = mode & SW_SPREAD_G, spread_du = mode & SW_SPREAD_DU;
   const bool spread = spread_g || spread_du;
   const bool inner_weighted = !(mode & SW_UNWEIGHTED);
+  const bool load_prev = spread_du && (mode & SW_LOAD_PREV);
+  const bool save_du = spread_du && (mode & SW_SAVE_DU);
   double res = 0.0;  // this thread's part of sum s |g|^2 over the workgroup's tiles
   const ListRange lr = list_range(meta[0]);
   for (uint32_t e = lr.e; e < lr.end; e += lr.step) {
@@ -562,7 +566,13 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
     float bsum = 0.0f;
     for (uint32_t k = p0 + threadIdx.x; !interp && k < p1; k += WG) {
       const float4 fr = sp_frac[k];
-      const float4 v = spread_du ? sp_du[k] : sp_g[k];
+      float4 v;
+      if (load_prev) {
+        v = du_prev[sp_base[k].w];
+        sp_du[k] = v;  // read again only by later launches
+      } else {
+        v = spread_du ? sp_du[k] : sp_g[k];
+      }
       const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
       bsum += vs * fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
     }
@@ -643,7 +653,8 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
       const float4 fr = sp_frac[k];
       float v0, v1, v2;
       if (spread_du) {
-        const float4 du = sp_du[k];
+        const float4 du = load_prev ? du_prev[b.w] : sp_du[k];
+        if (save_du) du_prev[b.w] = du;
         v0 = du.x * scale;
         v1 = du.y * scale;
         v2 = du.z * scale;
@@ -1058,7 +1069,7 @@ hipError_t launch_forcing(lbm_ctx* c) {
   auto sweep = [&](int it, int mode, const uint32_t* gate, float4* g_orig) {
     k_sweep_tiles<<<lg, WG, 0, st>>>(c->own_tiles, c->meta, c->start_own, c->sp_base, c->sp_frac,
                                      c->sp_ub, c->sp_g, c->sp_du, c->U, c->boxbuf, pg, mode | uw,
-                                     c->pt_partials + (2 + it) * rs, gate, g_orig);
+                                     c->pt_partials + (2 + it) * rs, gate, g_orig, c->du_prev);
     return hipGetLastError();
   };
   auto merge = [&](bool final_, const uint32_t* gate) {
@@ -1072,7 +1083,7 @@ hipError_t launch_forcing(lbm_ctx* c) {
     if (e_ != hipSuccess) return e_;         \
   } while (0)
   const int N = c->n_iter;
-  if (!(c->flags & (IBM_STOP_RESIDUAL | IBM_WARM_START))) {
+  if (!(c->flags & (IBM_STOP_RESIDUAL | IBM_WARM_START | IBM_WARM_PREV))) {
     // fixed number of sweeps; the last one spreads du into G
     for (int it = 0; it < N; ++it) {
       const bool last = it == N - 1;
@@ -1087,6 +1098,8 @@ hipError_t launch_forcing(lbm_ctx* c) {
   // gated by the device flag ctl[0], so the sequence runs without host round
   // trips; the final spread of du into G always runs.
   const bool warm = (c->flags & IBM_WARM_START) != 0;
+  const bool save_prev = (c->flags & IBM_WARM_PREV) != 0;
+  const bool from_prev = save_prev && c->du_prev_valid;
   const int use_thr = (c->flags & IBM_STOP_RESIDUAL) ? 1 : 0;
   const int64_t na = (n + LBM_BLOCK - 1) / LBM_BLOCK;
   k_resid_threshold<<<1, LBM_BLOCK, 0, st>>>(c->pt_partials + rs, na,
@@ -1095,9 +1108,9 @@ hipError_t launch_forcing(lbm_ctx* c) {
   for (int it = 0; it < N; ++it) {
     const bool last = it == N - 1;
     const uint32_t* gate = it == 0 ? nullptr : c->ctl;
-    // sweep 0 under a warm start only interpolates: the predicted du is
-    // spread in place of s g0
-    const bool spread = !last && !(warm && it == 0);
+    // sweep 0 under a warm start only interpolates: the predicted (or the
+    // previous forcing's) du is spread in place of s g0
+    const bool spread = !last && !((warm || from_prev) && it == 0);
     const int mode = SW_INTERP | (it == 0 ? SW_FIRST : 0) | (spread ? SW_SPREAD_G : 0);
     TRY(sweep(it, mode, gate, it == 0 && feats ? c->g0_orig : nullptr));
     k_resid_check<<<1, LBM_BLOCK, 0, st>>>(c->pt_partials + (2 + it) * rs, lg, c->resid_thr, it,
@@ -1114,11 +1127,14 @@ hipError_t launch_forcing(lbm_ctx* c) {
     if (it == 0 && warm && !last) {
       TRY(sweep(0, SW_SPREAD_DU, c->ctl, nullptr));
       TRY(merge(false, c->ctl));
+    } else if (it == 0 && from_prev && !last) {
+      TRY(sweep(0, SW_SPREAD_DU | SW_LOAD_PREV, c->ctl, nullptr));
+      TRY(merge(false, c->ctl));
     } else if (spread) {
       TRY(merge(false, c->ctl));
     }
   }
-  TRY(sweep(0, SW_SPREAD_DU, nullptr, nullptr));
+  TRY(sweep(0, SW_SPREAD_DU | (save_prev ? SW_SAVE_DU : 0), nullptr, nullptr));
   TRY(merge(true, nullptr));
 #undef TRY
   return hipSuccess;

@@ -67,6 +67,7 @@ struct lbm_ctx {
   // learned warm start
   int32_t* nbr = nullptr;       // [max_points][16] neighbour lists (caller order)
   float4* g0_orig = nullptr;    // [max_points] first deficit (caller order)
+  float4* du_prev = nullptr;    // [max_points] last forcing's du (caller order)
   float* feat = nullptr;        // [max_points][12] features of the last forcing (sorted)
   float* vref = nullptr;        // [LBM_MAX_BODIES] reference speed per body
   float* theta = nullptr;       // [IBM_MLP_NPARAM] network parameters
@@ -89,6 +90,7 @@ struct lbm_ctx {
   uint32_t flags = 0;
   float eps = 0.0f;
   bool nbr_valid = false;   // neighbour lists match the current surface
+  bool du_prev_valid = false;  // du_prev holds a forcing of the current surface
   bool theta_set = false;   // ibm_set_mlp has been called
   int64_t step = 0;
   int64_t g_valid_step = -1;

@@ -26,7 +26,7 @@ struct Plan {
   size_t elem, pop_stride, lat_bytes;
   // points
   size_t o_rest, o_body_of, o_key, o_rank, o_base, o_frac, o_ub, o_g, o_du, o_bodies, o_motion;
-  size_t o_nbr, o_g0, o_feat, o_vref, o_theta, o_packed;
+  size_t o_nbr, o_g0, o_duprev, o_feat, o_vref, o_theta, o_packed;
   size_t o_box, o_G;
   int64_t max_boxes;
   // tiles
@@ -149,6 +149,7 @@ void make_plan(const lbm_params* p, Plan& pl) {
   pl.o_motion = pc.take((size_t)LBM_MAX_BODIES * sizeof(BodyMotion));
   pl.o_nbr = pc.take(M * IBM_MLP_NNBR * sizeof(int32_t));
   pl.o_g0 = pc.take(M * sizeof(float4));
+  pl.o_duprev = pc.take(M * sizeof(float4));
   pl.o_feat = pc.take(M * IBM_MLP_NFEAT * sizeof(float));
   pl.o_vref = pc.take((size_t)LBM_MAX_BODIES * sizeof(float));
   pl.o_theta = pc.take((size_t)IBM_MLP_NPARAM * sizeof(float));
@@ -260,6 +261,7 @@ lbm_status do_forcing(lbm_ctx* c) {
   if (e != hipSuccess) return hip_fail(c, e, "forcing");
   ev_record(c, 0, false);
   if (c->ev_used > 4000) ev_collect(c);
+  if (c->flags & IBM_WARM_PREV) c->du_prev_valid = true;
   c->g_valid_step = c->step;
   return LBM_OK;
 }
@@ -274,7 +276,7 @@ lbm_status read_stats(lbm_ctx* c, ibm_stats* stats) {
   HIP_TRY(c, hipMemcpyAsync(h, c->small, sizeof(double) * (2 + c->n_iter), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(ctl, c->ctl, sizeof(ctl), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  const bool gated = (c->flags & (IBM_STOP_RESIDUAL | IBM_WARM_START)) != 0;
+  const bool gated = (c->flags & (IBM_STOP_RESIDUAL | IBM_WARM_START | IBM_WARM_PREV)) != 0;
   const int ran = gated ? std::min<int>((int)ctl[1], c->n_iter) : c->n_iter;
   std::memset(stats, 0, sizeof(*stats));
   stats->n_iter = ran;
@@ -353,6 +355,7 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->motion = (BodyMotion*)(P + pl.o_motion);
   c->nbr = (int32_t*)(P + pl.o_nbr);
   c->g0_orig = (float4*)(P + pl.o_g0);
+  c->du_prev = (float4*)(P + pl.o_duprev);
   c->feat = (float*)(P + pl.o_feat);
   c->vref = (float*)(P + pl.o_vref);
   c->theta = (float*)(P + pl.o_theta);
@@ -445,8 +448,11 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
   if (n_iter < 1 || n_iter > c->p.max_iter)
     return fail(c, LBM_ERR_ARG, "n_iter must be in [1, max_iter]");
   const uint32_t known =
-      IBM_INNER_UNWEIGHTED | IBM_STOP_RESIDUAL | IBM_WARM_START | IBM_KEEP_FEATURES | IBM_MLP_FP32;
+      IBM_INNER_UNWEIGHTED | IBM_STOP_RESIDUAL | IBM_WARM_START | IBM_KEEP_FEATURES | IBM_MLP_FP32 |
+      IBM_WARM_PREV;
   if (flags & ~known) return fail(c, LBM_ERR_ARG, "unknown flags");
+  if ((flags & IBM_WARM_START) && (flags & IBM_WARM_PREV))
+    return fail(c, LBM_ERR_ARG, "IBM_WARM_START and IBM_WARM_PREV exclude each other");
   if ((flags & IBM_WARM_START) && (flags & IBM_INNER_UNWEIGHTED))
     return fail(c, LBM_ERR_ARG, "IBM_WARM_START needs the weighted inner sweep");
   if (flags & IBM_STOP_RESIDUAL) {
@@ -510,6 +516,7 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
   c->flags = flags;
   c->eps = (flags & IBM_STOP_RESIDUAL) ? eps : 0.0f;
   c->nbr_valid = false;
+  c->du_prev_valid = false;
   c->meta_pending = false;  // the stream has been synchronised above
   c->prev_len_valid = false;
   c->g_valid_step = -1;
@@ -712,6 +719,7 @@ lbm_status lbm_write_fields(lbm_ctx* c, uint32_t mask, const lbm_fields* src) {
     if (e != hipSuccess) return hip_fail(c, e, "write pops");
     if (!dev) HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->g_valid_step = -1;
+    c->du_prev_valid = false;
   }
   if (mask & LBM_F_FORCE) {
     Staging st;

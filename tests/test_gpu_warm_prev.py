@@ -1,0 +1,112 @@
+"""GPU parity of the forcing warm-started from the previous step's
+correction (IBM_WARM_PREV) against the FP64 oracle, through the C
+interface: fixed sweep counts, the residual stop, the unweighted inner
+sweep, the reset on ibm_set_points and the flag checks."""
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_common import rel_linf, sim_for_workload, to_np
+from paper_1904_02108_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1904_02108_amd import lbmibm
+    return lbmibm
+
+
+def _oracle_steps(p, f, wl, n_iter, flags, t0, t1, du_prev=None, eps=0.0):
+    """Oracle steps t0 .. t1-1 on f, each warm-started from the du of the
+    one before (the first from du_prev, or plain when it is None)."""
+    r = None
+    for t in range(t0, t1):
+        pts = O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, n_iter, flags, eps,
+                       du_prev=du_prev)
+        r = O.step(p, f, pts, t)
+        du_prev = r["du"]
+    return r
+
+
+@pytest.mark.parametrize("n_iter,unweighted", [(2, False), (4, False), (3, True)])
+def test_warm_prev_parity(L, n_iter, unweighted):
+    """C0, 6 steps warm-started from the previous correction: the
+    corrections after 5 steps, then the 6th step's correction, force and
+    sweep residuals match the oracle."""
+    wl = W.config("c0")
+    flags = O.IBM_WARM_PREV | (O.IBM_INNER_UNWEIGHTED if unweighted else 0)
+    print("warm-prev parity: C0, n_iter", n_iter, "unweighted", unweighted, flush=True)
+    sim, p, _ = sim_for_workload(L, wl)
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, n_iter, flags)
+    sim.step(5)
+    f = O.init_equilibrium(p)
+    r4 = _oracle_steps(p, f, wl, n_iter, flags, 0, 5)
+    assert rel_linf(to_np(sim.read("pt_du")["pt_du"]), r4["du"]) < 1e-5
+    f_plain = f.copy()
+    st = sim.force_iterate(stats=True)
+    r = _oracle_steps(p, f, wl, n_iter, flags, 5, 6, du_prev=r4["du"])
+    assert st["n_iter"] == r["n_sweeps"] == n_iter
+    np.testing.assert_allclose(st["resid"], r["resid"], rtol=1e-4)
+    out = sim.read("force", "pt_du")
+    assert rel_linf(to_np(out["pt_du"]), r["du"]) < 1e-5
+    assert rel_linf(to_np(out["force"]), r["G"]) < 1e-5
+    # (whether it pays depends on the case: the oracle's plain step for context)
+    plain = O.step(p, f_plain, O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, n_iter,
+                                        flags & O.IBM_INNER_UNWEIGHTED), 5)
+    print("sum s|g|^2 after sweep 1: warm", r["resid"][1], "plain", plain["resid"][1], flush=True)
+
+
+def test_warm_prev_residual_stop(L):
+    """C0, 7 steps with the residual stop at eps = 0.3: every step stops at
+    the oracle's sweep (7, 4, 1, 3, 3, 2, 2 sweeps; step 2 stops at its first
+    deficit and carries s g0 alone), with the oracle's residuals; the last
+    correction matches.  The oracle's residuals stay at least 2% away from
+    eps at every step, so rounding cannot move a stopping sweep."""
+    wl = W.config("c0")
+    flags = O.IBM_WARM_PREV | O.IBM_STOP_RESIDUAL
+    eps = 0.3
+    sim, p, _ = sim_for_workload(L, wl)
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 8, flags, eps)
+    f = O.init_equilibrium(p)
+    du = None
+    counts = []
+    for t in range(7):
+        r = O.step(p, f, O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, 8, flags, eps,
+                                  du_prev=du), t)
+        du = r["du"]
+        _, ub = O.kinematics(wl.rest, wl.body_off, wl.bodies, t)
+        sub2 = float((wl.area.astype(np.float64)[:, None] * ub ** 2).sum())
+        assert np.abs(np.log(np.sqrt(r["resid"] / sub2) / eps)).min() > 0.02
+        sim.step(1)
+        st = sim.last_stats()
+        counts.append((st["n_iter"], r["n_sweeps"]))
+        print("step", t, "sweeps gpu", st["n_iter"], "oracle", r["n_sweeps"], flush=True)
+        assert st["n_iter"] == r["n_sweeps"]
+        np.testing.assert_allclose(st["resid"], r["resid"], rtol=1e-4)
+    assert min(c[1] for c in counts) == 1 and max(c[1] for c in counts) >= 4
+    assert rel_linf(to_np(sim.read("pt_du")["pt_du"]), r["du"]) < 1e-5
+
+
+def test_warm_prev_reset_and_flags(L):
+    """ibm_set_points drops the previous correction (the next forcing is the
+    plain one); IBM_WARM_PREV excludes IBM_WARM_START."""
+    wl = W.config("c0")
+    a, p, _ = sim_for_workload(L, wl)
+    a.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 4, L.IBM_WARM_PREV)
+    a.step(3)
+    a.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 4, L.IBM_WARM_PREV)
+    a.force_iterate()
+    b, _, _ = sim_for_workload(L, wl)
+    b.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 4, L.IBM_WARM_PREV)
+    b.step(3)
+    b.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 4, 0)
+    b.force_iterate()
+    ga, gb = to_np(a.read("force")["force"]), to_np(b.read("force")["force"])
+    assert rel_linf(ga, gb) < 1e-6
+    with pytest.raises(L.LbmError):
+        a.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, 4,
+                     L.IBM_WARM_PREV | L.IBM_WARM_START)
