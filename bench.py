@@ -105,10 +105,12 @@ def copy_bandwidth(torch, nbytes, reps=5):
 def learned_leg(torch, L, W, name="c1", n_pairs_steps=150, epochs=10, eval_steps=40, warm=5):
     """C4: the warm-start network trained on the GPU from plain runs of the
     single-propeller geometry with other seeds (1-8), then the canonical
-    single-propeller case (seed 0, held out) run three ways: plain with a
-    fixed 5 sweeps, plain to the residual threshold, and warm-started to the
-    same threshold.  The threshold is the median relative residual that the
-    plain method reaches at its 5th sweep on the held-out case."""
+    single-propeller case (seed 0, held out) run four ways: plain with a
+    fixed 5 sweeps, plain to the residual threshold, warm-started from the
+    previous step's correction (the non-learned baseline) and warm-started
+    by the network, both to the same threshold.  The threshold is the median
+    relative residual that the plain method reaches at its 5th sweep on the
+    held-out case."""
     import numpy as np
 
     from paper_1904_02108_amd import learned as LN
@@ -162,6 +164,7 @@ def learned_leg(torch, L, W, name="c1", n_pairs_steps=150, epochs=10, eval_steps
     # confirms that every step still met the threshold.
     for vname, flags, th in (("plain_5", 0, None),
                              ("plain_eps", L.IBM_STOP_RESIDUAL, None),
+                             ("prev_eps", L.IBM_STOP_RESIDUAL | L.IBM_WARM_PREV, None),
                              ("learned_eps", L.IBM_STOP_RESIDUAL | L.IBM_WARM_START, theta)):
         cap = 5 if not flags else 12
         sim = LN.surface_sim(wl, flags, cap, eps if flags else 0.0, theta=th)
@@ -172,7 +175,9 @@ def learned_leg(torch, L, W, name="c1", n_pairs_steps=150, epochs=10, eval_steps
         if flags:
             cap = int(min(12, sweeps.max() + 1))
             sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, cap, flags, eps)
-            sim.step(2)  # a new surface rebuilds its neighbour lists once: not timed
+            # a new surface rebuilds its neighbour lists once and has no
+            # previous correction yet: not timed
+            sim.step(2)
         ms, tm = timed(sim, eval_steps)
         check = LN.residual_history(sim, 20)
         met = [bool(rr[n - 1] <= eps * (1 + 1e-9)) for n, rr in check] if flags else None
@@ -191,7 +196,7 @@ def learned_leg(torch, L, W, name="c1", n_pairs_steps=150, epochs=10, eval_steps
             "point_updates_per_s": round(wl.n_points / (ms * 1e-3), 1),
         }
         sim.close()
-    pe, le = variants["plain_eps"], variants["learned_eps"]
+    pe, le, qe = variants["plain_eps"], variants["learned_eps"], variants["prev_eps"]
     return {
         "workload": "%s (seed 0, held out, %d points); training pairs from %s seeds 1-8"
                     % (name, wl.n_points, name),
@@ -205,7 +210,76 @@ def learned_leg(torch, L, W, name="c1", n_pairs_steps=150, epochs=10, eval_steps
         "forcing_speedup_vs_plain_5": round(variants["plain_5"]["ms_step_beyond_fluid"] /
                                             le["ms_step_beyond_fluid"], 3),
         "step_speedup_vs_plain_eps": round(pe["ms_per_step"] / le["ms_per_step"], 3),
+        "sweeps_saved_vs_prev_eps": round(qe["mean_sweeps"] - le["mean_sweeps"], 3),
+        "forcing_speedup_vs_prev_eps": round(qe["ms_step_beyond_fluid"] / le["ms_step_beyond_fluid"], 3),
     }
+
+
+def precision_leg(torch, L, W, name, storage, steps=10, warmup=3):
+    """C3: the same workload with populations stored as FP16 or BF16 offsets
+    (FP32 arithmetic): MLUPS and the stream-collide against the 76 B/cell
+    roofline (errors against the FP64 oracle are in the GPU tests)."""
+    wl = W.config(name)
+    sim = L.Simulation(wl.shape, wl.tau, bc=wl.bc, storage=storage, forcing=wl.forcing,
+                       max_points=wl.n_points, max_iter=wl.n_iter, device="cuda:0")
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    L.lbm_set_timing(sim.ctx, 1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    tm = L.lbm_get_timing(sim.ctx)
+    sim.close()
+    fluid = tm["ms_fluid"] / max(tm["n_fluid"], 1)
+    bpc = BYTES_PER_CELL[storage]
+    ach = bpc * wl.n_cells / (fluid * 1e-3) / 1e9
+    return {"MLUPS": round(wl.n_cells / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
+            "ms_fluid": round(fluid, 4), "fluid_MLUPS": round(wl.n_cells / (fluid * 1e-3) / 1e6, 1),
+            "stream_collide_GBs": round(ach, 1), "stream_collide_frac": round(ach / HBM_PEAK_GBS, 4),
+            "bytes_per_cell": bpc, "steps": steps, "warmup": warmup}
+
+
+# Best MLUPS the paper reports for its family on a Tesla P100 (§6; kernel
+# strategy): other hardware and another propeller mesh, context only.
+PAPER_P100_MLUPS = {1: 893.0, 6: 650.0, 18: 344.2}
+
+
+def paper_family_leg(torch, L, W, steps=20, warmup=5):
+    """§6's test-case family: 160 x 160 x 320 with 1-6 and 18 propellers of
+    3930 points each, plain forcing with 5 sweeps, FP32 storage, Guo forcing:
+    MLUPS and point updates per second per propeller count."""
+    out = {}
+    for k in W.PAPER_FAMILY_COUNTS:
+        wl = W.config("paper%d" % k)
+        sim = L.Simulation(wl.shape, wl.tau, bc=wl.bc, forcing=wl.forcing,
+                           max_points=wl.n_points, max_iter=wl.n_iter, device="cuda:0")
+        sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        L.lbm_set_timing(sim.ctx, 1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        tm = L.lbm_get_timing(sim.ctx)
+        sim.close()
+        fluid = tm["ms_fluid"] / max(tm["n_fluid"], 1)
+        r = {"points": wl.n_points, "MLUPS": round(wl.n_cells / (ms * 1e-3) / 1e6, 1),
+             "ms_per_step": round(ms, 4), "ms_fluid": round(fluid, 4),
+             "ms_step_beyond_fluid": round(ms - fluid, 4),
+             "point_updates_per_s": round(wl.n_points / (ms * 1e-3), 1)}
+        if k in PAPER_P100_MLUPS:
+            r["paper_p100_MLUPS"] = PAPER_P100_MLUPS[k]
+        out[str(k)] = r
+    return {"workload": "160x160x320 periodic, tau 0.6, propellers of 3930 points (h 1) on "
+                        "columns along z, omega 0.004, 5 sweeps, FP32, Guo",
+            "steps": steps, "warmup": warmup, "by_propellers": out}
 
 
 def main():
@@ -218,6 +292,10 @@ def main():
     ap.add_argument("--forcing", default="guo", choices=["guo", "shift"])
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP16 / BF16 storage runs of the same workload")
+    ap.add_argument("--no-paper-family", action="store_true",
+                    help="skip the 160x160x320 runs with 1-6 and 18 propellers")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm-start comparison on the single-propeller case")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -303,6 +381,12 @@ def main():
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if not args.no_precision:
+        out["precision"] = {sname: precision_leg(torch, L, W, args.workload, st)
+                            for sname, st in (("f16", L.LBM_STORE_F16), ("bf16", L.LBM_STORE_BF16))}
+        torch.cuda.empty_cache()
+    if not args.no_paper_family:
+        out["paper_family"] = paper_family_leg(torch, L, W)
     if not args.no_learned:
         out["learned"] = {}
         for name, n_steps in (("c1", 150), ("c1_dense", 60)):
