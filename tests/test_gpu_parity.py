@@ -278,6 +278,13 @@ def test_c2_dense_first_steps(L):
     _run_compare(L, W.config("c2_dense"), 2, [1, 2], tol_last=TOL_STEP)
 
 
+@pytest.mark.parametrize("n_props", [1, 18])
+def test_paper_family_first_steps(L, n_props):
+    """The §6 test-case family at full size (160 x 160 x 320, 3930 points per
+    propeller): three steps from rest, every cell and point compared."""
+    _run_compare(L, W.config("paper%d" % n_props), 3, [1, 3], tol_last=TOL_STEP)
+
+
 # ---------------------------------------------------------- error paths
 def test_error_paths(L):
     shape = (16, 16, 16)

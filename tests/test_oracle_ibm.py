@@ -234,6 +234,30 @@ def test_propeller_area_and_symmetry():
     assert np.abs((wl.area[:, None] * ub).sum(0)).max() < 1e-6
 
 
+def test_paper_family_inputs():
+    """The stand-in of the paper's test-case family (§6): 3930 points per
+    propeller, 70 740 for 18, point areas near one cell face, every
+    propeller's support inside the 160 x 160 x 320 box, and the swept discs
+    (tip radius 34) of different propellers disjoint."""
+    for k in W.PAPER_FAMILY_COUNTS:
+        wl = W.config("paper%d" % k)
+        assert wl.shape == (160, 160, 320) and wl.n_points == 3930 * k
+        assert np.all(np.diff(wl.body_off) == 3930)
+        assert abs(float(wl.area.astype(np.float64).mean()) - 1.0) < 0.05
+        r = np.linalg.norm(wl.rest[:, :2].astype(np.float64), axis=1).max()
+        assert abs(r - 34.0) < 1e-4
+        c = wl.bodies[:, :3]
+        lo = c - [r + 2, r + 2, 13 + 2]
+        hi = c + [r + 2, r + 2, 13 + 2]
+        assert (lo >= 0).all() and (hi <= [160, 160, 320]).all()
+        for i in range(k):
+            for j in range(i):
+                dxy = np.hypot(*(c[i, :2] - c[j, :2]))
+                dz = abs(c[i, 2] - c[j, 2])
+                assert dxy > 2 * r or dz > 24 + 2, (i, j)
+    assert W.config("paper18").n_points == 70740
+
+
 # ------------------------------------------------------------ whole step
 def test_step_with_ibm_invariants():
     """A full step with a rotating body in a periodic box: mass unchanged and
