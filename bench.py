@@ -282,6 +282,41 @@ def paper_family_leg(torch, L, W, steps=20, warmup=5):
             "steps": steps, "warmup": warmup, "by_propellers": out}
 
 
+def u_strategy_leg(torch, L, W, cases=(("paper1", 10), ("paper6", 10), ("paper18", 10),
+                                        ("c2_dense", 5)), warmup=3):
+    """§5's U pre-pass strategies (SURVEY ablation): the box strategy (U on
+    each body's moved bounding box), the kernel strategy (U on every
+    point's support cells, shared cells recomputed) and the default tile mask
+    (U on the 4^3 blocks some support reaches), same results, timed on the
+    paper's family and the dense 64-propeller case (plain 5 sweeps, FP32)."""
+    out = {}
+    for name, steps in cases:
+        wl = W.config(name)
+        row = {"points": wl.n_points}
+        for sname, flags in (("tile_mask", 0), ("box", L.IBM_U_BOX), ("kernel", L.IBM_U_KERNEL)):
+            sim = L.Simulation(wl.shape, wl.tau, bc=wl.bc, forcing=wl.forcing,
+                               max_points=wl.n_points, max_iter=wl.n_iter, device="cuda:0")
+            sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter, flags)
+            sim.step(warmup)
+            torch.cuda.synchronize()
+            L.lbm_set_timing(sim.ctx, 1)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sim.step(steps)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            tm = L.lbm_get_timing(sim.ctx)
+            sim.close()
+            fluid = tm["ms_fluid"] / max(tm["n_fluid"], 1)
+            row[sname] = {"MLUPS": round(wl.n_cells / (ms * 1e-3) / 1e6, 1),
+                          "ms_per_step": round(ms, 4),
+                          "ms_step_beyond_fluid": round(ms - fluid, 4)}
+        out[name] = row
+        torch.cuda.empty_cache()
+    return {"steps": {n: k for n, k in cases}, "warmup": warmup, "by_workload": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,6 +331,8 @@ def main():
                     help="skip the FP16 / BF16 storage runs of the same workload")
     ap.add_argument("--no-paper-family", action="store_true",
                     help="skip the 160x160x320 runs with 1-6 and 18 propellers")
+    ap.add_argument("--no-u-strategy", action="store_true",
+                    help="skip the box / kernel / tile-mask U pre-pass comparison")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm-start comparison on the single-propeller case")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -387,6 +424,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_paper_family:
         out["paper_family"] = paper_family_leg(torch, L, W)
+    if not args.no_u_strategy:
+        out["u_strategy"] = u_strategy_leg(torch, L, W)
     if not args.no_learned:
         out["learned"] = {}
         for name, n_steps in (("c1", 150), ("c1_dense", 60)):

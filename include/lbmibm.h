@@ -135,7 +135,7 @@ enum {
   IBM_MLP_FP32 = 16u,        /* evaluate the warm-start network in FP32 on the
                                 vector units; default: BF16 operands on the
                                 matrix cores with FP32 accumulation           */
-  IBM_WARM_PREV = 32u        /* warm start from the previous forcing (not in
+  IBM_WARM_PREV = 32u,       /* warm start from the previous forcing (not in
                                 the paper; the non-learned baseline of
                                 IBM_WARM_START): after the first deficit g0,
                                 the final du of the same point in the last
@@ -144,6 +144,18 @@ enum {
                                 forcing after ibm_set_points or a write of
                                 LBM_F_POPS has no previous du and runs the
                                 plain first sweep.  Not with IBM_WARM_START. */
+  IBM_U_BOX = 64u,           /* U pre-pass (§5) by the box strategy: U on every
+                                cell of each body's bounding box, the rest-
+                                position box of its points moved by the step's
+                                rigid motion, widened by the kernel support   */
+  IBM_U_KERNEL = 128u        /* U pre-pass by the kernel strategy (§5): U on
+                                the 4^3 support cells of every point (cells
+                                shared by several supports are computed once
+                                per point).  Default (neither bit): U on the
+                                4^3 blocks that some support reaches.  All
+                                three give the same U wherever it is read, so
+                                the results are identical; only the time
+                                differs.  Not both.                          */
 };
 
 /* mlp_forward precision */

@@ -433,9 +433,33 @@ __device__ __forceinline__ int64_t u_index_cell(const PointGeom& pg, int x, int 
   return u_index(t, comp, l);
 }
 
-// Velocity U = sum e f / rho (eq. 1) of the post-stream populations on the
-// flagged 4^3 blocks of every touched tile (the paper's lbm_u_start limited
-// to the cells the supports reach).  512 threads: one wave per 8x8 z-plane.
+// Velocity U = sum e f / rho (eq. 1) of the post-stream populations at one
+// cell, stored in the tile-major U array.  Every U pre-pass strategy uses
+// this one function, so all of them give bit-identical values.
+template <int S>
+__device__ __forceinline__ void cell_velocity(const typename Store<S>::T* __restrict__ lat,
+                                              const LatticeGeom& g, const PointGeom& pg, int x,
+                                              int y, int z, float* __restrict__ U) {
+  float f[Q];
+  gather_any<S>(lat, g, x, y, z, f);
+  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += f[i];
+    jx += EX[i] * f[i];
+    jy += EY[i] * f[i];
+    jz += EZ[i] * f[i];
+  }
+  const float inv = 1.0f / (1.0f + drho);
+  const int64_t c = u_index_cell(pg, x, y, z, 0);
+  U[c] = jx * inv;
+  U[c + TILE3] = jy * inv;
+  U[c + 2 * TILE3] = jz * inv;
+}
+
+// U pre-pass, tile-mask strategy (default): the flagged 4^3 blocks of every
+// touched tile, i.e. the paper's lbm_u_start limited to the blocks the
+// supports reach.  512 threads: one wave per 8x8 z-plane.
 template <int S>
 __global__ __launch_bounds__(TILE3) void k_moments_blocks(
     const typename Store<S>::T* __restrict__ lat, const LatticeGeom g, PointGeom pg,
@@ -450,22 +474,80 @@ __global__ __launch_bounds__(TILE3) void k_moments_blocks(
     const int z = o[2] + (threadIdx.x >> (2 * TILE_SHIFT));
     if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
     if (!bflag[fblock_of(g, x, y, z)]) continue;
-    float f[Q];
-    gather_any<S>(lat, g, x, y, z, f);
-    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      drho += f[i];
-      jx += EX[i] * f[i];
-      jy += EY[i] * f[i];
-      jz += EZ[i] * f[i];
-    }
-    const float inv = 1.0f / (1.0f + drho);
-    const uint32_t t = touch_tiles[e];
-    U[u_index(t, 0, threadIdx.x)] = jx * inv;
-    U[u_index(t, 1, threadIdx.x)] = jy * inv;
-    U[u_index(t, 2, threadIdx.x)] = jz * inv;
+    cell_velocity<S>(lat, g, pg, x, y, z, U);
   }
+}
+
+// U pre-pass, box strategy (§5): for each body, the axis-aligned box of its
+// rest-position bounding box (ubox: lo, hi relative to the centre) after the
+// step's rotation, widened to the support cells floor(x)-1 .. floor(x)+2
+// plus one cell.
+// Workgroup blockIdx.x covers body blockIdx.x / sub^3 and the 8^3 sub-block
+// blockIdx.x % sub^3 of a cube of edge 8 sub that bounds every rotation of
+// the box; cells outside the moved box are skipped.  Cells of overlapping
+// boxes are computed once per box (same value).
+template <int S>
+__global__ __launch_bounds__(TILE3) void k_moments_box(
+    const typename Store<S>::T* __restrict__ lat, const LatticeGeom g, PointGeom pg,
+    const BodyMotion* __restrict__ motion, const float* __restrict__ ubox, int sub,
+    float* __restrict__ U) {
+  const int sub3 = sub * sub * sub;
+  const int b = blockIdx.x / sub3, sblk = blockIdx.x - b * sub3;
+  const BodyMotion m = motion[b];
+  // moved box: the 8 corners of the rest box through the rotation
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  const double* a = m.axis;
+  for (int corner = 0; corner < 8; ++corner) {
+    const double r[3] = {(double)ubox[6 * b + ((corner & 1) ? 3 : 0)],
+                         (double)ubox[6 * b + 1 + ((corner & 2) ? 3 : 0)],
+                         (double)ubox[6 * b + 2 + ((corner & 4) ? 3 : 0)]};
+    const double adr = a[0] * r[0] + a[1] * r[1] + a[2] * r[2];
+    const double axr[3] = {a[1] * r[2] - a[2] * r[1], a[2] * r[0] - a[0] * r[2],
+                           a[0] * r[1] - a[1] * r[0]};
+    for (int k = 0; k < 3; ++k) {
+      const double x = m.center[k] + r[k] * m.c + axr[k] * m.s + a[k] * adr * (1.0 - m.c);
+      lo[k] = fmin(lo[k], x);
+      hi[k] = fmax(hi[k], x);
+    }
+  }
+  // support cells floor(x)-1 .. floor(x)+2, one more on each side so that a
+  // point on the box's face cannot fall outside it by rounding
+  int c0[3], c1[3];
+  for (int k = 0; k < 3; ++k) {
+    c0[k] = (int)floor(lo[k]) - 2;
+    c1[k] = (int)floor(hi[k]) + 3;
+  }
+  const int sx = sblk % sub, sy = (sblk / sub) % sub, sz = sblk / (sub * sub);
+  const int v[3] = {c0[0] + TILE * sx + (int)(threadIdx.x & (TILE - 1)),
+                    c0[1] + TILE * sy + (int)((threadIdx.x >> TILE_SHIFT) & (TILE - 1)),
+                    c0[2] + TILE * sz + (int)(threadIdx.x >> (2 * TILE_SHIFT))};
+  int cxyz[3];
+  for (int k = 0; k < 3; ++k) {
+    if (v[k] > c1[k]) return;
+    if (pg.bc[k] == LBM_BC_PERIODIC) {
+      cxyz[k] = tap_coord(v[k], pg.n[k], LBM_BC_PERIODIC);
+    } else {
+      if (v[k] < 0 || v[k] >= pg.n[k]) return;
+      cxyz[k] = v[k];
+    }
+  }
+  cell_velocity<S>(lat, g, pg, cxyz[0], cxyz[1], cxyz[2], U);
+}
+
+// U pre-pass, kernel strategy (§5): one wave per point, one lane per cell of
+// its 4^3 support (the paper uses a CUDA block per point's neighbourhood).
+template <int S>
+__global__ __launch_bounds__(WG) void k_moments_points(
+    const typename Store<S>::T* __restrict__ lat, const LatticeGeom g, PointGeom pg,
+    const int4* __restrict__ sp_base, int64_t npts, float* __restrict__ U) {
+  const int64_t k = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
+  if (k >= npts) return;
+  const int lane = threadIdx.x & 63;
+  const int4 b = sp_base[k];
+  const int x = tap_coord(b.x - 1 + (lane & 3), pg.n[0], pg.bc[0]);
+  const int y = tap_coord(b.y - 1 + ((lane >> 2) & 3), pg.n[1], pg.bc[1]);
+  const int z = tap_coord(b.z - 1 + (lane >> 4), pg.n[2], pg.bc[2]);
+  cell_velocity<S>(lat, g, pg, x, y, z, U);
 }
 
 // 1-D weights of Peskin's 4-point kernel (§3) for the taps floor(x)-1 ..
@@ -494,8 +576,9 @@ __device__ __forceinline__ void peskin4(float r, float w[4]) {
 // tile's points (coordinates wrapped on periodic axes).  The box sum is
 // accumulated in LDS in fixed point with the unit B / 2^30, where
 // B = (1/8) sum_k max_c |v_k,c| bounds every box cell (a tap weight is at
-// most 1/8): no overflow is possible and integer addition makes the sum
-// independent of the order of the atomics.  Components x and y share one
+// most 1/8; the sum is formed exactly in fixed point, bound_units): no
+// overflow is possible and integer addition makes the box independent of the
+// order of the atomics and of the points.  Components x and y share one
 // 64-bit atomic (x sign-extended in the low word, y in the high word: the
 // 64-bit sum is exactly sum_y 2^32 + sum_x, and |sum_x| < 2^31 recovers
 // both), z has its own 32-bit one.  The box is stored as FP32 in the tile's
@@ -506,6 +589,15 @@ __device__ __forceinline__ void peskin4(float r, float w[4]) {
 // nonzero *gate (the forcing has converged) makes the launch a no-op.  Each
 // workgroup writes its FP64 partial of s |g|^2 when interpolating.
 constexpr float FIX_ONE = 1073741824.0f;  // 2^30
+
+// A point's share of the box bound in units of 2^-32, rounded up, capped at
+// 2^12 (far beyond any lattice velocity or correction; a NaN also gives the
+// cap): with up to 2^20 points per tile the 64-bit sum cannot overflow, and
+// integer addition makes the bound independent of the order of the tile's
+// points, which the binning does not fix.
+__device__ __forceinline__ unsigned long long bound_units(float m) {
+  return (unsigned long long)ceilf(fminf(m, 4096.0f) * 4294967296.0f);
+}
 enum : int {
   SW_INTERP = 1,
   SW_FIRST = 2,
@@ -518,7 +610,7 @@ enum : int {
 
 
 
-__global__ __launch_bounds__(WG) void k_sweep_tiles(
+__global__ __launch_bounds__(WG, 7) void k_sweep_tiles(
     const uint32_t* __restrict__ own_tiles, const uint32_t* __restrict__ meta,
     const uint32_t* __restrict__ start_own, const int4* __restrict__ sp_base,
     const float4* __restrict__ sp_frac, const float4* __restrict__ sp_ub,
@@ -530,7 +622,7 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
   __shared__ __align__(16) float sU[3][BOX3];
   unsigned long long* accxy = reinterpret_cast<unsigned long long*>(&sU[0][0]);
   int* accz = reinterpret_cast<int*>(&sU[0][0]) + 2 * BOX3;
-  __shared__ float fred[WG / 64];
+  __shared__ unsigned long long bred[WG / 64];
   __shared__ double dred[WG / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (gate && *gate) return;  // the forcing has already converged
@@ -563,7 +655,7 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
     const uint32_t P = p1 - p0;
     // pass 1: interpolation, deficit, correction (or, spreading only, the
     // bound of the spread vector)
-    float bsum = 0.0f;
+    unsigned long long bsum = 0ull;  // in units of 2^-32 (see bound_units)
     for (uint32_t k = p0 + threadIdx.x; !interp && k < p1; k += WG) {
       const float4 fr = sp_frac[k];
       float4 v;
@@ -574,7 +666,7 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
         v = spread_du ? sp_du[k] : sp_g[k];
       }
       const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
-      bsum += vs * fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z)));
+      bsum += bound_units(vs * fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z))));
     }
     for (uint32_t i = threadIdx.x; interp && i < P; i += WG) {
       const uint32_t k = p0 + i;
@@ -617,18 +709,18 @@ __global__ __launch_bounds__(WG) void k_sweep_tiles(
       const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
       const float v0 = spread_du ? du.x : vs * g0, v1 = spread_du ? du.y : vs * g1,
                   v2 = spread_du ? du.z : vs * g2;
-      bsum += fmaxf(fabsf(v0), fmaxf(fabsf(v1), fabsf(v2)));
+      bsum += bound_units(fmaxf(fabsf(v0), fmaxf(fabsf(v1), fabsf(v2))));
     }
     if (!spread) continue;
-    // block bound B (FP32, fixed order)
+    // block bound B: an exact integer sum, whatever the order of the points
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) bsum += __shfl_xor(bsum, off, 64);
-    if (lane == 0) fred[wave] = bsum;
+    if (lane == 0) bred[wave] = bsum;
     __syncthreads();  // also: the interpolation's reads of sU are done
-    float B = 0.0f;
+    unsigned long long btot = 0ull;
 #pragma unroll
-    for (int w = 0; w < WG / 64; ++w) B += fred[w];
-    B *= 0.125f;
+    for (int w = 0; w < WG / 64; ++w) btot += bred[w];
+    const float B = (float)((double)btot * 0x1p-32) * 0.125f;
     const float scale = B > 0.0f ? FIX_ONE / B : 0.0f;
     for (int i = threadIdx.x; i < BOX3; i += WG) {
       accxy[i] = 0ull;
@@ -1004,6 +1096,29 @@ int64_t forcing_list_grid(const lbm_ctx* c) { return c->own_grid; }
 // The forcing of one time step: motion, binning, U near the surface,
 // n_iter sweeps of interpolation + correction with n_iter - 1 intermediate
 // spreads into U and the final spread of du into G.
+// The U pre-pass of the strategy the surface was set with.
+template <int S>
+hipError_t launch_u_prepass(lbm_ctx* c, const typename Store<S>::T* lat, const PointGeom& pg,
+                            unsigned tg) {
+  hipStream_t st = c->stream;
+  if (c->flags & IBM_U_BOX) {
+    const int64_t sub = c->ubox_sub;
+    const int64_t nblk = (int64_t)c->nbodies * sub * sub * sub;
+    if (nblk > 0)
+      k_moments_box<S><<<(unsigned)nblk, TILE3, 0, st>>>(lat, c->geom, pg, c->motion, c->ubox,
+                                                         (int)sub, c->U);
+  } else if (c->flags & IBM_U_KERNEL) {
+    const int64_t nblk = (c->npts + WG / 64 - 1) / (WG / 64);
+    if (nblk > 0)
+      k_moments_points<S><<<(unsigned)nblk, WG, 0, st>>>(lat, c->geom, pg, c->sp_base, c->npts,
+                                                         c->U);
+  } else {
+    k_moments_blocks<S><<<tg, TILE3, 0, st>>>(lat, c->geom, pg, c->touch_tiles, c->meta,
+                                              c->bflag, c->U);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_forcing(lbm_ctx* c) {
   const PointGeom pg = point_geom(c);
   const int64_t n = c->npts;
@@ -1044,21 +1159,20 @@ hipError_t launch_forcing(lbm_ctx* c) {
                                             c->start_own, c->sp_base, c->sp_frac, c->sp_ub,
                                             c->bflag, c->pt_partials, c->pt_partials + rs);
   LAUNCH_CHECK();
-  const unsigned mg = tg;
-  switch (c->p.storage) {
-    case LBM_STORE_F16:
-      k_moments_blocks<LBM_STORE_F16><<<mg, TILE3, 0, st>>>(
-          (const _Float16*)c->lat[c->cur], c->geom, pg, c->touch_tiles, c->meta, c->bflag, c->U);
-      break;
-    case LBM_STORE_BF16:
-      k_moments_blocks<LBM_STORE_BF16><<<mg, TILE3, 0, st>>>(
-          (const uint16_t*)c->lat[c->cur], c->geom, pg, c->touch_tiles, c->meta, c->bflag, c->U);
-      break;
-    default:
-      k_moments_blocks<LBM_STORE_F32><<<mg, TILE3, 0, st>>>(
-          (const float*)c->lat[c->cur], c->geom, pg, c->touch_tiles, c->meta, c->bflag, c->U);
+  {
+    hipError_t e = hipSuccess;
+    switch (c->p.storage) {
+      case LBM_STORE_F16:
+        e = launch_u_prepass<LBM_STORE_F16>(c, (const _Float16*)c->lat[c->cur], pg, tg);
+        break;
+      case LBM_STORE_BF16:
+        e = launch_u_prepass<LBM_STORE_BF16>(c, (const uint16_t*)c->lat[c->cur], pg, tg);
+        break;
+      default:
+        e = launch_u_prepass<LBM_STORE_F32>(c, (const float*)c->lat[c->cur], pg, tg);
+    }
+    if (e != hipSuccess) return e;
   }
-  LAUNCH_CHECK();
   const int uw = (c->flags & IBM_INNER_UNWEIGHTED) ? SW_UNWEIGHTED : 0;
   const bool feats = (c->flags & (IBM_WARM_START | IBM_KEEP_FEATURES)) != 0;
   if (feats && !c->nbr_valid) {

@@ -68,6 +68,8 @@ struct lbm_ctx {
   int32_t* nbr = nullptr;       // [max_points][16] neighbour lists (caller order)
   float4* g0_orig = nullptr;    // [max_points] first deficit (caller order)
   float4* du_prev = nullptr;    // [max_points] last forcing's du (caller order)
+  float* ubox = nullptr;        // [LBM_MAX_BODIES][6] rest-position box (lo, hi) per body
+  int ubox_sub = 0;             // 8^3 sub-blocks per axis bounding any moved box
   float* feat = nullptr;        // [max_points][12] features of the last forcing (sorted)
   float* vref = nullptr;        // [LBM_MAX_BODIES] reference speed per body
   float* theta = nullptr;       // [IBM_MLP_NPARAM] network parameters

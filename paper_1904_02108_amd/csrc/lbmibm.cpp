@@ -26,7 +26,7 @@ struct Plan {
   size_t elem, pop_stride, lat_bytes;
   // points
   size_t o_rest, o_body_of, o_key, o_rank, o_base, o_frac, o_ub, o_g, o_du, o_bodies, o_motion;
-  size_t o_nbr, o_g0, o_duprev, o_feat, o_vref, o_theta, o_packed;
+  size_t o_nbr, o_g0, o_duprev, o_feat, o_vref, o_theta, o_packed, o_ubox;
   size_t o_box, o_G;
   int64_t max_boxes;
   // tiles
@@ -152,6 +152,7 @@ void make_plan(const lbm_params* p, Plan& pl) {
   pl.o_duprev = pc.take(M * sizeof(float4));
   pl.o_feat = pc.take(M * IBM_MLP_NFEAT * sizeof(float));
   pl.o_vref = pc.take((size_t)LBM_MAX_BODIES * sizeof(float));
+  pl.o_ubox = pc.take((size_t)LBM_MAX_BODIES * 6 * sizeof(float));
   pl.o_theta = pc.take((size_t)IBM_MLP_NPARAM * sizeof(float));
   pl.o_packed = pc.take(MLP_PACKED_BYTES);
   pl.size[LBM_BUF_POINTS] = pc.at;
@@ -358,6 +359,7 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->du_prev = (float4*)(P + pl.o_duprev);
   c->feat = (float*)(P + pl.o_feat);
   c->vref = (float*)(P + pl.o_vref);
+  c->ubox = (float*)(P + pl.o_ubox);
   c->theta = (float*)(P + pl.o_theta);
   c->theta_packed = (void*)(P + pl.o_packed);
   c->boxbuf = (float*)(F + pl.o_box);
@@ -449,10 +451,12 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
     return fail(c, LBM_ERR_ARG, "n_iter must be in [1, max_iter]");
   const uint32_t known =
       IBM_INNER_UNWEIGHTED | IBM_STOP_RESIDUAL | IBM_WARM_START | IBM_KEEP_FEATURES | IBM_MLP_FP32 |
-      IBM_WARM_PREV;
+      IBM_WARM_PREV | IBM_U_BOX | IBM_U_KERNEL;
   if (flags & ~known) return fail(c, LBM_ERR_ARG, "unknown flags");
   if ((flags & IBM_WARM_START) && (flags & IBM_WARM_PREV))
     return fail(c, LBM_ERR_ARG, "IBM_WARM_START and IBM_WARM_PREV exclude each other");
+  if ((flags & IBM_U_BOX) && (flags & IBM_U_KERNEL))
+    return fail(c, LBM_ERR_ARG, "IBM_U_BOX and IBM_U_KERNEL exclude each other");
   if ((flags & IBM_WARM_START) && (flags & IBM_INNER_UNWEIGHTED))
     return fail(c, LBM_ERR_ARG, "IBM_WARM_START needs the weighted inner sweep");
   if (flags & IBM_STOP_RESIDUAL) {
@@ -469,6 +473,8 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
   std::vector<int32_t> body_of((size_t)n);
   std::vector<double> btab((size_t)nbodies * 8);
   std::vector<float> vref((size_t)nbodies);
+  std::vector<float> ubox((size_t)nbodies * 6, 0.0f);
+  double ubox_reach = 0.0;  // largest distance of a rest-box corner from its centre
   const int dims[3] = {c->p.nx, c->p.ny, c->p.nz};
   for (int b = 0; b < nbodies; ++b) {
     const ibm_body& B = bodies[b];
@@ -504,11 +510,30 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
     // speed bound |omega| max |r|, or 1 for a body at rest
     const double vr = std::fabs(B.omega) * rmax;
     vref[(size_t)b] = vr > 0.0 ? (float)vr : 1.0f;
+    // rest-position bounding box of the body's points (box U pre-pass)
+    if (body_off[b + 1] > body_off[b]) {
+      float lo[3] = {rest_xyz[3 * body_off[b]], rest_xyz[3 * body_off[b] + 1], rest_xyz[3 * body_off[b] + 2]};
+      float hi[3] = {lo[0], lo[1], lo[2]};
+      for (int64_t k = body_off[b]; k < body_off[b + 1]; ++k)
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = std::min(lo[a], rest_xyz[3 * k + a]);
+          hi[a] = std::max(hi[a], rest_xyz[3 * k + a]);
+        }
+      double reach2 = 0.0;
+      for (int a = 0; a < 3; ++a) {
+        ubox[6 * (size_t)b + a] = lo[a];
+        ubox[6 * (size_t)b + 3 + a] = hi[a];
+        const double m = std::max(std::fabs((double)lo[a]), std::fabs((double)hi[a]));
+        reach2 += m * m;
+      }
+      ubox_reach = std::max(ubox_reach, std::sqrt(reach2));
+    }
   }
   HIP_TRY(c, hipMemcpyAsync(c->rest, rest.data(), rest.size() * sizeof(float4), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->body_of, body_of.data(), body_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->bodies, btab.data(), btab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->vref, vref.data(), vref.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->ubox, ubox.data(), ubox.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->npts = n;
   c->nbodies = nbodies;
@@ -517,6 +542,10 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
   c->eps = (flags & IBM_STOP_RESIDUAL) ? eps : 0.0f;
   c->nbr_valid = false;
   c->du_prev_valid = false;
+  // a moved box lies in the cube of half-edge reach around the centre; the
+  // pre-pass widens it to floor(lo) - 2 .. floor(hi) + 3, at most 2 reach + 7
+  // cells per axis (one more for rounding)
+  c->ubox_sub = (int)std::ceil((2.0 * ubox_reach + 8.0) / lbmd::TILE);
   c->meta_pending = false;  // the stream has been synchronised above
   c->prev_len_valid = false;
   c->g_valid_step = -1;

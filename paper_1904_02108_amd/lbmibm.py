@@ -31,7 +31,7 @@ LBM_FORCE_GUO, LBM_FORCE_SHIFT = 0, 1
 LBM_NBUF = 5
 IBM_INNER_UNWEIGHTED, IBM_STOP_RESIDUAL, IBM_WARM_START, IBM_KEEP_FEATURES, IBM_MLP_FP32 = (
     1, 2, 4, 8, 16)
-IBM_WARM_PREV = 32
+IBM_WARM_PREV, IBM_U_BOX, IBM_U_KERNEL = 32, 64, 128
 MLP_FP32, MLP_BF16 = 0, 1
 IBM_MLP_NPARAM, IBM_MLP_NFEAT, IBM_MLP_NNBR = 9347, 12, 16
 LBM_MAX_ITER = 64

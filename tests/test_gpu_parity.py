@@ -166,6 +166,40 @@ def test_forcing_on_random_flow(L, lat, name):
     _check_forcing(sim, p, pts, wl, 7, U0)
 
 
+U_STRATEGIES = {"tile-mask": 0, "box": 64, "kernel": 128}
+
+
+@pytest.mark.parametrize("name", ["tiny-periodic", "tiny-walls"])
+@pytest.mark.parametrize("strategy", list(U_STRATEGIES))
+def test_u_prepass_strategy_on_random_flow(L, lat, name, strategy):
+    """Each U pre-pass strategy (§5: box, kernel, and the default tile mask)
+    against the oracle on a random flow at step 7."""
+    wl = FORCE_CASES[name]()
+    sim, p, _ = sim_for_workload(L, wl, flags=U_STRATEGIES[strategy])
+    pts = O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter, 0)
+    f0 = _rand_pops(wl.shape, 33, lat, amp=0.03)
+    sim.write(pops=f0, step=7)
+    _, U0 = O.moments(p, f0)
+    _check_forcing(sim, p, pts, wl, 7, U0)
+
+
+@pytest.mark.parametrize("name,steps", [("c0", 4), ("paper18", 2)])
+def test_u_prepass_strategies_identical(L, name, steps):
+    """The three U pre-pass strategies compute the same U wherever it is
+    read, with the same arithmetic: force, corrections and the flow after a
+    few steps are bit-identical."""
+    wl = W.config(name)
+    out = {}
+    for strategy, flags in U_STRATEGIES.items():
+        sim, _, _ = sim_for_workload(L, wl, flags=flags)
+        sim.step(steps)
+        out[strategy] = {k: to_np(v) for k, v in sim.read("force", "pt_du", "vel").items()}
+        sim.close()
+    for strategy in ("box", "kernel"):
+        for k in ("force", "pt_du", "vel"):
+            assert np.array_equal(out[strategy][k], out["tile-mask"][k]), (strategy, k)
+
+
 def test_special_positions(L, lat):
     """Non-rotating points at integer and half-integer coordinates and on the
     periodic seams, on a box smaller than one tile along y."""
@@ -305,6 +339,10 @@ def test_error_paths(L):
     assert ei.value.status == L.LBM_ERR_ARG
     with pytest.raises(L.LbmError) as ei:
         sim.set_points(np.zeros((2, 3), np.float32), np.ones(2), [0, 3], bodies)
+    assert ei.value.status == L.LBM_ERR_ARG
+    with pytest.raises(L.LbmError) as ei:      # two U pre-pass strategies at once
+        sim.set_points(np.zeros((2, 3), np.float32), np.ones(2), [0, 2], bodies, 5,
+                       L.IBM_U_BOX | L.IBM_U_KERNEL)
     assert ei.value.status == L.LBM_ERR_ARG
     sim.set_points(np.zeros((2, 3), np.float32), np.ones(2), [0, 2], bodies)
     with pytest.raises(L.LbmError) as ei:
