@@ -317,6 +317,51 @@ def u_strategy_leg(torch, L, W, cases=(("paper1", 10), ("paper6", 10), ("paper18
     return {"steps": {n: k for n, k in cases}, "warmup": warmup, "by_workload": out}
 
 
+def forcing_schemes_leg(torch, L, taus=(0.6, 0.9, 1.2), steps=40000):
+    """Velocity-shift (§2 step 3) against Guo forcing on flows with closed
+    forms, run to a steady state on the GPU: a channel driven by g = 1e-5
+    between halfway bounce-back walls (4 x 16 x 4; relative L-inf error of
+    U + G/2 against the no-slip parabola, which includes the walls' own
+    error), and a pressure-balanced force G_x = 1e-4 sin(2 pi x / 32)
+    (32 x 4 x 4; the physical velocity U + G/2 should vanish, and ln rho
+    should follow 3 int G dx)."""
+    import numpy as np
+    out = {"steps": steps, "channel": {}, "pressure_balanced": {}}
+    for tau in taus:
+        nu = (tau - 0.5) / 3
+        row_c, row_p = {}, {}
+        for sname, fc in (("guo", L.LBM_FORCE_GUO), ("shift", L.LBM_FORCE_SHIFT)):
+            g = 1e-5
+            sim = L.Simulation((4, 16, 4), tau, bc=(0, 1, 0), forcing=fc, g_ext=(g, 0.0, 0.0),
+                               device="cuda:0")
+            sim.step(steps)
+            u = sim.read("vel")["vel"].cpu().numpy()[0].mean(axis=(0, 2)) + g / 2
+            sim.close()
+            y = np.arange(16)
+            ref = g / (2 * nu) * (y + 0.5) * (16 - 0.5 - y)
+            row_c[sname] = float(np.abs(u - ref).max() / ref.max())
+            g = 1e-4
+            x = np.arange(32)
+            G = np.zeros((3, 4, 4, 32), np.float32)
+            G[0] = (g * np.sin(2 * np.pi * x / 32))[None, None, :]
+            sim = L.Simulation((32, 4, 4), tau, forcing=fc, device="cuda:0")
+            sim.write(force=G)
+            sim.step(steps // 4)
+            o = sim.read("rho", "vel")
+            rho = o["rho"].cpu().numpy().astype(np.float64)
+            vel = o["vel"].cpu().numpy().astype(np.float64)
+            sim.close()
+            lr = np.log(rho[0, 0, :])
+            ref = -3 * g * 32 / (2 * np.pi) * np.cos(2 * np.pi * x / 32)
+            row_p[sname] = {
+                "max_u_phys_over_g": float(np.abs(vel + G.astype(np.float64) / 2).max() / g),
+                "ln_rho_rel_err": float(np.abs((lr - lr.mean()) - (ref - ref.mean())).max() /
+                                        np.abs(ref).max())}
+        out["channel"]["tau_%g" % tau] = row_c
+        out["pressure_balanced"]["tau_%g" % tau] = row_p
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,6 +378,8 @@ def main():
                     help="skip the 160x160x320 runs with 1-6 and 18 propellers")
     ap.add_argument("--no-u-strategy", action="store_true",
                     help="skip the box / kernel / tile-mask U pre-pass comparison")
+    ap.add_argument("--no-forcing-schemes", action="store_true",
+                    help="skip the velocity-shift vs Guo comparison on closed-form flows")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm-start comparison on the single-propeller case")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -426,6 +473,8 @@ def main():
         out["paper_family"] = paper_family_leg(torch, L, W)
     if not args.no_u_strategy:
         out["u_strategy"] = u_strategy_leg(torch, L, W)
+    if not args.no_forcing_schemes:
+        out["forcing_schemes"] = forcing_schemes_leg(torch, L)
     if not args.no_learned:
         out["learned"] = {}
         for name, n_steps in (("c1", 150), ("c1_dense", 60)):

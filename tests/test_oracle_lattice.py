@@ -195,6 +195,52 @@ def test_poiseuille_guo():
     assert np.abs(u - ref).max() / ref.max() < 0.05
 
 
+def test_poiseuille_shift_and_guo():
+    """The same channel with the velocity-shift forcing (§2 step 3): the
+    steady U + G/2 has the same bulk second difference -g/nu for both schemes
+    (a uniform force in a unidirectional steady flow leaves no trace of the
+    scheme), so the two steady profiles agree; only the halfway bounce-back
+    walls make them differ from the parabola."""
+    ny, gx = 16, 1e-6
+    for tau in (0.7, 1.2):
+        nu = (tau - 0.5) / 3
+        prof = {}
+        for fc in (O.FORCE_GUO, O.FORCE_SHIFT):
+            p = O.params((1, ny, 1), tau, bc=(0, 1, 0), forcing=fc, g_ext=(gx, 0, 0))
+            f = O.init_equilibrium(p)
+            u = _steady(p, f, 80000, 1e-16)[0, 0, :, 0] + gx / 2
+            d2 = u[2:] - 2 * u[1:-1] + u[:-2]
+            np.testing.assert_allclose(d2, -gx / nu, rtol=1e-5)
+            prof[fc] = u
+        np.testing.assert_allclose(prof[O.FORCE_SHIFT], prof[O.FORCE_GUO], rtol=1e-6)
+
+
+@pytest.mark.parametrize("forcing", [0, 1])
+def test_pressure_balanced_force(forcing):
+    """A periodic force G_x = g sin(2 pi x / N) that a pressure gradient can
+    balance: for both schemes the steady physical velocity U + G/2
+    vanishes, and ln rho follows 3 int G dx (c_s^2 = 1/3) up to the
+    lattice's second-order discretization error, O(k^2) for the mode
+    k = 2 pi / N (3.2e-3, about k^2 / 12, at N = 32; bounded here by k^2/6
+    and required to be present, so that a scheme reproducing the continuum
+    profile exactly would be noticed)."""
+    N, g, tau = 32, 1e-4, 0.8
+    p = O.params((N, 1, 1), tau, forcing=forcing)
+    x = np.arange(N)
+    G = np.zeros((3, 1, 1, N))
+    G[0, 0, 0, :] = g * np.sin(2 * np.pi * x / N)
+    f = O.init_equilibrium(p)
+    for _ in range(12000):
+        f = O.collide_stream(p, f, G)
+    rho, U = O.moments(p, f)
+    u = U[0, 0, 0, :] + G[0, 0, 0, :] / 2
+    assert np.abs(u).max() < 1e-8 * g
+    lr = np.log(rho[0, 0, :])
+    ref = -3 * g * N / (2 * np.pi) * np.cos(2 * np.pi * x / N)
+    err = np.abs((lr - lr.mean()) - (ref - ref.mean())).max() / np.abs(ref).max()
+    assert 1e-3 < err < 6.4e-3
+
+
 def test_couette_linear():
     """Moving top wall, resting bottom wall: the steady profile is exactly
     linear, u(y) = U_w (y + 1/2) / N (halfway bounce-back with Ladd's term)."""
