@@ -367,7 +367,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2_dense", choices=["c0", "c1", "c1_dense", "c2", "c2_dense"])
+    ap.add_argument("--workload", default="c2_dense",
+                    choices=["c0", "c1", "c1_dense", "c2", "c2_dense"] +
+                            ["paper%d" % k for k in (1, 2, 3, 4, 5, 6, 18)])
+    ap.add_argument("--u-prepass", default="tile", choices=["tile", "box", "kernel"],
+                    help="U pre-pass strategy of the main run (section 5)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--forcing", default="guo", choices=["guo", "shift"])
     ap.add_argument("--cpu-steps", type=int, default=1)
@@ -401,7 +405,8 @@ def main():
     torch.cuda.set_device(0)
     sim = L.Simulation(wl.shape, wl.tau, bc=wl.bc, storage=storage, forcing=forcing,
                        max_points=wl.n_points, max_iter=wl.n_iter, device="cuda:0")
-    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter)
+    uflags = {"tile": 0, "box": L.IBM_U_BOX, "kernel": L.IBM_U_KERNEL}[args.u_prepass]
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter, uflags)
     stream = torch.cuda.current_stream()
 
     sim.step(args.warmup)
@@ -443,7 +448,7 @@ def main():
         "config": {"workload": wl.name, "grid": list(wl.shape), "bc": list(wl.bc), "tau": wl.tau,
                    "n_points": wl.n_points, "n_bodies": int(len(wl.bodies)), "h": wl.h,
                    "sweeps": wl.n_iter, "forcing": args.forcing, "storage": args.storage,
-                   "parallelism": "single GPU"},
+                   "u_prepass": args.u_prepass, "parallelism": "single GPU"},
         "point_updates_per_s": round(wl.n_points * K / (ms * 1e-3), 1),
         "hbm_frac_full_step": round(mlups * 1e6 * bpc / (HBM_PEAK_GBS * 1e9), 4),
         "ms_fluid": round(fluid_ms, 4),
