@@ -284,7 +284,7 @@ def paper_family_leg(torch, L, W, steps=20, warmup=5):
 
 def u_strategy_leg(torch, L, W, cases=(("paper1", 10), ("paper6", 10), ("paper18", 10),
                                         ("c2_dense", 5)), warmup=3):
-    """§5's U pre-pass strategies (SURVEY ablation): the box strategy (U on
+    """§5's U pre-pass strategies compared: the box strategy (U on
     each body's moved bounding box), the kernel strategy (U on every
     point's support cells, shared cells recomputed) and the default tile mask
     (U on the 4^3 blocks some support reaches), same results, timed on the
@@ -390,7 +390,7 @@ def main():
                     help="also time a plain streaming kernel (read + write of half the lattice bytes each)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU; this build has no multi-GPU path "
+        print("bench.py measures one GPU; the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
