@@ -104,8 +104,8 @@ def copy_bandwidth(torch, nbytes, reps=5):
 
 def learned_leg(torch, L, W, name="c1", n_pairs_steps=150, epochs=10, eval_steps=40, warm=5):
     """C4: the warm-start network trained on the GPU from plain runs of the
-    single-propeller geometry with other seeds (1-8), then the canonical
-    single-propeller case (seed 0, held out) run four ways: plain with a
+    workload's geometry with other seeds (1-8: other axes, phases and
+    rates), then the canonical case (seed 0, held out) run four ways: plain with a
     fixed 5 sweeps, plain to the residual threshold, warm-started from the
     previous step's correction (the non-learned baseline) and warm-started
     by the network, both to the same threshold.  The threshold is the median
@@ -482,7 +482,7 @@ def main():
         out["forcing_schemes"] = forcing_schemes_leg(torch, L)
     if not args.no_learned:
         out["learned"] = {}
-        for name, n_steps in (("c1", 150), ("c1_dense", 60)):
+        for name, n_steps in (("c1", 150), ("c1_dense", 60), ("paper18", 20)):
             out["learned"][name] = learned_leg(torch, L, W, name, n_pairs_steps=n_steps)
             torch.cuda.empty_cache()
     if args.copy_calibration:

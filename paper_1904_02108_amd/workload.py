@@ -185,14 +185,14 @@ def config(name, h=None, seed=0, forcing=FORCE_GUO):
         return Workload(name, (256, 256, 256), 0.55, (0, 0, 0), forcing, rest, area, off, bodies,
                         5, 500, hh, {"seed": seed})
     if name.startswith("paper") and name[5:].isdigit():
-        return paper_family(int(name[5:]), forcing=forcing)
+        return paper_family(int(name[5:]), forcing=forcing, seed=seed)
     raise KeyError(name)
 
 
 PAPER_FAMILY_COUNTS = (1, 2, 3, 4, 5, 6, 18)
 
 
-def paper_family(n_props, forcing=FORCE_GUO):
+def paper_family(n_props, forcing=FORCE_GUO, seed=0):
     """The test-case family of §6: a 160 x 160 x 320 lattice with 1 to 6 or 18
     rotating propellers of 3930 points each (18 give 70 740 points), the
     area of a point about one cell face (h = 1).
@@ -204,7 +204,9 @@ def paper_family(n_props, forcing=FORCE_GUO):
     0.136).  Up to 6 propellers sit on the axis x = y = 80, evenly spaced in
     z; 18 form three such columns of 6 at radius 40 around it (columns 69
     cells apart, so the swept discs of neighbouring columns do not meet).
-    Phases theta0 are spread deterministically."""
+    Phases theta0 are spread deterministically.  seed > 0 (training data of
+    the learned warm start): theta0 ~ U[0, 2 pi) and omega = +-U[0.003,
+    0.005] per propeller, axes unchanged."""
     if n_props not in PAPER_FAMILY_COUNTS:
         raise KeyError("paper%d" % n_props)
     pts, ar = propeller_surface(12.0, 24.0, 22.0, 17.0, 1.0)
@@ -213,14 +215,18 @@ def paper_family(n_props, forcing=FORCE_GUO):
         for c in range(3)]
     per = n_props if n_props <= 6 else 6
     props = []
+    rng = _rng(seed) if seed else None
     for c, (cx, cy) in enumerate(cols):
         for j in range(per):
             cz = 320.0 * (j + 0.5) / per
-            th0 = 0.7 * j + 2.1 * c
-            props.append((pts, ar, (cx, cy, cz), (0.0, 0.0, 1.0), th0, 0.004))
+            th0, om = 0.7 * j + 2.1 * c, 0.004
+            if rng is not None:
+                th0 = rng.uniform(0.0, 2.0 * math.pi)
+                om = rng.uniform(0.003, 0.005) * (1.0 if rng.uniform() < 0.5 else -1.0)
+            props.append((pts, ar, (cx, cy, cz), (0.0, 0.0, 1.0), th0, om))
     rest, area, off, bodies = _assemble(props)
     return Workload("paper%d" % n_props, (160, 160, 320), 0.6, (0, 0, 0), forcing, rest, area,
-                    off, bodies, 5, 1000, 1.0, {"propellers": n_props})
+                    off, bodies, 5, 1000, 1.0, {"propellers": n_props, "seed": seed})
 
 
 def tiny_propeller_case(shape=(24, 20, 28), bc=(0, 0, 0), h=1.0, omega=0.02, theta0=0.3,
