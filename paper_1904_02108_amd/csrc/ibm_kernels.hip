@@ -198,7 +198,9 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_point_count(
 }
 
 // Pass 2: exclusive scan of the owner counts and the compact lists of tiles
-// that own points / are touched (with each owner tile's slot in its list),
+// that own points / are touched (with each owner tile's slot in its list;
+// tiles with more points than a sweep workgroup has threads come first, so
+// that their longer sweeps start first),
 // in three launches: chunk totals, a scan of the chunk totals (which also
 // writes the list lengths, to the device and to pinned host memory for the
 // next forcing's grid sizes), and the chunk rescans that write the outputs
@@ -207,11 +209,15 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_point_count(
 // with zeros to whole chunks).
 constexpr int SCAN_WG = 256, SCAN_PER = 8, SCAN_CHUNK = SCAN_WG * SCAN_PER;
 constexpr int SCAN_WAVES = SCAN_WG / 64;
+// scanned per tile: points owned, owner tile with more than HEAVY_TILE
+// points, other owner tile, touched tile
+constexpr int SCAN_NV = 4;
+constexpr uint32_t HEAVY_TILE = WG;
 
 __device__ __forceinline__ void load_counts(const uint32_t* __restrict__ cnt_own,
                                             const uint32_t* __restrict__ cnt_touch, int64_t t0,
                                             uint32_t a[SCAN_PER], uint32_t b[SCAN_PER],
-                                            uint32_t s[3]) {
+                                            uint32_t s[SCAN_NV]) {
 #pragma unroll
   for (int j = 0; j < SCAN_PER; j += 4) {
     const uint4 va = *reinterpret_cast<const uint4*>(cnt_own + t0 + j);
@@ -219,23 +225,25 @@ __device__ __forceinline__ void load_counts(const uint32_t* __restrict__ cnt_own
     a[j] = va.x; a[j + 1] = va.y; a[j + 2] = va.z; a[j + 3] = va.w;
     b[j] = vb.x; b[j + 1] = vb.y; b[j + 2] = vb.z; b[j + 3] = vb.w;
   }
-  s[0] = s[1] = s[2] = 0u;
+  s[0] = s[1] = s[2] = s[3] = 0u;
 #pragma unroll
   for (int j = 0; j < SCAN_PER; ++j) {
     s[0] += a[j];
-    s[1] += a[j] ? 1u : 0u;
-    s[2] += b[j] ? 1u : 0u;
+    s[1] += a[j] > HEAVY_TILE ? 1u : 0u;
+    s[2] += (a[j] && a[j] <= HEAVY_TILE) ? 1u : 0u;
+    s[3] += b[j] ? 1u : 0u;
   }
 }
 
-// Workgroup-wide exclusive scan of three values per thread; tot: the sums.
+// Workgroup-wide exclusive scan of SCAN_NV values per thread; tot: the sums.
 template <int NW>
-__device__ __forceinline__ void block_scan3(const uint32_t s[3], uint32_t ex[3], uint32_t tot[3]) {
-  __shared__ uint32_t wtot[3][NW];
+__device__ __forceinline__ void block_scan(const uint32_t s[SCAN_NV], uint32_t ex[SCAN_NV],
+                                           uint32_t tot[SCAN_NV]) {
+  __shared__ uint32_t wtot[SCAN_NV][NW];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  uint32_t inc[3];
+  uint32_t inc[SCAN_NV];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < SCAN_NV; ++q) {
     uint32_t v = s[q];
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -247,7 +255,7 @@ __device__ __forceinline__ void block_scan3(const uint32_t s[3], uint32_t ex[3],
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < SCAN_NV; ++q) {
     uint32_t base = 0u, all = 0u;
     for (int w = 0; w < NW; ++w) {
       base += w < wv ? wtot[q][w] : 0u;
@@ -263,10 +271,10 @@ __global__ __launch_bounds__(SCAN_WG) void k_scan_totals(const uint32_t* __restr
                                                          const uint32_t* __restrict__ cnt_touch,
                                                          uint32_t* __restrict__ chunk) {
   const int64_t t0 = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
-  uint32_t a[SCAN_PER], b[SCAN_PER], s[3], ex[3], tot[3];
+  uint32_t a[SCAN_PER], b[SCAN_PER], s[SCAN_NV], ex[SCAN_NV], tot[SCAN_NV];
   load_counts(cnt_own, cnt_touch, t0, a, b, s);
-  block_scan3<SCAN_WAVES>(s, ex, tot);
-  if (threadIdx.x < 3) chunk[3 * blockIdx.x + threadIdx.x] = tot[threadIdx.x];
+  block_scan<SCAN_WAVES>(s, ex, tot);
+  if (threadIdx.x < SCAN_NV) chunk[SCAN_NV * blockIdx.x + threadIdx.x] = tot[threadIdx.x];
 }
 
 constexpr int SCAN2_WG = 1024;
@@ -274,29 +282,31 @@ __global__ __launch_bounds__(SCAN2_WG) void k_scan_chunks(uint32_t* __restrict__
                                                           uint32_t* __restrict__ start_own,
                                                           int64_t ntiles, uint32_t* __restrict__ meta,
                                                           uint32_t* __restrict__ meta_host) {
-  __shared__ uint32_t carry[3];
-  if (threadIdx.x < 3) carry[threadIdx.x] = 0u;
+  __shared__ uint32_t carry[SCAN_NV];
+  if (threadIdx.x < SCAN_NV) carry[threadIdx.x] = 0u;
   __syncthreads();
   for (int64_t c0 = 0; c0 < nch; c0 += SCAN2_WG) {
     const int64_t c = c0 + threadIdx.x;
-    uint32_t s[3], ex[3], tot[3];
+    uint32_t s[SCAN_NV], ex[SCAN_NV], tot[SCAN_NV];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) s[q] = c < nch ? chunk[3 * c + q] : 0u;
-    block_scan3<SCAN2_WG / 64>(s, ex, tot);
+    for (int q = 0; q < SCAN_NV; ++q) s[q] = c < nch ? chunk[SCAN_NV * c + q] : 0u;
+    block_scan<SCAN2_WG / 64>(s, ex, tot);
     if (c < nch)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) chunk[3 * c + q] = carry[q] + ex[q];
+      for (int q = 0; q < SCAN_NV; ++q) chunk[SCAN_NV * c + q] = carry[q] + ex[q];
     __syncthreads();
-    if (threadIdx.x < 3) carry[threadIdx.x] += tot[threadIdx.x];
+    if (threadIdx.x < SCAN_NV) carry[threadIdx.x] += tot[threadIdx.x];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    // meta: owner tiles, touched tiles, heavy owner tiles (listed first)
     start_own[ntiles] = carry[0];
-    meta[0] = carry[1];
-    meta[1] = carry[2];
+    meta[0] = carry[1] + carry[2];
+    meta[1] = carry[3];
+    meta[2] = carry[1];
     if (meta_host) {  // zero-copy: a plain (vector) store to pinned host memory
-      meta_host[0] = carry[1];
-      meta_host[1] = carry[2];
+      meta_host[0] = carry[1] + carry[2];
+      meta_host[1] = carry[3];
     }
   }
 }
@@ -305,22 +315,26 @@ __global__ __launch_bounds__(SCAN_WG) void k_scan_write(
     uint32_t* __restrict__ cnt_own, uint32_t* __restrict__ cnt_touch,
     const uint32_t* __restrict__ chunk, int64_t ntiles, uint32_t* __restrict__ start_own,
     int32_t* __restrict__ own_slot, uint32_t* __restrict__ own_tiles,
-    uint32_t* __restrict__ touch_tiles, uint32_t* __restrict__ bflag_words, int64_t nbflag_words) {
+    uint32_t* __restrict__ touch_tiles, uint32_t* __restrict__ bflag_words, int64_t nbflag_words,
+    const uint32_t* __restrict__ meta) {
   const int64_t t0 = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
-  uint32_t a[SCAN_PER], b[SCAN_PER], s[3], ex[3], tot[3];
+  uint32_t a[SCAN_PER], b[SCAN_PER], s[SCAN_NV], ex[SCAN_NV], tot[SCAN_NV];
   load_counts(cnt_own, cnt_touch, t0, a, b, s);
-  block_scan3<SCAN_WAVES>(s, ex, tot);
-  uint32_t run[3];
+  block_scan<SCAN_WAVES>(s, ex, tot);
+  uint32_t run[SCAN_NV];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) run[q] = chunk[3 * blockIdx.x + q] + ex[q];
+  for (int q = 0; q < SCAN_NV; ++q) run[q] = chunk[SCAN_NV * blockIdx.x + q] + ex[q];
+  run[2] += meta[2];  // the other owner tiles follow the heavy ones
 #pragma unroll
   for (int j = 0; j < SCAN_PER; ++j) {
     const int64_t t = t0 + j;
     if (t < ntiles) {
       start_own[t] = run[0];
-      own_slot[t] = a[j] ? (int32_t)run[1] : -1;
-      if (a[j]) own_tiles[run[1]++] = (uint32_t)t;
-      if (b[j]) touch_tiles[run[2]++] = (uint32_t)t;
+      int32_t slot = -1;
+      if (a[j]) slot = (int32_t)(a[j] > HEAVY_TILE ? run[1]++ : run[2]++);
+      own_slot[t] = slot;
+      if (slot >= 0) own_tiles[slot] = (uint32_t)t;
+      if (b[j]) touch_tiles[run[3]++] = (uint32_t)t;
       run[0] += a[j];
     }
   }
@@ -411,6 +425,51 @@ __device__ __forceinline__ ListRange list_range(uint32_t n) {
   r.end = min(n, (xcd + 1u) * chunk);
   r.step = gridDim.x >> 3;
   return r;
+}
+
+// Owner-tile entries of a sweep workgroup: the nh heavy tiles at the front
+// of the list go one per workgroup to the first workgroups of the launch
+// (dispatched first, spread over the XCDs); the others to the remaining
+// workgroups as in list_range.  A grid too small for that interleaves every
+// entry over all workgroups.
+struct OwnOrder {
+  uint32_t h, h_end, h_step;
+  ListRange l;
+  __device__ __forceinline__ bool next(uint32_t& e) {
+    if (h < h_end) {
+      e = h;
+      h += h_step;
+      return true;
+    }
+    if (l.e < l.end) {
+      e = l.e;
+      l.e += l.step;
+      return true;
+    }
+    return false;
+  }
+};
+__device__ __forceinline__ OwnOrder own_order(uint32_t n, uint32_t nh) {
+  OwnOrder o;
+  const uint32_t G = gridDim.x, b = blockIdx.x;
+  const uint32_t H = (nh + 7u) / 8u * 8u;
+  o.l.e = o.l.end = o.l.step = 0u;
+  if (G < H + 8u) {
+    o.h = b;
+    o.h_end = n;
+    o.h_step = G;
+    return o;
+  }
+  o.h = b;
+  o.h_end = nh;
+  o.h_step = G;
+  if (b >= H) {
+    const uint32_t m = n - nh, chunk = (m + 7u) / 8u, xcd = (b - H) & 7u;
+    o.l.e = nh + xcd * chunk + ((b - H) >> 3);
+    o.l.end = nh + min(m, (xcd + 1u) * chunk);
+    o.l.step = (G - H) >> 3;
+  }
+  return o;
 }
 
 __device__ __forceinline__ void tile_origin(const PointGeom& pg, uint32_t t, int o[3]) {
@@ -633,8 +692,9 @@ __global__ __launch_bounds__(WG, 7) void k_sweep_tiles(
   const bool load_prev = spread_du && (mode & SW_LOAD_PREV);
   const bool save_du = spread_du && (mode & SW_SAVE_DU);
   double res = 0.0;  // this thread's part of sum s |g|^2 over the workgroup's tiles
-  const ListRange lr = list_range(meta[0]);
-  for (uint32_t e = lr.e; e < lr.end; e += lr.step) {
+  OwnOrder order = own_order(meta[0], meta[2]);
+  uint32_t e;
+  while (order.next(e)) {
     const uint32_t t = own_tiles[e];
     int o[3];
     tile_origin(pg, t, o);
@@ -1152,7 +1212,7 @@ hipError_t launch_forcing(lbm_ctx* c) {
     k_scan_write<<<(unsigned)nch, SCAN_WG, 0, st>>>(c->cnt_own, c->cnt_touch, c->chunk_tot,
                                                     c->ntiles, c->start_own, c->own_slot,
                                                     c->own_tiles, c->touch_tiles,
-                                                    (uint32_t*)c->bflag, c->nbflag_words);
+                                                    (uint32_t*)c->bflag, c->nbflag_words, c->meta);
     LAUNCH_CHECK();
   }
   k_point_scatter<<<nb, LBM_BLOCK, 0, st>>>(c->rest, c->body_of, c->motion, n, pg, c->key, c->rank,

@@ -168,7 +168,7 @@ void make_plan(const lbm_params* p, Plan& pl) {
   pl.o_touch_tiles = tc.take(NT * 4);
   pl.o_meta = tc.take(4 * 4);
   pl.o_bflag = tc.take((size_t)pl.nbflag_words * 4);
-  pl.o_chunk = tc.take((NTpad / 2048) * 3 * 4);  // totals of the 2048-tile scan chunks
+  pl.o_chunk = tc.take((NTpad / 2048) * 4 * 4);  // totals of the 2048-tile scan chunks
   pl.size[LBM_BUF_TILES] = tc.at;
 
   {  // blocks of the stream-collide launch (see stream_collide_shape)

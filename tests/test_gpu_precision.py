@@ -29,20 +29,29 @@ def L():
 
 @pytest.mark.parametrize("storage", [1, 2])
 @pytest.mark.parametrize("bc", [(0, 0, 0), (0, 1, 1)])
-def test_one_step_16bit(L, storage, bc):
-    shape = (14, 11, 9)
+@pytest.mark.parametrize("shape,forcing", [((14, 11, 9), 0), ((128, 11, 9), 0),
+                                           ((256, 6, 5), 1)])
+def test_one_step_16bit(L, storage, bc, shape, forcing):
+    """One step from the state the GPU holds, on a box with ragged blocks and
+    on rows of whole 128- and 256-cell blocks (the last with the velocity
+    shift).  The step's FP64 sums are those of the state it started from."""
     _, w, _ = O.d3q19()
-    sim = make_sim(L, shape, 0.7, bc=bc, storage=storage)
+    sim = make_sim(L, shape, 0.7, bc=bc, storage=storage, forcing=forcing)
     f0 = W.random_populations(shape, 71, amp=0.05, weights=w)
     G = W.random_field(shape, 72, amp=1e-3)
     sim.write(pops=f0, force=G)
     held = to_np(sim.read("pops", pops_f64=True)["pops"])      # rounded state
     assert rel_linf(held - w.reshape(19, 1, 1, 1), f0 - w.reshape(19, 1, 1, 1)) < EPS16[storage]
     sim.step(1)
-    out = to_np(sim.read("pops", pops_f64=True)["pops"])
-    ref = O.collide_stream(oracle_params(shape, 0.7, bc=bc), held, G)
+    got = sim.read("pops", "sums", pops_f64=True)
+    out = to_np(got["pops"])
+    p = oracle_params(shape, 0.7, bc=bc, forcing=forcing)
+    ref = O.collide_stream(p, held, G)
     off = w.reshape(19, 1, 1, 1)
     assert rel_linf(out - off, ref - off) < 2 * EPS16[storage]
+    s, s_ref = to_np(got["sums"]), O.sums(p, held)
+    assert abs(s[0] - s_ref[0]) < 1e-9 * s_ref[0]
+    assert np.abs(s[1:] - s_ref[1:]).max() < 1e-6
 
 
 @pytest.mark.parametrize("storage,tol_vel", [(1, 5e-3), (2, 5e-2)])
