@@ -1153,9 +1153,6 @@ int64_t tile_grid(const lbm_ctx* c, int list) {
 
 int64_t forcing_list_grid(const lbm_ctx* c) { return c->own_grid; }
 
-// The forcing of one time step: motion, binning, U near the surface,
-// n_iter sweeps of interpolation + correction with n_iter - 1 intermediate
-// spreads into U and the final spread of du into G.
 // The U pre-pass of the strategy the surface was set with.
 template <int S>
 hipError_t launch_u_prepass(lbm_ctx* c, const typename Store<S>::T* lat, const PointGeom& pg,
@@ -1179,6 +1176,9 @@ hipError_t launch_u_prepass(lbm_ctx* c, const typename Store<S>::T* lat, const P
   return hipGetLastError();
 }
 
+// The forcing of one time step: motion, binning, U near the surface,
+// n_iter sweeps of interpolation + correction with n_iter - 1 intermediate
+// spreads into U and the final spread of du into G.
 hipError_t launch_forcing(lbm_ctx* c) {
   const PointGeom pg = point_geom(c);
   const int64_t n = c->npts;
