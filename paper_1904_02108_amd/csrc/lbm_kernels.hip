@@ -26,18 +26,26 @@ __device__ __forceinline__ void cell_xyz(const LatticeGeom& g, int64_t cell, int
 #ifndef LBM_SC_ROWS
 #define LBM_SC_ROWS 1
 #endif
-template <int S, int FORCING>
+template <int S, int FORCING, bool FLAT>
 __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
     const typename Store<S>::T* __restrict__ src, typename Store<S>::T* __restrict__ dst,
     const LatticeGeom g, const float* __restrict__ G, const uint8_t* __restrict__ flags,
     double* __restrict__ partials) {
   // 3-D launch: blockDim.x spans x, blockDim.y spans y, one z-plane per block
-  // row; each workgroup takes LBM_SC_ROWS consecutive block rows along y
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  // row; each workgroup takes LBM_SC_ROWS consecutive block rows along y.
+  // FLAT (x extents that are not a multiple of the wavefront): 256 threads
+  // over consecutive cells of an x-y plane, so that no lane idles at the
+  // end of a row.
+  int xf = blockIdx.x * blockDim.x + threadIdx.x, yf = 0;
+  if (FLAT) {
+    yf = xf / g.nx;
+    xf -= yf * g.nx;
+  }
+  const int x = xf;
   const int z = blockIdx.z;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   for (int r = 0; r < LBM_SC_ROWS; ++r) {
-  const int y = (blockIdx.y * LBM_SC_ROWS + r) * blockDim.y + threadIdx.y;
+  const int y = FLAT ? yf : (blockIdx.y * LBM_SC_ROWS + r) * blockDim.y + threadIdx.y;
   if (x < g.nx && y < g.ny) {
     const uint32_t cell = (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
     float f[Q];
@@ -249,8 +257,17 @@ int64_t cell_blocks(const lbm_ctx* c) { return (c->ncell + LBM_BLOCK - 1) / LBM_
 }  // namespace
 
 // Launch shape of the stream-collide: 256 threads, blockDim.x = the x extent
-// rounded to a wavefront (at most 256), the rest of the block along y.
+// rounded to a wavefront (at most 256), the rest of the block along y; for an
+// x extent that is not a multiple of the wavefront, 256 consecutive cells of
+// an x-y plane (this grid never has more blocks than the other one).
+static bool stream_collide_flat(const lbm_ctx* c) { return c->p.nx % 64 != 0; }
+
 void stream_collide_shape(const lbm_ctx* c, dim3& grid, dim3& block) {
+  if (stream_collide_flat(c)) {
+    block = dim3(LBM_BLOCK, 1, 1);
+    grid = dim3((unsigned)(((int64_t)c->p.nx * c->p.ny + LBM_BLOCK - 1) / LBM_BLOCK), 1, c->p.nz);
+    return;
+  }
   int bx = ((c->p.nx + 63) / 64) * 64;
   if (bx > LBM_BLOCK) bx = LBM_BLOCK;
   const int by = LBM_BLOCK / bx;
@@ -268,12 +285,22 @@ hipError_t stream_collide_s(lbm_ctx* c) {
   T* dst = (T*)c->lat[c->cur ^ 1];
   dim3 grid, block;
   stream_collide_shape(c, grid, block);
-  if (c->p.forcing == LBM_FORCE_SHIFT)
-    k_stream_collide<S, LBM_FORCE_SHIFT><<<grid, block, 0, c->stream>>>(
-        src, dst, c->geom, c->G, c->bflag, c->sum_partials);
-  else
-    k_stream_collide<S, LBM_FORCE_GUO><<<grid, block, 0, c->stream>>>(
-        src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+  const bool flat = stream_collide_flat(c);
+  if (c->p.forcing == LBM_FORCE_SHIFT) {
+    if (flat)
+      k_stream_collide<S, LBM_FORCE_SHIFT, true><<<grid, block, 0, c->stream>>>(
+          src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+    else
+      k_stream_collide<S, LBM_FORCE_SHIFT, false><<<grid, block, 0, c->stream>>>(
+          src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+  } else {
+    if (flat)
+      k_stream_collide<S, LBM_FORCE_GUO, true><<<grid, block, 0, c->stream>>>(
+          src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+    else
+      k_stream_collide<S, LBM_FORCE_GUO, false><<<grid, block, 0, c->stream>>>(
+          src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+  }
   return hipGetLastError();
 }
 
