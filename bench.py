@@ -365,8 +365,11 @@ def forcing_schemes_leg(torch, L, taus=(0.6, 0.9, 1.2), steps=40000):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    # the dense 64-propeller flow (tip speeds up to Mach 0.72 at tau 0.55, as
+    # configured) stops being finite near step 60: 5 + 30 steps keep the
+    # timed window, whose work does not depend on the values, on a finite flow
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2_dense",
                     choices=["c0", "c1", "c1_dense", "c2", "c2_dense"] +
                             ["paper%d" % k for k in (1, 2, 3, 4, 5, 6, 18)])
