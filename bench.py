@@ -406,7 +406,7 @@ def main():
                     help="U pre-pass strategy of the main run (section 5)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--forcing", default="guo", choices=["guo", "shift"])
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-half-rate", action="store_true",
                     help="skip the run of the dense case with halved rotation rates")
