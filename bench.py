@@ -60,13 +60,20 @@ def cpu_baseline(wl, n_steps):
     import numpy as np  # noqa: F401
 
     import oracle as O
-    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    threads = O.set_threads(int(os.environ.get("OMP_NUM_THREADS", 0)) or
+                            len(os.sched_getaffinity(0)))
     p = O.params(wl.shape, wl.tau, bc=wl.bc, forcing=wl.forcing)
     pts = O.Points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter)
     f = O.init_equilibrium(p)
     t0 = time.perf_counter()
     O.run(p, f, pts, 0, n_steps)
     dt = time.perf_counter() - t0
+    # one more step on one thread (the next step of the same run)
+    O.set_threads(1)
+    t1 = time.perf_counter()
+    O.run(p, f, pts, n_steps, 1)
+    dt1 = time.perf_counter() - t1
+    O.set_threads(threads)
     cpu = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -79,7 +86,10 @@ def cpu_baseline(wl, n_steps):
     return {"value": round(wl.n_cells * n_steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": "%d step(s) of the same workload from rest (FP64, OpenMP), %.1f s wall, %s"
-                      % (n_steps, dt, cpu)}
+                      % (n_steps, dt, cpu),
+            "single_thread": {"value": round(wl.n_cells / dt1 / 1e6, 3), "unit": "MLUPS",
+                              "sample": "step %d of the same run on 1 thread, %.1f s wall"
+                                        % (n_steps, dt1)}}
 
 
 def copy_bandwidth(torch, nbytes, reps=5):
@@ -406,7 +416,7 @@ def main():
                     help="U pre-pass strategy of the main run (section 5)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--forcing", default="guo", choices=["guo", "shift"])
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-half-rate", action="store_true",
                     help="skip the run of the dense case with halved rotation rates")
@@ -487,6 +497,8 @@ def main():
                    "sweeps": wl.n_iter, "forcing": args.forcing, "storage": args.storage,
                    "u_prepass": args.u_prepass, "parallelism": "single GPU"},
         "point_updates_per_s": round(wl.n_points * K / (ms * 1e-3), 1),
+        # point updates per sweep over the forcing's own time
+        "point_sweep_updates_per_s_forcing": round(wl.n_points * wl.n_iter / (forcing_ms * 1e-3), 1),
         "hbm_frac_full_step": round(mlups * 1e6 * bpc / (HBM_PEAK_GBS * 1e9), 4),
         "ms_fluid": round(fluid_ms, 4),
         # forcing kernels after the binning (the next step's binning runs on a

@@ -36,6 +36,22 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Number of OpenMP threads of the oracle's parallel loops (timing only: the
+ * results do not depend on it beyond the order of FP64 atomic additions in
+ * the spread).  Returns the number in effect. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 #define Q 19
 

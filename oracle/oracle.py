@@ -106,6 +106,8 @@ def _load():
             lib.orc_mlp_loss_grad.argtypes = [vp, i64, vp, vp, vp]
             lib.orc_mlp_loss_grad.restype = d
             lib.orc_adam_step.argtypes = [vp, vp, vp, vp, i64, d, d, d, d]
+            lib.orc_set_threads.argtypes = [ct.c_int]
+            lib.orc_set_threads.restype = ct.c_int
             _lib = lib
     return _lib
 
@@ -399,6 +401,11 @@ def run(p, f, pts=None, step0=0, n_steps=1, sweeps=False):
 
 
 # ------------------------------------------------------------ learned warm start
+def set_threads(n=0):
+    """Set the oracle's OpenMP thread count (n > 0); returns the count in effect."""
+    return int(_load().orc_set_threads(int(n)))
+
+
 def mlp_nparam():
     return int(_load().orc_mlp_nparam())
 
