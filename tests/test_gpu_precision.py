@@ -111,3 +111,40 @@ def test_c1_100_steps_by_storage(L, c1_oracle_100, storage, tol):
     print("c1 storage", storage, e, "mass drift", drift, flush=True)
     assert e["vel"] < tol and e["du"] < tol and e["force"] < tol
     assert drift < 1e-5
+
+
+GOLDEN_500 = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden",
+                                        "c1_500_steps.npz")
+
+
+# bounds about three times the measured errors (velocity, force, du):
+# FP32 2.4e-5, 6.0e-6, 1.5e-6; FP16 5.7e-3, 4.9e-4, 4.7e-4; BF16 0.16, 5.5e-3,
+# 5.6e-3.  The wake of C1 (Re about 800) amplifies any perturbation of the
+# flow; BF16's 8-bit significand, rounded once per step, perturbs it most.
+C1_500_TOL = {0: (1e-4, 2e-5, 5e-6), 1: (2e-2, 2e-3, 2e-3), 2: (0.5, 2e-2, 2e-2)}
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_c1_500_steps_by_storage(L, storage):
+    """C3 after 500 steps: C1 with FP32, FP16 and BF16 storage against the
+    FP64 oracle's run stored by tests/golden/make_c1_500.py (density and
+    velocity at sampled cells, G at the same cells, every point's du, the
+    mass).  Errors are relative to the largest oracle value of each
+    sample."""
+    tol_vel, tol_force, tol_du = C1_500_TOL[storage]
+    ref = np.load(GOLDEN_500)
+    wl = W.config("c1")
+    sim, _, _ = sim_for_workload(L, wl, storage=storage)
+    sim.step(int(ref["steps"]))
+    out = sim.read("rho", "vel", "force", "pt_du", "sums")
+    z, y, x = ref["cells"].T.astype(np.int64)
+    e = dict(vel=rel_linf(to_np(out["vel"])[:, z, y, x], ref["vel"]),
+             rho=rel_linf(to_np(out["rho"])[z, y, x] - 1, ref["rho_minus_1"]),
+             force=rel_linf(to_np(out["force"])[:, z, y, x], ref["force"]),
+             du=rel_linf(to_np(out["pt_du"]), ref["du"]))
+    mass0 = float(np.prod(wl.shape))
+    drift = abs(float(to_np(out["sums"])[0]) - mass0) / mass0
+    print("c1 500 steps, storage", storage, e, "mass drift", drift,
+          "oracle drift", abs(float(ref["mass"]) - mass0) / mass0, flush=True)
+    assert e["vel"] < tol_vel and e["force"] < tol_force and e["du"] < tol_du
+    assert drift < 1e-5
