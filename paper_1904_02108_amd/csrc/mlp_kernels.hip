@@ -20,6 +20,11 @@ static_assert(OFF_B4 + NOUT == NPARAM, "MLP parameter layout");
 constexpr int NNBR = IBM_MLP_NNBR;
 
 __device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// The same with the hardware reciprocal (about 1 ulp), for the matrix-core
+// network whose BF16 operands round far more coarsely.
+__device__ __forceinline__ float silu_fast(float z) {
+  return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
 __device__ __forceinline__ float silu_grad(float z) {
   const float s = 1.0f / (1.0f + __expf(-z));
   return s * (1.0f + z * (1.0f - s));
@@ -100,20 +105,13 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int N_MFMA = 22;
 
-__device__ __forceinline__ uint32_t bf16_bits(float v) {
-  uint32_t u = __float_as_uint(v);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (u >> 16) | 0x40u;
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return u >> 16;
-}
-
+// Eight values as BF16 (round to nearest even; gfx950 converts two per
+// instruction).
 __device__ __forceinline__ bf16x8 pack8(const float* v) {
-  u32x4 w;
-  w.x = bf16_bits(v[0]) | (bf16_bits(v[1]) << 16);
-  w.y = bf16_bits(v[2]) | (bf16_bits(v[3]) << 16);
-  w.z = bf16_bits(v[4]) | (bf16_bits(v[5]) << 16);
-  w.w = bf16_bits(v[6]) | (bf16_bits(v[7]) << 16);
-  return __builtin_bit_cast(bf16x8, w);
+  bf16x8 w;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) w[e] = (__bf16)v[e];
+  return w;
 }
 
 // Hidden unit held by element e of the B operand of chunk c of input block b
@@ -171,7 +169,8 @@ __device__ __forceinline__ void hidden_to_operands(const f32x16 acc[2], const fl
   for (int b = 0; b < 2; ++b) {
     float a[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) a[r] = silu(acc[b][r] + bias[32 * b + 8 * (r >> 2) + 4 * h + (r & 3)]);
+    for (int r = 0; r < 16; ++r)
+      a[r] = silu_fast(acc[b][r] + bias[32 * b + 8 * (r >> 2) + 4 * h + (r & 3)]);
     B[2 * b] = pack8(a);
     B[2 * b + 1] = pack8(a + 8);
   }
@@ -236,6 +235,10 @@ __global__ __launch_bounds__(MFMA_WG) void k_mlp_forward_mfma(const u32x4* __res
   const int64_t groups = (n + 31) / 32;
   for (int64_t g = (int64_t)blockIdx.x * (MFMA_WG / 64) + wave; g < groups;
        g += (int64_t)gridDim.x * (MFMA_WG / 64)) {
+    // weights and biases are re-read from LDS for every group: kept in
+    // registers across groups they would take most of the register file
+    // and leave one wave per SIMD to hide the gathers' latency
+    asm volatile("" ::: "memory");
     const int64_t k = 32 * g + (l & 31);
     float x8[8], yo[3];
     load_x8(x, k, n, h, x8);
@@ -248,9 +251,40 @@ __global__ __launch_bounds__(MFMA_WG) void k_mlp_forward_mfma(const u32x4* __res
   }
 }
 
+// Sum, component-wise max and count of g0 over entries 8 half .. 8 half + 7
+// of N(orig) (the list's -1 pads come last): two 16-byte loads of indices,
+// then the eight deficits loaded together.  The features add the two halves'
+// sums (half 0 + half 1), the same in both feature kernels.
+__device__ __forceinline__ void nbr_half(const int32_t* __restrict__ nbr,
+                                         const float4* __restrict__ g0_orig, int orig, int half,
+                                         float s[3], float mx[3], int& cnt) {
+  const int4* row = reinterpret_cast<const int4*>(nbr + (int64_t)orig * NNBR) + 2 * half;
+  const int4 a = row[0], b = row[1];
+  const int q[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  float4 gq[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) gq[e] = q[e] >= 0 ? g0_orig[q[e]] : make_float4(0.f, 0.f, 0.f, 0.f);
+  s[0] = s[1] = s[2] = 0.0f;
+  mx[0] = mx[1] = mx[2] = -INFINITY;
+  cnt = 0;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    if (q[e] < 0) continue;
+    s[0] += gq[e].x;
+    s[1] += gq[e].y;
+    s[2] += gq[e].z;
+    mx[0] = fmaxf(mx[0], gq[e].x);
+    mx[1] = fmaxf(mx[1], gq[e].y);
+    mx[2] = fmaxf(mx[2], gq[e].z);
+    ++cnt;
+  }
+}
+
 // Elements 8 h .. 8 h + 7 of the features of point k (sorted order; the same
 // definition as k_features_warm): g0, u_b, mean and component-wise max of g0
-// over N(k), divided by v_ref.
+// over N(k), divided by v_ref.  Each half-wave gathers half of the
+// neighbours; the two halves of a point (lanes l and l ^ 32) exchange their
+// partial sums, so every lane of the wave must call this.
 __device__ __forceinline__ void features8(int64_t k, int64_t n, int h,
                                           const int4* __restrict__ sp_base,
                                           const float4* __restrict__ sp_g,
@@ -261,23 +295,21 @@ __device__ __forceinline__ void features8(int64_t k, int64_t n, int h,
                                           const float* __restrict__ vref, float x8[8]) {
 #pragma unroll
   for (int e = 0; e < 8; ++e) x8[e] = 0.0f;
-  if (k >= n) return;
-  const int orig = sp_base[k].w;
-  const float inv = 1.0f / vref[body_of[orig]];
-  float m[3] = {0.f, 0.f, 0.f}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-  int cnt = 0;
-  for (int j = 0; j < NNBR; ++j) {
-    const int q = nbr[(int64_t)orig * NNBR + j];
-    if (q < 0) break;
-    const float4 gq = g0_orig[q];
-    m[0] += gq.x;
-    m[1] += gq.y;
-    m[2] += gq.z;
-    mx[0] = fmaxf(mx[0], gq.x);
-    mx[1] = fmaxf(mx[1], gq.y);
-    mx[2] = fmaxf(mx[2], gq.z);
-    ++cnt;
+  const bool live = k < n;  // the same for both halves of a point
+  const int orig = live ? sp_base[k].w : 0;
+  float sh[3], mh[3];
+  int ch;
+  nbr_half(nbr, g0_orig, orig, h, sh, mh, ch);
+  float m[3], mx[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float so = __shfl_xor(sh[c], 32, 64), mo = __shfl_xor(mh[c], 32, 64);
+    m[c] = h == 0 ? sh[c] + so : so + sh[c];  // half 0 + half 1 on both
+    mx[c] = fmaxf(mh[c], mo);
   }
+  const int cnt = ch + __shfl_xor(ch, 32, 64);
+  if (!live) return;
+  const float inv = 1.0f / vref[body_of[orig]];
   const float mean[3] = {cnt ? m[0] / (float)cnt * inv : 0.0f, cnt ? m[1] / (float)cnt * inv : 0.0f,
                          cnt ? m[2] / (float)cnt * inv : 0.0f};
   if (h == 0) {
@@ -315,6 +347,10 @@ __global__ __launch_bounds__(MFMA_WG) void k_warm_mfma(
   const int64_t groups = (n + 31) / 32;
   for (int64_t g = (int64_t)blockIdx.x * (MFMA_WG / 64) + wave; g < groups;
        g += (int64_t)gridDim.x * (MFMA_WG / 64)) {
+    // weights and biases are re-read from LDS for every group: kept in
+    // registers across groups they would take most of the register file
+    // and leave one wave per SIMD to hide the gathers' latency
+    asm volatile("" ::: "memory");
     const int64_t k = 32 * g + (l & 31);
     float x8[8], yo[3];
     if (feat)
@@ -478,20 +514,15 @@ __global__ __launch_bounds__(256) void k_features_warm(
   const float inv = 1.0f / v;
   const float4 g = sp_g[k];
   const float4 ub = sp_ub[k];
-  float m[3] = {0.f, 0.f, 0.f}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-  int cnt = 0;
-  for (int j = 0; j < NNBR; ++j) {
-    const int q = nbr[(int64_t)orig * NNBR + j];
-    if (q < 0) break;
-    const float4 gq = g0_orig[q];
-    m[0] += gq.x;
-    m[1] += gq.y;
-    m[2] += gq.z;
-    mx[0] = fmaxf(mx[0], gq.x);
-    mx[1] = fmaxf(mx[1], gq.y);
-    mx[2] = fmaxf(mx[2], gq.z);
-    ++cnt;
+  float s0[3], s1[3], x0[3], x1[3], m[3], mx[3];
+  int c0, c1;
+  nbr_half(nbr, g0_orig, orig, 0, s0, x0, c0);
+  nbr_half(nbr, g0_orig, orig, 1, s1, x1, c1);
+  for (int c = 0; c < 3; ++c) {
+    m[c] = s0[c] + s1[c];
+    mx[c] = fmaxf(x0[c], x1[c]);
   }
+  const int cnt = c0 + c1;
   float x[NIN];
   x[0] = g.x * inv;
   x[1] = g.y * inv;
