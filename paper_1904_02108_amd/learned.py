@@ -80,9 +80,11 @@ def surface_sim(wl, flags, n_iter, eps=0.0, theta=None, device="cuda"):
     return sim
 
 
-def collect_pairs(wl, n_steps, n_iter=10, skip=0, flags=0, eps=0.0, device="cuda", limit=50.0):
+def collect_pairs(wl, n_steps, n_iter=10, skip=0, flags=0, eps=0.0, device="cuda", limit=50.0,
+                  stride=1):
     """Training pairs from a plain run of ``wl``: the first-sweep features
-    and the final correction of every step after ``skip`` warm-up steps.
+    and the final correction of n_steps steps, the first after ``skip``
+    warm-up steps and then every ``stride``-th step.
     Returns device tensors x [m,12], t [m,3] with m = n_points * (steps
     kept).  Features and targets are velocities over the body's reference
     speed, of order one while the flow is sound; a run keeps only the steps
@@ -96,6 +98,8 @@ def collect_pairs(wl, n_steps, n_iter=10, skip=0, flags=0, eps=0.0, device="cuda
     if skip:
         sim.step(skip)
     for k in range(n_steps):
+        if k and stride > 1:
+            sim.step(stride - 1)
         sim.step(1)
         sim.log_pairs(x[k * n:(k + 1) * n], t[k * n:(k + 1) * n])
     torch.cuda.synchronize(device)
