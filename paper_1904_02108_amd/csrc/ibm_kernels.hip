@@ -1034,39 +1034,47 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_reduce_rows(const double* __restr
 // inside the sweep by its last workgroup would need a device-scope release
 // fence in every workgroup, which writes back the L2 and costs more than
 // this launch.)
-__global__ __launch_bounds__(LBM_BLOCK) void k_resid_threshold(const double* __restrict__ part_sub2,
-                                                               int64_t nblk, double eps2,
-                                                               double* __restrict__ thr,
-                                                               uint32_t* __restrict__ ctl) {
-  double s = 0.0;
-  for (int64_t b = threadIdx.x; b < nblk; b += LBM_BLOCK) s += part_sub2[b];
-  __shared__ double red[LBM_BLOCK / 64];
-  const double v = wave_sum(s);
+// One workgroup of RESID_WG threads sums the partials in a fixed order: each
+// thread a strided subset (four loads in flight), then the waves.
+constexpr int RESID_WG = 1024;
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int64_t n) {
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t b = threadIdx.x;
+  for (; b + 3 * RESID_WG < n; b += 4 * RESID_WG) {
+    s0 += part[b];
+    s1 += part[b + RESID_WG];
+    s2 += part[b + 2 * RESID_WG];
+    s3 += part[b + 3 * RESID_WG];
+  }
+  for (; b < n; b += RESID_WG) s0 += part[b];
+  __shared__ double red[RESID_WG / 64];
+  const double v = wave_sum((s0 + s1) + (s2 + s3));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < RESID_WG / 64; ++w) t += red[w];
+  return t;  // the same on every thread
+}
+
+__global__ __launch_bounds__(RESID_WG) void k_resid_threshold(const double* __restrict__ part_sub2,
+                                                              int64_t nblk, double eps2,
+                                                              double* __restrict__ thr,
+                                                              uint32_t* __restrict__ ctl) {
+  const double t = sum_partials(part_sub2, nblk);
   if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < LBM_BLOCK / 64; ++w) t += red[w];
     *thr = eps2 * t;
     ctl[0] = 0u;
     ctl[1] = 0u;
   }
 }
 
-__global__ __launch_bounds__(LBM_BLOCK) void k_resid_check(const double* __restrict__ part_res,
-                                                           int64_t nblk, const double* __restrict__ thr,
-                                                           int it, int last, int use_thr,
-                                                           uint32_t* __restrict__ ctl) {
+__global__ __launch_bounds__(RESID_WG) void k_resid_check(const double* __restrict__ part_res,
+                                                          int64_t nblk, const double* __restrict__ thr,
+                                                          int it, int last, int use_thr,
+                                                          uint32_t* __restrict__ ctl) {
   if (ctl[0]) return;
-  double s = 0.0;
-  for (int64_t b = threadIdx.x; b < nblk; b += LBM_BLOCK) s += part_res[b];
-  __shared__ double red[LBM_BLOCK / 64];
-  const double v = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
+  const double t = sum_partials(part_res, nblk);
   if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < LBM_BLOCK / 64; ++w) t += red[w];
     ctl[1] = (uint32_t)(it + 1);
     if (last || (use_thr && t <= *thr)) ctl[0] = 1u;
   }
@@ -1276,7 +1284,7 @@ hipError_t launch_forcing(lbm_ctx* c) {
   const bool from_prev = save_prev && c->du_prev_valid;
   const int use_thr = (c->flags & IBM_STOP_RESIDUAL) ? 1 : 0;
   const int64_t na = (n + LBM_BLOCK - 1) / LBM_BLOCK;
-  k_resid_threshold<<<1, LBM_BLOCK, 0, st>>>(c->pt_partials + rs, na,
+  k_resid_threshold<<<1, RESID_WG, 0, st>>>(c->pt_partials + rs, na,
                                              (double)c->eps * (double)c->eps, c->resid_thr, c->ctl);
   TRY(hipGetLastError());
   for (int it = 0; it < N; ++it) {
@@ -1287,7 +1295,7 @@ hipError_t launch_forcing(lbm_ctx* c) {
     const bool spread = !last && !((warm || from_prev) && it == 0);
     const int mode = SW_INTERP | (it == 0 ? SW_FIRST : 0) | (spread ? SW_SPREAD_G : 0);
     TRY(sweep(it, mode, gate, it == 0 && feats ? c->g0_orig : nullptr));
-    k_resid_check<<<1, LBM_BLOCK, 0, st>>>(c->pt_partials + (2 + it) * rs, lg, c->resid_thr, it,
+    k_resid_check<<<1, RESID_WG, 0, st>>>(c->pt_partials + (2 + it) * rs, lg, c->resid_thr, it,
                                            last ? 1 : 0, use_thr, c->ctl);
     TRY(hipGetLastError());
     if (it == 0 && feats) {
