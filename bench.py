@@ -420,10 +420,16 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2_dense",
-                    choices=["c0", "c1", "c1_dense", "c2", "c2_dense"] +
+                    choices=["c0", "c1", "c1_dense", "c2", "c2_dense", "c2_half", "c2_dense_half"] +
                             ["paper%d" % k for k in (1, 2, 3, 4, 5, 6, 18)])
     ap.add_argument("--u-prepass", default="tile", choices=["tile", "box", "kernel"],
                     help="U pre-pass strategy of the main run (section 5)")
+    ap.add_argument("--stop-eps", type=float, default=0.0,
+                    help="main run: stop the sweeps at this relative residual (at most the "
+                         "workload's sweep count)")
+    ap.add_argument("--warm", default="none", choices=["none", "prev", "net"],
+                    help="main run: warm start from the previous step's correction, or from an "
+                         "untrained network (its cost only)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--forcing", default="guo", choices=["guo", "shift"])
     ap.add_argument("--cpu-steps", type=int, default=4)
@@ -460,7 +466,15 @@ def main():
     sim = L.Simulation(wl.shape, wl.tau, bc=wl.bc, storage=storage, forcing=forcing,
                        max_points=wl.n_points, max_iter=wl.n_iter, device="cuda:0")
     uflags = {"tile": 0, "box": L.IBM_U_BOX, "kernel": L.IBM_U_KERNEL}[args.u_prepass]
-    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter, uflags)
+    if args.stop_eps > 0:
+        uflags |= L.IBM_STOP_RESIDUAL
+    if args.warm == "prev":
+        uflags |= L.IBM_WARM_PREV
+    elif args.warm == "net":
+        uflags |= L.IBM_WARM_START
+        sim.set_mlp(W.mlp_init(5))
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter, uflags,
+                   args.stop_eps if args.stop_eps > 0 else 0.0)
     stream = torch.cuda.current_stream()
 
     sim.step(args.warmup)
@@ -505,7 +519,8 @@ def main():
         "config": {"workload": wl.name, "grid": list(wl.shape), "bc": list(wl.bc), "tau": wl.tau,
                    "n_points": wl.n_points, "n_bodies": int(len(wl.bodies)), "h": wl.h,
                    "sweeps": wl.n_iter, "forcing": args.forcing, "storage": args.storage,
-                   "u_prepass": args.u_prepass, "parallelism": "single GPU"},
+                   "u_prepass": args.u_prepass, "stop_eps": args.stop_eps, "warm": args.warm,
+                   "parallelism": "single GPU"},
         "point_updates_per_s": round(wl.n_points * K / (ms * 1e-3), 1),
         # point updates per sweep over the forcing's own time
         "point_sweep_updates_per_s_forcing": round(wl.n_points * wl.n_iter / (forcing_ms * 1e-3), 1),
