@@ -55,6 +55,12 @@ def traffic_from_profiles(storage):
     return d.get("bytes_per_launch", {}).get(str(storage))
 
 
+def stream_collide_kernel(storage, nx):
+    """The stream-collide kernel the library launches: cell pairs for 16-bit
+    storage with an even x extent, one cell per thread otherwise."""
+    return "k_stream_collide_pairs" if storage != 0 and nx % 2 == 0 else "k_stream_collide"
+
+
 def cpu_baseline(wl, n_steps):
     """The FP64 oracle on the host cores: n_steps steps of the same workload."""
     import numpy as np  # noqa: F401
@@ -289,6 +295,8 @@ def precision_leg(torch, L, W, name, storage, steps=10, warmup=3):
     return {"MLUPS": round(wl.n_cells / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
             "ms_fluid": round(fluid, 4), "fluid_MLUPS": round(wl.n_cells / (fluid * 1e-3) / 1e6, 1),
             "stream_collide_GBs": round(ach, 1), "stream_collide_frac": round(ach / HBM_PEAK_GBS, 4),
+            "stream_collide_kernel": stream_collide_kernel(storage, wl.shape[0]),
+            "stream_collide_traffic": traffic_from_profiles(storage) if name == "c2_dense" else None,
             "bytes_per_cell": bpc, "steps": steps, "warmup": warmup}
 
 
@@ -536,7 +544,7 @@ def main():
         "mass_rel_drift": float(abs(sums[0] - wl.n_cells) / wl.n_cells),
         "finite": bool(all(map(lambda v: v == v and abs(v) != float("inf"), sums))),
         "max_abs_velocity": vmax,
-        "roofline": {"bound": "hbm", "kernel": "k_stream_collide",
+        "roofline": {"bound": "hbm", "kernel": stream_collide_kernel(storage, wl.shape[0]),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": bpc * wl.n_cells},

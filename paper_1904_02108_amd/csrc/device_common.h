@@ -53,6 +53,20 @@ struct Store<LBM_STORE_F16> {
   static __device__ __forceinline__ void store_nt(T* p, float v) {
     __builtin_nontemporal_store((_Float16)v, p);
   }
+  // load2_nt / store2_nt: two consecutive values at an even element offset
+  // (4-byte aligned) in one access.
+  typedef _Float16 V2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ void load2_nt(const T* p, float& a, float& b) {
+    const V2 v = __builtin_nontemporal_load(reinterpret_cast<const V2*>(p));
+    a = (float)v.x;
+    b = (float)v.y;
+  }
+  static __device__ __forceinline__ void store2_nt(T* p, float a, float b) {
+    V2 v;
+    v.x = (_Float16)a;
+    v.y = (_Float16)b;
+    __builtin_nontemporal_store(v, reinterpret_cast<V2*>(p));
+  }
 };
 
 template <>
@@ -64,16 +78,23 @@ struct Store<LBM_STORE_BF16> {
   static __device__ __forceinline__ float load_nt(const T* p) {
     return __uint_as_float(((uint32_t)__builtin_nontemporal_load(p)) << 16);
   }
+  // gfx950 converts FP32 to BF16 in hardware, rounding to nearest even and
+  // keeping NaN quiet; one instruction in place of the integer sequence.
   static __device__ __forceinline__ uint16_t bits(float v) {
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
-      return (uint16_t)((u >> 16) | 0x40u);  // keep NaN quiet
-    u += 0x7fffu + ((u >> 16) & 1u);        // round to nearest even
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)v);
   }
   static __device__ __forceinline__ void store(T* p, float v) { *p = bits(v); }
   static __device__ __forceinline__ void store_nt(T* p, float v) {
     __builtin_nontemporal_store(bits(v), p);
+  }
+  static __device__ __forceinline__ void load2_nt(const T* p, float& a, float& b) {
+    const uint32_t u = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p));
+    a = __uint_as_float(u << 16);
+    b = __uint_as_float(u & 0xffff0000u);
+  }
+  static __device__ __forceinline__ void store2_nt(T* p, float a, float b) {
+    const uint32_t u = (uint32_t)bits(a) | ((uint32_t)bits(b) << 16);
+    __builtin_nontemporal_store(u, reinterpret_cast<uint32_t*>(p));
   }
 };
 
@@ -188,6 +209,43 @@ __device__ __forceinline__ void gather_fast(const typename Store<S>::T* __restri
     const typename Store<S>::T* q =
         lat + (int64_t)i * g.stride + (p.xs[EX[i] + 1] + p.ys[EY[i] + 1] + p.zs[EZ[i] + 1]);
     f[i] = NT ? Store<S>::load_nt(q) : Store<S>::load(q);
+  }
+}
+
+// Pull gather of two neighbouring cells x0 and x0 + 1 of one row for the
+// 16-bit formats (x0 even, nx even, so that the pair is aligned).  Away from walls each population
+// comes as one pair load at the source row's x0; a population with e_x = +1
+// takes x0 - 1 for the first cell from a single load, one with e_x = -1 takes
+// x0 + 2 for the second.  Next to a wall: the general gather of each cell.
+template <int S>
+__device__ __forceinline__ void gather_pair(const typename Store<S>::T* __restrict__ lat,
+                                            const LatticeGeom& g, int x0, int y, int z,
+                                            float f0[Q], float f1[Q]) {
+  const PullIdx p = pull_index(g, x0, y, z);
+  const bool periodic_x = g.bc[0] == LBM_BC_PERIODIC;
+  if (!(p.fast && (periodic_x || x0 + 2 < g.nx))) {
+    gather_pull<S>(lat, g, x0, y, z, f0);
+    gather_pull<S>(lat, g, x0 + 1, y, z, f1);
+    return;
+  }
+  const uint32_t xl = p.xs[2];                                   // x0 - 1, wrapped
+  const uint32_t xr = (uint32_t)(x0 + 2 == g.nx ? 0 : x0 + 2);   // x0 + 2, wrapped
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const typename Store<S>::T* row =
+        lat + (int64_t)i * g.stride + (p.ys[EY[i] + 1] + p.zs[EZ[i] + 1]);
+    float a, b;
+    Store<S>::load2_nt(row + x0, a, b);
+    if (EX[i] == 0) {
+      f0[i] = a;
+      f1[i] = b;
+    } else if (EX[i] == 1) {
+      f0[i] = Store<S>::load_nt(row + xl);
+      f1[i] = a;
+    } else {
+      f0[i] = b;
+      f1[i] = Store<S>::load_nt(row + xr);
+    }
   }
 }
 

@@ -17,12 +17,81 @@ __device__ __forceinline__ void cell_xyz(const LatticeGeom& g, int64_t cell, int
 }
 
 // ---------------------------------------------------------------------------
-// Fused stream-collide.  One thread per cell: gather the post-stream offsets
-// (pull), form rho and U (eq. 1), add the force of flagged tiles and the
-// uniform acceleration, relax towards the equilibrium (eqs. 2-3) with the
+// Fused stream-collide.  Per cell: gather the post-stream offsets (pull), form
+// rho and U (eq. 1), add the force of flagged tiles and the uniform
+// acceleration, relax towards the equilibrium (eqs. 2-3) with the
 // velocity-shift or Guo forcing, store the post-collision offsets.  Each
 // workgroup also writes FP64 partial sums of (rho - 1, rho U).
 // ---------------------------------------------------------------------------
+
+// Collision of one cell: f holds the post-stream offsets on entry and the
+// post-collision ones on return; (gx, gy, gz) is the acceleration at the
+// cell.  Returns rho - 1 and rho U before the force.
+template <int FORCING>
+__device__ __forceinline__ void collide_cell(const LatticeGeom& g, float f[Q], float gx, float gy,
+                                             float gz, float& drho, float& jx, float& jy,
+                                             float& jz) {
+  drho = 0.f;
+  jx = 0.f;
+  jy = 0.f;
+  jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += f[i];
+    if (EX[i]) jx += EX[i] * f[i];
+    if (EY[i]) jy += EY[i] * f[i];
+    if (EZ[i]) jz += EZ[i] * f[i];
+  }
+  const float rho = 1.0f + drho;
+  const float inv = 1.0f / rho;
+  float ux, uy, uz;
+  if (FORCING == LBM_FORCE_SHIFT) {
+    ux = jx * inv + g.tau * gx;
+    uy = jy * inv + g.tau * gy;
+    uz = jz * inv + g.tau * gz;
+  } else {
+    ux = jx * inv + 0.5f * gx;
+    uy = jy * inv + 0.5f * gy;
+    uz = jz * inv + 0.5f * gz;
+  }
+  const float uu = ux * ux + uy * uy + uz * uz;
+  const float om = g.omega;
+  const float fx = rho * gx, fy = rho * gy, fz = rho * gz;
+  const float uF = ux * fx + uy * fy + uz * fz;
+  const float guo = 1.0f - 0.5f * om;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
+    const float feq = wgt(i) * (drho + rho * (3.0f * eu + 4.5f * eu * eu - 1.5f * uu));
+    float post = f[i] + om * (feq - f[i]);
+    if (FORCING == LBM_FORCE_GUO) {
+      const float eF = EX[i] * fx + EY[i] * fy + EZ[i] * fz;
+      post += guo * wgt(i) * (3.0f * (eF - uF) + 9.0f * eu * eF);
+    }
+    f[i] = post;
+  }
+}
+
+// The workgroup's FP64 sums of part[0..3] into partials[blk].
+__device__ __forceinline__ void store_partials(double part[4], int tid, int64_t blk,
+                                               double* __restrict__ partials) {
+  __shared__ double red[4][LBM_BLOCK / 64];
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double v = wave_sum(part[k]);
+    if (lane == 0) red[k][wave] = v;
+  }
+  __syncthreads();
+  if (tid < 4) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < LBM_BLOCK / 64; ++w) s += red[tid][w];
+    partials[blk * 4 + tid] = s;
+  }
+}
+
+// One thread per cell (FP32 storage, odd x extents).
 #ifndef LBM_SC_ROWS
 #define LBM_SC_ROWS 1
 #endif
@@ -45,75 +114,82 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
   const int z = blockIdx.z;
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   for (int r = 0; r < LBM_SC_ROWS; ++r) {
-  const int y = FLAT ? yf : (blockIdx.y * LBM_SC_ROWS + r) * blockDim.y + threadIdx.y;
-  if (x < g.nx && y < g.ny) {
-    const uint32_t cell = (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
-    float f[Q];
-    gather_any<S, true>(src, g, x, y, z, f);
-  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      drho += f[i];
-      if (EX[i]) jx += EX[i] * f[i];
-      if (EY[i]) jy += EY[i] * f[i];
-      if (EZ[i]) jz += EZ[i] * f[i];
-    }
-    const float rho = 1.0f + drho;
-    const float inv = 1.0f / rho;
-    float gx = g.g_ext[0], gy = g.g_ext[1], gz = g.g_ext[2];
-    if (flags[fblock_of(g, x, y, z)]) {
-      gx += G[cell];
-      gy += G[g.ncell + cell];
-      gz += G[2 * g.ncell + cell];
-    }
-    float ux, uy, uz;
-    if (FORCING == LBM_FORCE_SHIFT) {
-      ux = jx * inv + g.tau * gx;
-      uy = jy * inv + g.tau * gy;
-      uz = jz * inv + g.tau * gz;
-    } else {
-      ux = jx * inv + 0.5f * gx;
-      uy = jy * inv + 0.5f * gy;
-      uz = jz * inv + 0.5f * gz;
-    }
-    const float uu = ux * ux + uy * uy + uz * uz;
-    const float om = g.omega;
-    const float fx = rho * gx, fy = rho * gy, fz = rho * gz;
-    const float uF = ux * fx + uy * fy + uz * fz;
-    const float guo = 1.0f - 0.5f * om;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const float eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
-      const float feq = wgt(i) * (drho + rho * (3.0f * eu + 4.5f * eu * eu - 1.5f * uu));
-      float post = f[i] + om * (feq - f[i]);
-      if (FORCING == LBM_FORCE_GUO) {
-        const float eF = EX[i] * fx + EY[i] * fy + EZ[i] * fz;
-        post += guo * wgt(i) * (3.0f * (eF - uF) + 9.0f * eu * eF);
+    const int y = FLAT ? yf : (blockIdx.y * LBM_SC_ROWS + r) * blockDim.y + threadIdx.y;
+    if (x < g.nx && y < g.ny) {
+      const uint32_t cell =
+          (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+      float f[Q];
+      gather_any<S, true>(src, g, x, y, z, f);
+      float gx = g.g_ext[0], gy = g.g_ext[1], gz = g.g_ext[2];
+      if (flags[fblock_of(g, x, y, z)]) {
+        gx += G[cell];
+        gy += G[g.ncell + cell];
+        gz += G[2 * g.ncell + cell];
       }
-      Store<S>::store_nt(dst + (int64_t)i * g.stride + cell, post);
+      float drho, jx, jy, jz;
+      collide_cell<FORCING>(g, f, gx, gy, gz, drho, jx, jy, jz);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) Store<S>::store_nt(dst + (int64_t)i * g.stride + cell, f[i]);
+      part[0] += drho;
+      part[1] += jx;
+      part[2] += jy;
+      part[3] += jz;
     }
+  }
+  const int64_t blk = (int64_t)blockIdx.x +
+                      (int64_t)gridDim.x * ((int64_t)blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+  store_partials(part, threadIdx.x + blockDim.x * threadIdx.y, blk, partials);
+}
+
+// Two cells per thread (16-bit storage, even x extents): the pair (x0, x0 + 1)
+// is read and written with one 4-byte access per population (see
+// gather_pair); 256 threads over consecutive pairs of an x-y plane.
+template <int S, int FORCING>
+__global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide_pairs(
+    const typename Store<S>::T* __restrict__ src, typename Store<S>::T* __restrict__ dst,
+    const LatticeGeom g, const float* __restrict__ G, const uint8_t* __restrict__ flags,
+    double* __restrict__ partials) {
+  const int px = g.nx >> 1;
+  const int pf = blockIdx.x * LBM_BLOCK + threadIdx.x;
+  const int y = pf / px;
+  const int x0 = 2 * (pf - y * px);
+  const int z = blockIdx.z;
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+  if (y < g.ny) {
+    const uint32_t cell =
+        (uint32_t)x0 + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+    float f0[Q], f1[Q];
+    gather_pair<S>(src, g, x0, y, z, f0, f1);
+    float ax[2] = {g.g_ext[0], g.g_ext[0]}, ay[2] = {g.g_ext[1], g.g_ext[1]},
+          az[2] = {g.g_ext[2], g.g_ext[2]};
+    if (flags[fblock_of(g, x0, y, z)]) {  // x0 and x0 + 1 share a force block
+      const float2 gxv = *reinterpret_cast<const float2*>(G + cell);
+      const float2 gyv = *reinterpret_cast<const float2*>(G + g.ncell + cell);
+      const float2 gzv = *reinterpret_cast<const float2*>(G + 2 * g.ncell + cell);
+      ax[0] += gxv.x;
+      ax[1] += gxv.y;
+      ay[0] += gyv.x;
+      ay[1] += gyv.y;
+      az[0] += gzv.x;
+      az[1] += gzv.y;
+    }
+    float drho, jx, jy, jz;
+    collide_cell<FORCING>(g, f0, ax[0], ay[0], az[0], drho, jx, jy, jz);
     part[0] += drho;
     part[1] += jx;
     part[2] += jy;
     part[3] += jz;
-  }
-  }
-  __shared__ double red[4][LBM_BLOCK / 64];
-  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
-  const int lane = tid & 63, wave = tid >> 6;
+    collide_cell<FORCING>(g, f1, ax[1], ay[1], az[1], drho, jx, jy, jz);
+    part[0] += drho;
+    part[1] += jx;
+    part[2] += jy;
+    part[3] += jz;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    double v = wave_sum(part[k]);
-    if (lane == 0) red[k][wave] = v;
+    for (int i = 0; i < Q; ++i)
+      Store<S>::store2_nt(dst + (int64_t)i * g.stride + cell, f0[i], f1[i]);
   }
-  __syncthreads();
-  if (tid < 4) {
-    double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < LBM_BLOCK / 64; ++w) s += red[tid][w];
-    const int64_t blk = (int64_t)blockIdx.x + (int64_t)gridDim.x * ((int64_t)blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
-    partials[blk * 4 + tid] = s;
-  }
+  store_partials(part, threadIdx.x, (int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.z,
+                 partials);
 }
 
 // Loads post-stream populations f (full values, float or double) as the
@@ -256,13 +332,27 @@ int64_t cell_blocks(const lbm_ctx* c) { return (c->ncell + LBM_BLOCK - 1) / LBM_
 
 }  // namespace
 
-// Launch shape of the stream-collide: 256 threads, blockDim.x = the x extent
-// rounded to a wavefront (at most 256), the rest of the block along y; for an
-// x extent that is not a multiple of the wavefront, 256 consecutive cells of
-// an x-y plane (this grid never has more blocks than the other one).
+// Launch shape of the stream-collide.  16-bit storage with an even x extent:
+// the pair kernel, 256 threads over consecutive cell pairs of an x-y plane
+// (a 2-byte access per lane reaches far less of the HBM bandwidth than a
+// 4-byte one; for FP32 the pair form measured slower than one cell per
+// thread).  Otherwise 256 threads, blockDim.x = the x extent rounded to a
+// wavefront (at most 256), the rest of the block along y; for an x extent
+// that is not a multiple of the wavefront, 256 consecutive cells of an x-y
+// plane.  No shape has more blocks than ceil(nx / bx) * ceil(ny / by) * nz,
+// the count the partial sums are sized for.
+static bool stream_collide_pairs(const lbm_ctx* c) {
+  return c->p.storage != LBM_STORE_F32 && c->p.nx % 2 == 0;
+}
 static bool stream_collide_flat(const lbm_ctx* c) { return c->p.nx % 64 != 0; }
 
 void stream_collide_shape(const lbm_ctx* c, dim3& grid, dim3& block) {
+  if (stream_collide_pairs(c)) {
+    block = dim3(LBM_BLOCK, 1, 1);
+    grid = dim3((unsigned)(((int64_t)(c->p.nx / 2) * c->p.ny + LBM_BLOCK - 1) / LBM_BLOCK), 1,
+                c->p.nz);
+    return;
+  }
   if (stream_collide_flat(c)) {
     block = dim3(LBM_BLOCK, 1, 1);
     grid = dim3((unsigned)(((int64_t)c->p.nx * c->p.ny + LBM_BLOCK - 1) / LBM_BLOCK), 1, c->p.nz);
@@ -285,6 +375,17 @@ hipError_t stream_collide_s(lbm_ctx* c) {
   T* dst = (T*)c->lat[c->cur ^ 1];
   dim3 grid, block;
   stream_collide_shape(c, grid, block);
+  if constexpr (S != LBM_STORE_F32) {
+    if (stream_collide_pairs(c)) {
+      if (c->p.forcing == LBM_FORCE_SHIFT)
+        k_stream_collide_pairs<S, LBM_FORCE_SHIFT><<<grid, block, 0, c->stream>>>(
+            src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+      else
+        k_stream_collide_pairs<S, LBM_FORCE_GUO><<<grid, block, 0, c->stream>>>(
+            src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+      return hipGetLastError();
+    }
+  }
   const bool flat = stream_collide_flat(c);
   if (c->p.forcing == LBM_FORCE_SHIFT) {
     if (flat)

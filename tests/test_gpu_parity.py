@@ -61,6 +61,13 @@ CASES = [
     dict(shape=(12, 9, 11), bc=(0, 1, 1), forcing=0, tau=0.8, moving=True),
     dict(shape=(7, 12, 10), bc=(1, 1, 1), forcing=1, tau=0.9, moving=True, g_ext=(1e-5, -2e-5, 3e-5)),
     dict(shape=(5, 3, 7), bc=(0, 0, 1), forcing=0, tau=0.7),
+    # even x extents with walls on x, rows that end inside a wavefront, and
+    # nx = 2, where both x neighbours of a cell wrap or meet a wall
+    dict(shape=(8, 12, 10), bc=(1, 1, 1), forcing=0, tau=0.9, moving=True),
+    dict(shape=(10, 7, 6), bc=(1, 0, 1), forcing=1, tau=0.7),
+    dict(shape=(130, 3, 2), bc=(0, 0, 0), forcing=0, tau=0.65),
+    dict(shape=(2, 5, 4), bc=(0, 0, 0), forcing=1, tau=0.6),
+    dict(shape=(2, 6, 3), bc=(1, 1, 0), forcing=0, tau=0.75),
 ]
 
 

@@ -28,13 +28,17 @@ def L():
 
 
 @pytest.mark.parametrize("storage", [1, 2])
-@pytest.mark.parametrize("bc", [(0, 0, 0), (0, 1, 1)])
+@pytest.mark.parametrize("bc", [(0, 0, 0), (0, 1, 1), (1, 0, 1)])
 @pytest.mark.parametrize("shape,forcing", [((14, 11, 9), 0), ((128, 11, 9), 0),
-                                           ((256, 6, 5), 1)])
+                                           ((256, 6, 5), 1), ((13, 6, 5), 1),
+                                           ((130, 3, 2), 0), ((2, 5, 4), 1)])
 def test_one_step_16bit(L, storage, bc, shape, forcing):
-    """One step from the state the GPU holds, on a box with ragged blocks and
-    on rows of whole 128- and 256-cell blocks (the last with the velocity
-    shift).  The step's FP64 sums are those of the state it started from."""
+    """One step from the state the GPU holds, on a box with ragged blocks, on
+    rows of whole 128- and 256-cell blocks (with the velocity shift), with an
+    odd x extent (one cell per thread), rows of pairs that end inside a
+    wavefront, and nx = 2, where both x neighbours of a cell pair wrap or
+    meet a wall.  The step's FP64 sums are those of the state it started
+    from."""
     _, w, _ = O.d3q19()
     sim = make_sim(L, shape, 0.7, bc=bc, storage=storage, forcing=forcing)
     f0 = W.random_populations(shape, 71, amp=0.05, weights=w)
