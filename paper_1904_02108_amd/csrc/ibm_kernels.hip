@@ -1025,15 +1025,14 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_reduce_rows(const double* __restr
   }
 }
 
-// Residual-stopped forcing (ctl: [0] converged flag, [1] sweeps run).
-// k_resid_threshold: thr = eps^2 sum_k s |u_b|^2 (FP64, fixed order) and a
-// cleared control block.  k_resid_check after sweep `it`: unless already
-// converged, R = sum_k s |g|^2 of the sweep is compared with thr; R <= thr,
-// or the last allowed sweep, ends the forcing.  Comparing squared sums keeps
-// a body at rest (both sums zero) converged without a division.  (A check
-// inside the sweep by its last workgroup would need a device-scope release
-// fence in every workgroup, which writes back the L2 and costs more than
-// this launch.)
+// Residual-stopped forcing (ctl: [0] converged flag, [1] sweeps run).  After
+// each sweep, unless already converged, R = sum_k s |g|^2 of the sweep is
+// compared with thr = eps^2 sum_k s |u_b|^2 (both FP64, fixed order; thr is
+// formed by the check of sweep 0); R <= thr, or the last allowed sweep, ends
+// the forcing.  Comparing squared sums keeps a body at rest (both sums zero)
+// converged without a division.  (A check inside the sweep by its last
+// workgroup would need a device-scope release fence in every workgroup,
+// which writes back the L2 and costs more than this launch.)
 // One workgroup of RESID_WG threads sums the partials in a fixed order: each
 // thread a strided subset (four loads in flight), then the waves.
 constexpr int RESID_WG = 1024;
@@ -1056,27 +1055,31 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
   return t;  // the same on every thread
 }
 
-__global__ __launch_bounds__(RESID_WG) void k_resid_threshold(const double* __restrict__ part_sub2,
-                                                              int64_t nblk, double eps2,
-                                                              double* __restrict__ thr,
-                                                              uint32_t* __restrict__ ctl) {
-  const double t = sum_partials(part_sub2, nblk);
-  if (threadIdx.x == 0) {
-    *thr = eps2 * t;
-    ctl[0] = 0u;
-    ctl[1] = 0u;
-  }
-}
-
+// Residual test after sweep `it`: sets ctl[1] = it + 1 and, once the sweep's
+// sum s |g|^2 is within the threshold (or the sweep is the last), ctl[0] = 1,
+// which gates off every later sweep and merge of the forcing.  The check of
+// sweep 0 starts the forcing's control words and first forms the threshold
+// eps^2 sum s |u_b|^2 from the binning's partials (part_sub2, na of them); a
+// later check returns at once when ctl[0] is already set.
 __global__ __launch_bounds__(RESID_WG) void k_resid_check(const double* __restrict__ part_res,
-                                                          int64_t nblk, const double* __restrict__ thr,
-                                                          int it, int last, int use_thr,
+                                                          int64_t nblk,
+                                                          const double* __restrict__ part_sub2,
+                                                          int64_t na, double eps2,
+                                                          double* __restrict__ thr, int it,
+                                                          int last, int use_thr,
                                                           uint32_t* __restrict__ ctl) {
-  if (ctl[0]) return;
+  double th;
+  if (it == 0) {
+    th = eps2 * sum_partials(part_sub2, na);
+    if (threadIdx.x == 0) *thr = th;
+  } else {
+    if (ctl[0]) return;
+    th = *thr;
+  }
   const double t = sum_partials(part_res, nblk);
   if (threadIdx.x == 0) {
     ctl[1] = (uint32_t)(it + 1);
-    if (last || (use_thr && t <= *thr)) ctl[0] = 1u;
+    ctl[0] = (last || (use_thr && t <= th)) ? 1u : 0u;
   }
 }
 
@@ -1284,9 +1287,7 @@ hipError_t launch_forcing(lbm_ctx* c) {
   const bool from_prev = save_prev && c->du_prev_valid;
   const int use_thr = (c->flags & IBM_STOP_RESIDUAL) ? 1 : 0;
   const int64_t na = (n + LBM_BLOCK - 1) / LBM_BLOCK;
-  k_resid_threshold<<<1, RESID_WG, 0, st>>>(c->pt_partials + rs, na,
-                                             (double)c->eps * (double)c->eps, c->resid_thr, c->ctl);
-  TRY(hipGetLastError());
+  const double eps2 = (double)c->eps * (double)c->eps;
   for (int it = 0; it < N; ++it) {
     const bool last = it == N - 1;
     const uint32_t* gate = it == 0 ? nullptr : c->ctl;
@@ -1295,7 +1296,8 @@ hipError_t launch_forcing(lbm_ctx* c) {
     const bool spread = !last && !((warm || from_prev) && it == 0);
     const int mode = SW_INTERP | (it == 0 ? SW_FIRST : 0) | (spread ? SW_SPREAD_G : 0);
     TRY(sweep(it, mode, gate, it == 0 && feats ? c->g0_orig : nullptr));
-    k_resid_check<<<1, RESID_WG, 0, st>>>(c->pt_partials + (2 + it) * rs, lg, c->resid_thr, it,
+    k_resid_check<<<1, RESID_WG, 0, st>>>(c->pt_partials + (2 + it) * rs, lg,
+                                           c->pt_partials + rs, na, eps2, c->resid_thr, it,
                                            last ? 1 : 0, use_thr, c->ctl);
     TRY(hipGetLastError());
     if (it == 0 && feats) {
