@@ -31,7 +31,7 @@ def test_traffic_only_for_the_current_kernel_source(monkeypatch):
         pytest.skip("the counter summary predates the current stream-collide source")
     assert bench.traffic_from_profiles(0) == d["bytes_per_launch"]["0"]
     assert bench.traffic_from_profiles(1) == d["bytes_per_launch"]["1"]
-    assert bench.traffic_from_profiles(2) is None   # no counters taken for BF16
+    assert bench.traffic_from_profiles(2) == d["bytes_per_launch"]["2"]
     monkeypatch.setattr(bench, "kernel_hash", lambda: "0" * 16)
     assert bench.traffic_from_profiles(0) is None
 
@@ -40,7 +40,7 @@ def test_traffic_summary_is_consistent():
     with open(TRAFFIC) as fh:
         d = json.load(fh)
     ncell = 256 ** 3
-    for key, bpc in (("0", 152), ("1", 76)):
+    for key, bpc in (("0", 152), ("1", 76), ("2", 76)):
         e = d["by_storage"][key]
         assert e["algorithmic_bytes_per_launch"] == bpc * ncell
         total = e["read_bytes_per_launch"] + e["write_bytes_per_launch"]
