@@ -45,6 +45,27 @@ def test_activation_is_silu():
     np.testing.assert_allclose(y[:, 1:], 0.0, atol=0)
 
 
+def test_weight_layout_out_by_in():
+    """The flat layout is row-major out x in: one non-symmetric path
+    W1[3][7], W2[5][3], W3[9][5], W4[2][9] = 1 routes input 7 through hidden
+    units 3, 5 and 9 to output 2, so y_2 = silu(silu(silu(x_7))), the other
+    outputs are 0 and no other input matters.  A transposed (in x out) read
+    of any of the four matrices sends the path elsewhere."""
+    th = np.zeros(NP)
+    W1, b1, W2, b2, W3, b3, W4, b4 = split(th)
+    W1[3, 7] = W2[5, 3] = W3[9, 5] = W4[2, 9] = 1.0
+    silu = lambda z: z / (1.0 + np.exp(-z))
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(6, 12))
+    x[:, 7] = [-2.5, -0.3, 0.0, 0.4, 1.1, 3.0]
+    y = O.mlp_forward(th, x)
+    np.testing.assert_allclose(y[:, 2], silu(silu(silu(x[:, 7]))), rtol=1e-14, atol=1e-300)
+    np.testing.assert_array_equal(y[:, :2], 0.0)
+    x2 = rng.normal(size=(6, 12))
+    x2[:, 7] = x[:, 7]
+    np.testing.assert_array_equal(O.mlp_forward(th, x2), y)
+
+
 def test_loss_zero_at_fit():
     rng = np.random.default_rng(1)
     th = rng.normal(scale=0.2, size=NP)
