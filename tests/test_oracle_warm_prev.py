@@ -127,3 +127,34 @@ def test_warm_prev_carried_between_steps():
         _, pts_t = _rotor(3, PREV, du_prev=r_prev["du"])
         r_prev = O.step(p, f_man, pts_t, t)
     np.testing.assert_allclose(f_run, f_man, rtol=0, atol=1e-15)
+
+
+def test_warm_prev_winds_up_along_a_null_direction():
+    """Why the carried correction can diverge where a truncated sweep cannot.
+    Two coincident points (s = 1) with opposite velocities +-u: the spread of
+    any du with du_1 = -du_2 vanishes, so interpolation keeps returning the
+    untouched field (U0 = 0) and the deficit stays g = u_b in every sweep.
+    The plain N-sweep forcing ends with du = N u_b, every step afresh; warm
+    started from the previous du, the T-th forcing ends with
+    du = (N + (T - 1)(N - 1)) u_b, growing without bound while G stays 0 and
+    the residual never drops.  Surfaces of neighbouring bodies that cross
+    with different velocities have such directions (nearly: their spread is
+    small but not zero, so G grows too)."""
+    shape = (12, 12, 12)
+    p = O.params(shape, 0.7)
+    x = np.array([[5.3, 6.1, 4.7], [5.3, 6.1, 4.7]])
+    u = np.array([0.02, -0.01, 0.03])
+    ub = np.stack([u, -u])
+    s = np.ones(2)
+    U0 = np.zeros((3,) + shape[::-1])
+    N = 4
+    plain = O.ibm_ex(p, x, ub, s, U0, n_iter=N)
+    np.testing.assert_allclose(plain["du"], N * ub, rtol=1e-14)
+    du = None
+    for T in range(1, 7):
+        r = O.ibm_ex(p, x, ub, s, U0, n_iter=N, flags=PREV if du is not None else 0,
+                     du_prev=du)
+        du = r["du"]
+        np.testing.assert_allclose(du, (N + (T - 1) * (N - 1)) * ub, rtol=1e-13)
+        np.testing.assert_allclose(r["resid"], np.full(N, (ub ** 2).sum()), rtol=1e-13)
+        assert np.abs(r["G"]).max() < 1e-15
