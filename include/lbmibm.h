@@ -50,7 +50,7 @@ enum {
   LBM_ERR_HIP = -3,       /* a HIP runtime call or launch failed              */
   LBM_ERR_STATE = -4,     /* call not valid in the current state              */
   LBM_ERR_DOMAIN = -5,    /* a point's kernel support leaves a walled box     */
-  LBM_ERR_NONFINITE = -6  /* non-finite mass or momentum detected             */
+  LBM_ERR_NONFINITE = -6  /* non-finite state detected (see lbm_set_check)     */
 };
 
 /* Boundary condition per axis (both faces).  Bounce-back is the halfway
@@ -260,6 +260,20 @@ lbm_status ibm_force_iterate(lbm_ctx* ctx, ibm_stats* stats);
 /* Advances n_steps >= 0 time steps: per step, the forcing (if a surface is
  * set) followed by the fused stream-collide (§2 steps 1, 3-6). */
 lbm_status lbm_step(lbm_ctx* ctx, int32_t n_steps);
+
+/* Failure detection (not in the paper): the stream-collide raises a sticky
+ * device status word when a workgroup's FP64 partial of the mass or
+ * momentum sums is not finite (a NaN or infinite population, §2 eq. (1)),
+ * and a forcing sweep raises another when a value it spreads (§3, Algorithm
+ * 2) is not finite or exceeds 4096 in magnitude, beyond which the spread's
+ * fixed-point accumulation cannot represent it.  every > 0: lbm_step
+ * synchronises after every `every` steps, and ibm_force_iterate after each
+ * forcing, reads the words and returns LBM_ERR_NONFINITE if one is raised
+ * (lbm_last_error names which and the step reached).  The steps before the
+ * check have run and are not undone; the words stay raised until the next
+ * lbm_set_check.  every = 0 (the default) turns the check off; the words are
+ * raised either way.  Each call clears them.  LBM_ERR_ARG for every < 0. */
+lbm_status lbm_set_check(lbm_ctx* ctx, int32_t every);
 
 /* Reads fields selected by mask into caller memory (see LBM_F_*). */
 lbm_status lbm_read_fields(lbm_ctx* ctx, uint32_t mask, const lbm_fields* dst);

@@ -650,12 +650,23 @@ __device__ __forceinline__ void peskin4(float r, float w[4]) {
 constexpr float FIX_ONE = 1073741824.0f;  // 2^30
 
 // A point's share of the box bound in units of 2^-32, rounded up, capped at
-// 2^12 (far beyond any lattice velocity or correction; a NaN also gives the
-// cap): with up to 2^20 points per tile the 64-bit sum cannot overflow, and
-// integer addition makes the bound independent of the order of the tile's
-// points, which the binning does not fix.
+// SPREAD_CAP = 2^12 (far beyond any sound lattice velocity or correction):
+// with up to 2^20 points per tile the 64-bit sum cannot overflow, and integer
+// addition makes the bound independent of the order of the tile's points,
+// which the binning does not fix.  The box bound B, and with it the promise
+// that no fixed-point sum overflows, holds only while every point's
+// max_c |v_c| is finite and at most the cap.  A larger or non-finite value
+// (a diverging flow) would saturate the conversions, let the packed x sum
+// carry into the y half and replace NaN by a finite number; spread_guard
+// raises the sticky status word bad[1] for it instead of hiding it, and the
+// forcing's results are then not valid.
+constexpr float SPREAD_CAP = 4096.0f;
 __device__ __forceinline__ unsigned long long bound_units(float m) {
-  return (unsigned long long)ceilf(fminf(m, 4096.0f) * 4294967296.0f);
+  return (unsigned long long)ceilf(fminf(m, SPREAD_CAP) * 4294967296.0f);
+}
+// (each component on its own: fmaxf would drop a NaN operand)
+__device__ __forceinline__ void spread_guard(float a, float b, float c, uint32_t* __restrict__ bad) {
+  if (!(fabsf(a) <= SPREAD_CAP && fabsf(b) <= SPREAD_CAP && fabsf(c) <= SPREAD_CAP)) bad[1] = 1u;
 }
 enum : int {
   SW_INTERP = 1,
@@ -676,7 +687,8 @@ __global__ __launch_bounds__(WG, 8) void k_sweep_tiles(
     const float4* __restrict__ sp_frac, const float4* __restrict__ sp_ub,
     float4* __restrict__ sp_g, float4* __restrict__ sp_du, const float* __restrict__ U,
     float* __restrict__ boxbuf, PointGeom pg, int mode, double* __restrict__ part_res,
-    const uint32_t* __restrict__ gate, float4* __restrict__ g_orig, float4* __restrict__ du_prev) {
+    const uint32_t* __restrict__ gate, float4* __restrict__ g_orig, float4* __restrict__ du_prev,
+    uint32_t* __restrict__ bad) {
   // U of the box during the interpolation, then (same storage) the integer
   // accumulators of the spread: x and y packed in 64 bits, z in 32 bits
   __shared__ __align__(16) float sU[3][BOX3];
@@ -727,6 +739,7 @@ __global__ __launch_bounds__(WG, 8) void k_sweep_tiles(
         v = spread_du ? sp_du[k] : sp_g[k];
       }
       const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
+      spread_guard(vs * v.x, vs * v.y, vs * v.z, bad);
       bsum += bound_units(vs * fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z))));
     }
     for (uint32_t i = threadIdx.x; interp && i < P; i += WG) {
@@ -770,6 +783,7 @@ __global__ __launch_bounds__(WG, 8) void k_sweep_tiles(
       const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
       const float v0 = spread_du ? du.x : vs * g0, v1 = spread_du ? du.y : vs * g1,
                   v2 = spread_du ? du.z : vs * g2;
+      if (spread) spread_guard(v0, v1, v2, bad);
       bsum += bound_units(fmaxf(fabsf(v0), fmaxf(fabsf(v1), fabsf(v2))));
     }
     if (!spread) continue;
@@ -1255,7 +1269,8 @@ hipError_t launch_forcing(lbm_ctx* c) {
   auto sweep = [&](int it, int mode, const uint32_t* gate, float4* g_orig) {
     k_sweep_tiles<<<lg, WG, 0, st>>>(c->own_tiles, c->meta, c->start_own, c->sp_base, c->sp_frac,
                                      c->sp_ub, c->sp_g, c->sp_du, c->U, c->boxbuf, pg, mode | uw,
-                                     c->pt_partials + (2 + it) * rs, gate, g_orig, c->du_prev);
+                                     c->pt_partials + (2 + it) * rs, gate, g_orig, c->du_prev,
+                                     c->status);
     return hipGetLastError();
   };
   auto merge = [&](bool final_, const uint32_t* gate) {

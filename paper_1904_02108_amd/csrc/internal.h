@@ -84,6 +84,7 @@ struct lbm_ctx {
   double* pt_partials = nullptr;    // [max_iter + 2][part_row]
   int64_t part_row = 0;
   double* small = nullptr;          // [256] reduced results
+  uint32_t* status = nullptr;       // [4] sticky: [0] sums not finite, [1] spread out of range
 
   // state
   int64_t npts = 0;
@@ -98,6 +99,8 @@ struct lbm_ctx {
   int64_t g_valid_step = -1;
   bool g_prescribed = false;
   bool have_sums = false;  // a stream-collide has written the sum partials
+  int32_t check_every = 0;  // lbm_set_check interval (0 = off)
+  int64_t check_since = 0;  // steps since the last check
 
   // lengths of the owner / touched tile lists of a previous forcing, copied
   // asynchronously to pinned host memory, to size the tile grids

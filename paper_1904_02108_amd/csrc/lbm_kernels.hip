@@ -72,9 +72,12 @@ __device__ __forceinline__ void collide_cell(const LatticeGeom& g, float f[Q], f
   }
 }
 
-// The workgroup's FP64 sums of part[0..3] into partials[blk].
+// The workgroup's FP64 sums of part[0..3] into partials[blk]; a sum that is
+// not finite (a NaN or infinite population, or an overflowing moment) also
+// sets the sticky status word bad[0] (the non-finite check of lbm_step).
 __device__ __forceinline__ void store_partials(double part[4], int tid, int64_t blk,
-                                               double* __restrict__ partials) {
+                                               double* __restrict__ partials,
+                                               uint32_t* __restrict__ bad) {
   __shared__ double red[4][LBM_BLOCK / 64];
   const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
@@ -88,6 +91,7 @@ __device__ __forceinline__ void store_partials(double part[4], int tid, int64_t 
 #pragma unroll
     for (int w = 0; w < LBM_BLOCK / 64; ++w) s += red[tid][w];
     partials[blk * 4 + tid] = s;
+    if (!(fabs(s) <= 1.7976931348623157e308)) bad[0] = 1u;
   }
 }
 
@@ -99,7 +103,7 @@ template <int S, int FORCING, bool FLAT>
 __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
     const typename Store<S>::T* __restrict__ src, typename Store<S>::T* __restrict__ dst,
     const LatticeGeom g, const float* __restrict__ G, const uint8_t* __restrict__ flags,
-    double* __restrict__ partials) {
+    double* __restrict__ partials, uint32_t* __restrict__ bad) {
   // 3-D launch: blockDim.x spans x, blockDim.y spans y, one z-plane per block
   // row; each workgroup takes LBM_SC_ROWS consecutive block rows along y.
   // FLAT (x extents that are not a multiple of the wavefront): 256 threads
@@ -138,7 +142,7 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
   }
   const int64_t blk = (int64_t)blockIdx.x +
                       (int64_t)gridDim.x * ((int64_t)blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
-  store_partials(part, threadIdx.x + blockDim.x * threadIdx.y, blk, partials);
+  store_partials(part, threadIdx.x + blockDim.x * threadIdx.y, blk, partials, bad);
 }
 
 // Two cells per thread (16-bit storage, even x extents): the pair (x0, x0 + 1)
@@ -148,7 +152,7 @@ template <int S, int FORCING>
 __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide_pairs(
     const typename Store<S>::T* __restrict__ src, typename Store<S>::T* __restrict__ dst,
     const LatticeGeom g, const float* __restrict__ G, const uint8_t* __restrict__ flags,
-    double* __restrict__ partials) {
+    double* __restrict__ partials, uint32_t* __restrict__ bad) {
   const int px = g.nx >> 1;
   const int pf = blockIdx.x * LBM_BLOCK + threadIdx.x;
   const int y = pf / px;
@@ -189,7 +193,7 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide_pairs(
       Store<S>::store2_nt(dst + (int64_t)i * g.stride + cell, f0[i], f1[i]);
   }
   store_partials(part, threadIdx.x, (int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.z,
-                 partials);
+                 partials, bad);
 }
 
 // Loads post-stream populations f (full values, float or double) as the
@@ -379,10 +383,10 @@ hipError_t stream_collide_s(lbm_ctx* c) {
     if (stream_collide_pairs(c)) {
       if (c->p.forcing == LBM_FORCE_SHIFT)
         k_stream_collide_pairs<S, LBM_FORCE_SHIFT><<<grid, block, 0, c->stream>>>(
-            src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+            src, dst, c->geom, c->G, c->bflag, c->sum_partials, c->status);
       else
         k_stream_collide_pairs<S, LBM_FORCE_GUO><<<grid, block, 0, c->stream>>>(
-            src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+            src, dst, c->geom, c->G, c->bflag, c->sum_partials, c->status);
       return hipGetLastError();
     }
   }
@@ -390,17 +394,17 @@ hipError_t stream_collide_s(lbm_ctx* c) {
   if (c->p.forcing == LBM_FORCE_SHIFT) {
     if (flat)
       k_stream_collide<S, LBM_FORCE_SHIFT, true><<<grid, block, 0, c->stream>>>(
-          src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+          src, dst, c->geom, c->G, c->bflag, c->sum_partials, c->status);
     else
       k_stream_collide<S, LBM_FORCE_SHIFT, false><<<grid, block, 0, c->stream>>>(
-          src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+          src, dst, c->geom, c->G, c->bflag, c->sum_partials, c->status);
   } else {
     if (flat)
       k_stream_collide<S, LBM_FORCE_GUO, true><<<grid, block, 0, c->stream>>>(
-          src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+          src, dst, c->geom, c->G, c->bflag, c->sum_partials, c->status);
     else
       k_stream_collide<S, LBM_FORCE_GUO, false><<<grid, block, 0, c->stream>>>(
-          src, dst, c->geom, c->G, c->bflag, c->sum_partials);
+          src, dst, c->geom, c->G, c->bflag, c->sum_partials, c->status);
   }
   return hipGetLastError();
 }

@@ -35,7 +35,7 @@ struct Plan {
   int64_t nblocks4, nbflag_words;
   int fblk[3];
   // scratch
-  size_t o_sum_part, o_pt_part, o_small, o_ctl, o_thr;
+  size_t o_sum_part, o_pt_part, o_small, o_ctl, o_thr, o_status;
   int64_t part_row;
   int64_t n_cell_blocks, n_pt_blocks;
   int64_t ncell, ntiles;
@@ -186,6 +186,7 @@ void make_plan(const lbm_params* p, Plan& pl) {
   pl.o_small = sc.take(256 * sizeof(double));
   pl.o_ctl = sc.take(4 * sizeof(uint32_t));
   pl.o_thr = sc.take(sizeof(double));
+  pl.o_status = sc.take(4 * sizeof(uint32_t));
   pl.size[LBM_BUF_SCRATCH] = sc.at;
 }
 
@@ -287,6 +288,22 @@ lbm_status read_stats(lbm_ctx* c, ibm_stats* stats) {
   return LBM_OK;
 }
 
+// The non-finite check: reads the sticky status words (synchronises) and
+// turns a raised word into LBM_ERR_NONFINITE naming where it was raised.
+lbm_status check_status(lbm_ctx* c, const char* where) {
+  uint32_t* h = c->meta_host + 4;  // pinned words 4..7
+  HIP_TRY(c, hipMemcpyAsync(h, c->status, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->check_since = 0;
+  if (!h[0] && !h[1]) return LBM_OK;
+  std::string m = std::string("non-finite state detected ") + where + " (step " +
+                  std::to_string(c->step) + ", checked every " +
+                  std::to_string(c->check_every) + " step(s)):";
+  if (h[0]) m += " mass/momentum sums not finite;";
+  if (h[1]) m += " a forcing spread value not finite or beyond 4096;";
+  return fail(c, LBM_ERR_NONFINITE, m);
+}
+
 }  // namespace
 
 extern "C" {
@@ -385,6 +402,7 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->small = (double*)(S + pl.o_small);
   c->ctl = (uint32_t*)(S + pl.o_ctl);
   c->resid_thr = (double*)(S + pl.o_thr);
+  c->status = (uint32_t*)(S + pl.o_status);
 
   hipError_t e = hipSuccess;
   const int64_t ntpad = (c->ntiles + 16383) / 16384 * 16384;
@@ -392,13 +410,14 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   if (e == hipSuccess) e = launch_fill_u32(c, c->cnt_touch, 0u, ntpad);
   if (e == hipSuccess) e = launch_fill_u32(c, c->meta, 0u, 4);
   if (e == hipSuccess) e = launch_fill_u32(c, c->ctl, 0u, 4);
+  if (e == hipSuccess) e = launch_fill_u32(c, c->status, 0u, 4);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->bflag, 0u, c->nbflag_words);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->U, 0u, pl.o_G / sizeof(float));
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->G, 0u, 3 * c->ncell);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->sum_partials, 0u, 8 * c->n_cell_blocks);
   if (e == hipSuccess) e = launch_init_equilibrium(c);
   if (e == hipSuccess)
-    e = hipHostMalloc((void**)&c->meta_host, 4 * sizeof(uint32_t), hipHostMallocMapped);
+    e = hipHostMalloc((void**)&c->meta_host, 8 * sizeof(uint32_t), hipHostMallocMapped);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->meta_host_dev, c->meta_host, 0);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->meta_event, hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -558,7 +577,21 @@ lbm_status ibm_force_iterate(lbm_ctx* c, ibm_stats* stats) {
   if (c->npts == 0) return fail(c, LBM_ERR_STATE, "no Lagrangian points set");
   lbm_status st = do_forcing(c);
   if (st != LBM_OK) return st;
+  if (c->check_every > 0) {
+    st = check_status(c, "after the forcing");
+    if (st != LBM_OK) return st;
+  }
   return stats ? read_stats(c, stats) : LBM_OK;
+}
+
+lbm_status lbm_set_check(lbm_ctx* c, int32_t every) {
+  if (!c) return LBM_ERR_ARG;
+  if (every < 0) return fail(c, LBM_ERR_ARG, "every must be >= 0");
+  hipError_t e = launch_fill_u32(c, c->status, 0u, 4);
+  if (e != hipSuccess) return hip_fail(c, e, "clear status words");
+  c->check_every = every;
+  c->check_since = 0;
+  return LBM_OK;
 }
 
 lbm_status ibm_last_stats(lbm_ctx* c, ibm_stats* stats) {
@@ -608,6 +641,10 @@ lbm_status lbm_step(lbm_ctx* c, int32_t n_steps) {
     if (c->ev_used > 4000) ev_collect(c);
     c->have_sums = true;
     c->step += 1;
+    if (c->check_every > 0 && ++c->check_since >= c->check_every) {
+      lbm_status st = check_status(c, "after the stream-collide");
+      if (st != LBM_OK) return st;
+    }
   }
   return LBM_OK;
 }

@@ -42,7 +42,7 @@ ABI_FUNCTIONS = ("lbm_buffer_sizes", "lbm_create", "lbm_destroy", "lbm_last_erro
                  "ibm_set_points", "ibm_force_iterate", "lbm_step", "lbm_read_fields",
                  "lbm_write_fields", "lbm_set_timing", "lbm_get_timing", "ibm_set_mlp",
                  "ibm_log_pairs", "ibm_last_stats", "mlp_workspace_size", "mlp_forward",
-                 "mlp_loss_grad", "mlp_train")
+                 "mlp_loss_grad", "mlp_train", "lbm_set_check")
 
 
 class lbm_params(ct.Structure):
@@ -87,6 +87,7 @@ _lib.lbm_step.argtypes = [_C, ct.c_int32]
 _lib.lbm_read_fields.argtypes = [_C, ct.c_uint32, ct.POINTER(lbm_fields)]
 _lib.lbm_write_fields.argtypes = [_C, ct.c_uint32, ct.POINTER(lbm_fields)]
 _lib.lbm_set_timing.argtypes = [_C, ct.c_int32]
+_lib.lbm_set_check.argtypes = [_C, ct.c_int32]
 _lib.lbm_get_timing.argtypes = [_C, ct.POINTER(ct.c_double)]
 _lib.ibm_set_mlp.argtypes = [_C, ct.c_void_p]
 _lib.ibm_log_pairs.argtypes = [_C, ct.c_void_p, ct.c_void_p]
@@ -101,7 +102,8 @@ _lib.mlp_train.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.POINTER(ct.
                            ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32,
                            ct.c_double, ct.c_void_p, ct.c_void_p, ct.c_void_p]
 for _f in ("lbm_buffer_sizes", "lbm_create", "ibm_set_points", "ibm_force_iterate", "lbm_step",
-           "lbm_read_fields", "lbm_write_fields", "lbm_set_timing", "lbm_get_timing"):
+           "lbm_read_fields", "lbm_write_fields", "lbm_set_timing", "lbm_get_timing",
+           "lbm_set_check"):
     getattr(_lib, _f).restype = ct.c_int32
 
 
@@ -249,6 +251,10 @@ def lbm_set_timing(ctx, enable):
     _check(_lib.lbm_set_timing(ctx, int(enable)), ctx)
 
 
+def lbm_set_check(ctx, every):
+    _check(_lib.lbm_set_check(ctx, int(every)), ctx)
+
+
 def lbm_get_timing(ctx):
     out = (ct.c_double * 4)()
     _check(_lib.lbm_get_timing(ctx, out), ctx)
@@ -296,6 +302,9 @@ class Simulation:
     def set_points(self, rest, area, body_off, bodies, n_iter=5, flags=0, eps=0.0):
         ibm_set_points(self.ctx, rest, area, body_off, bodies, n_iter, flags, eps)
         self.n_points = int(np.asarray(rest).reshape(-1, 3).shape[0])
+
+    def set_check(self, every=1):
+        lbm_set_check(self.ctx, every)
 
     def force_iterate(self, stats=False):
         return ibm_force_iterate(self.ctx, stats)

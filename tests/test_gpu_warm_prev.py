@@ -60,6 +60,36 @@ def test_warm_prev_parity(L, n_iter, unweighted):
     print("sum s|g|^2 after sweep 1: warm", r["resid"][1], "plain", plain["resid"][1], flush=True)
 
 
+def test_warm_prev_parity_multi_tile(L):
+    """c1_dense (24 950 points at h 0.41, walls on y and z): owner tiles of
+    more than 256 points, which the sweep deals out in strided passes and
+    launches first, and a correction carried over 10 steps.  After 10
+    warm-started steps of 4 sweeps the corrections, then the 11th step's
+    correction, force and sweep residuals match the oracle."""
+    wl = W.config("c1_dense")
+    flags = O.IBM_WARM_PREV
+    n_iter = 4
+    x, _ = O.kinematics(wl.rest, wl.body_off, wl.bodies, 10)
+    t = np.floor(x).astype(np.int64) // 8
+    _, counts = np.unique(t[:, 0] + 16 * (t[:, 1] + 16 * t[:, 2]), return_counts=True)
+    print("c1_dense: points per owner tile at step 10, max", counts.max(), flush=True)
+    assert counts.max() > 256
+    sim, p, _ = sim_for_workload(L, wl)
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, n_iter, flags)
+    sim.step(10)
+    f = O.init_equilibrium(p)
+    r9 = _oracle_steps(p, f, wl, n_iter, flags, 0, 10)
+    e9 = rel_linf(to_np(sim.read("pt_du")["pt_du"]), r9["du"])
+    st = sim.force_iterate(stats=True)
+    r = _oracle_steps(p, f, wl, n_iter, flags, 10, 11, du_prev=r9["du"])
+    out = sim.read("force", "pt_du")
+    e_du, e_G = rel_linf(to_np(out["pt_du"]), r["du"]), rel_linf(to_np(out["force"]), r["G"])
+    print("c1_dense warm-prev: du after 10 steps", e9, "step 10: du", e_du, "G", e_G, flush=True)
+    assert e9 < 1e-5 and e_du < 1e-5 and e_G < 1e-5
+    assert st["n_iter"] == r["n_sweeps"] == n_iter
+    np.testing.assert_allclose(st["resid"], r["resid"], rtol=1e-4)
+
+
 def test_warm_prev_residual_stop(L):
     """C0, 7 steps with the residual stop at eps = 0.3: every step stops at
     the oracle's sweep (7, 4, 1, 3, 3, 2, 2 sweeps; step 2 stops at its first
