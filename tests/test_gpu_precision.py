@@ -152,3 +152,52 @@ def test_c1_500_steps_by_storage(L, storage):
           "oracle drift", abs(float(ref["mass"]) - mass0) / mass0, flush=True)
     assert e["vel"] < tol_vel and e["force"] < tol_force and e["du"] < tol_du
     assert drift < 1e-5
+
+
+# Error model of the 16-bit storage (arithmetic in FP32; the offsets f - t_i
+# rounded to nearest even once per step): a step perturbs every stored
+# offset by at most u = 2^-11 (FP16) or 2^-8 (BF16) of its size.  The
+# roundings are unbiased and independent from step to step, so in a flow
+# that does not amplify perturbations they accumulate as a random walk: after
+# n steps a field is off by about sqrt(n) u of its largest value, which is
+# the bound.  FP32 storage is held to the 1e-4 of the FP32 path.
+C2_200_TOL = {0: dict(vel=1e-4, rho=1e-4, force=1e-4, du=1e-4),
+              1: {k: 200 ** 0.5 * 2.0 ** -11 for k in ("vel", "rho", "force", "du")},
+              2: {k: 200 ** 0.5 * 2.0 ** -8 for k in ("vel", "rho", "force", "du")}}
+
+GOLDEN_C2 = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden",
+                                       "c2_dense_half_200_steps.npz")
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_c2_dense_half_200_steps_by_storage(L, storage):
+    """C3 on the dense 64-propeller geometry (256^3, 1.6M points, rates
+    halved so that the flow stays sound): 200 steps with FP32, FP16 and BF16
+    storage against the FP64 oracle's run stored by
+    tests/golden/make_c2_half.py (density and velocity at 8192 sampled
+    cells, G there, du of 33 142 points, mass).  Errors are relative to the
+    largest oracle value of each sample."""
+    if not __import__("os").path.exists(GOLDEN_C2):
+        pytest.skip("golden file not generated")
+    ref = np.load(GOLDEN_C2)
+    wl = W.config("c2_dense_half")
+    sim = make_sim(L, wl.shape, wl.tau, bc=wl.bc, storage=storage, forcing=wl.forcing,
+                   max_points=wl.n_points, max_iter=wl.n_iter)
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter)
+    print("c2_dense_half 200 steps, storage", storage, flush=True)
+    sim.step(int(ref["steps"]))
+    out = sim.read("rho", "vel", "force", "pt_du", "sums")
+    z, y, x = ref["cells"].T.astype(np.int64)
+    e = dict(vel=rel_linf(to_np(out["vel"])[:, z, y, x], ref["vel"]),
+             rho=rel_linf(to_np(out["rho"])[z, y, x] - 1, ref["rho_minus_1"]),
+             force=rel_linf(to_np(out["force"])[:, z, y, x], ref["force"]),
+             du=rel_linf(to_np(out["pt_du"])[ref["points"]], ref["du"]))
+    mass0 = float(np.prod(wl.shape))
+    drift = abs(float(to_np(out["sums"])[0]) - mass0) / mass0
+    sim.close()
+    print("c2_dense_half 200 steps, storage", storage, e, "mass drift", drift,
+          "oracle drift", abs(float(ref["sums"][0]) - mass0) / mass0, flush=True)
+    tol = C2_200_TOL[storage]
+    for k in ("vel", "rho", "force", "du"):
+        assert e[k] < tol[k], (k, e[k], tol[k])
+    assert drift < 1e-5
