@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbmibm.so")
-SOURCES = ["lbm_kernels.hip", "ibm_kernels.hip", "mlp_kernels.hip", "lbmibm.cpp"]
+SOURCES = ["lbm_kernels.hip", "ibm_kernels.hip", "mlp_kernels.hip", "lbmibm.cpp", "host_plan.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc")
 ARCH = "gfx950"
 

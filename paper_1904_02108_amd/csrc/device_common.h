@@ -6,12 +6,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "layout.h"
 #include "lbmibm.h"
 
 namespace lbmd {
 
 // D3Q19 velocity set in the export order documented in lbmibm.h.
-constexpr int Q = 19;
 constexpr int EX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
 constexpr int EY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
 constexpr int EZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
@@ -114,10 +114,6 @@ struct LatticeGeom {
   int fblk_x, fblk_y;  // grid of 4^3 force blocks (x, y extent) for flag lookups
 };
 
-constexpr int TILE = 8;       // edge of the cubic tiles the forcing works on
-constexpr int TILE_SHIFT = 3;
-constexpr int FBLK = 4;       // edge of the cubic blocks flagged as touched by a support
-constexpr int FBLK_SHIFT = 2;
 
 // Pull-stream gather of the 19 post-stream offsets at cell (x, y, z) from the
 // post-collision lattice `lat` (eq. (4) read backwards: f_i(X) = f*_i(X - e_i);

@@ -640,14 +640,35 @@ __device__ __forceinline__ void peskin4(float r, float w[4]) {
 // order of the atomics and of the points.  Components x and y share one
 // 64-bit atomic (x sign-extended in the low word, y in the high word: the
 // 64-bit sum is exactly sum_y 2^32 + sum_x, and |sum_x| < 2^31 recovers
-// both), z has its own 32-bit one.  The box is stored as FP32 in the tile's
-// slot of boxbuf.
+// both), z has its own 32-bit one.  The box is stored as these integer sums
+// with its unit in the tile's slot of boxbuf (box_slot layout); the merge
+// converts them.
 //
 // Each workgroup takes a stride of the owner-tile list (contiguous per XCD;
 // one tile per workgroup unless the list is longer than the grid).  A
 // nonzero *gate (the forcing has converged) makes the launch a no-op.  Each
 // workgroup writes its FP64 partial of s |g|^2 when interpolating.
 constexpr float FIX_ONE = 1073741824.0f;  // 2^30
+
+// A stored spread box in its BOX_SLOT_BYTES slot of boxbuf: the packed x/y
+// sums of the 11^3 cells (64-bit, as accumulated), then the z sums (32-bit),
+// and the box's fixed-point unit B / 2^30 (FP32) in the slot's last word.
+constexpr int BOX_Z_OFF = BOX3 * 8;
+constexpr int BOX_UNIT_OFF = BOX_SLOT_BYTES - 4;
+static_assert(BOX_Z_OFF + BOX3 * 4 <= BOX_UNIT_OFF, "box slot too small");
+
+// Adds cell bi of a stored box to (s0, s1, s2): each sum times the unit.
+__device__ __forceinline__ void add_box_cell(const unsigned char* __restrict__ slot, int bi,
+                                             float& s0, float& s1, float& s2) {
+  const float unit = *reinterpret_cast<const float*>(slot + BOX_UNIT_OFF);
+  const unsigned long long xy = reinterpret_cast<const unsigned long long*>(slot)[bi];
+  const int sx = (int)(uint32_t)xy;
+  const int sy = (int)(uint32_t)((xy - (unsigned long long)(long long)sx) >> 32);
+  const int sz = reinterpret_cast<const int*>(slot + BOX_Z_OFF)[bi];
+  s0 += (float)sx * unit;
+  s1 += (float)sy * unit;
+  s2 += (float)sz * unit;
+}
 
 // A point's share of the box bound in units of 2^-32, rounded up, capped at
 // SPREAD_CAP = 2^12 (far beyond any sound lattice velocity or correction):
@@ -686,7 +707,7 @@ __global__ __launch_bounds__(WG, 8) void k_sweep_tiles(
     const uint32_t* __restrict__ start_own, const int4* __restrict__ sp_base,
     const float4* __restrict__ sp_frac, const float4* __restrict__ sp_ub,
     float4* __restrict__ sp_g, float4* __restrict__ sp_du, const float* __restrict__ U,
-    float* __restrict__ boxbuf, PointGeom pg, int mode, double* __restrict__ part_res,
+    unsigned char* __restrict__ boxbuf, PointGeom pg, int mode, double* __restrict__ part_res,
     const uint32_t* __restrict__ gate, float4* __restrict__ g_orig, float4* __restrict__ du_prev,
     uint32_t* __restrict__ bad) {
   // U of the box during the interpolation, then (same storage) the integer
@@ -696,6 +717,10 @@ __global__ __launch_bounds__(WG, 8) void k_sweep_tiles(
   int* accz = reinterpret_cast<int*>(&sU[0][0]) + 2 * BOX3;
   __shared__ unsigned long long bred[WG / 64];
   __shared__ double dred[WG / 64];
+  // index of the box's cells in the tile-major U: a sum of one term per
+  // axis (the wrapped coordinate's tile times the tile stride plus its
+  // position in the tile), tabulated once per tile
+  __shared__ int64_t uoff[3][BOX];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (gate && *gate) return;  // the forcing has already converged
   const bool interp = mode & SW_INTERP;
@@ -712,16 +737,23 @@ __global__ __launch_bounds__(WG, 8) void k_sweep_tiles(
     int o[3];
     tile_origin(pg, t, o);
     __syncthreads();  // the previous tile's box has been stored
+    if (interp && threadIdx.x < 3 * BOX) {
+      const int a = threadIdx.x / BOX, b = threadIdx.x - a * BOX;
+      const int v = tap_coord(o[a] - 1 + b, pg.n[a], pg.bc[a]);
+      const int64_t tstride = a == 0 ? 1 : (a == 1 ? (int64_t)pg.tiles[0]
+                                                   : (int64_t)pg.tiles[0] * pg.tiles[1]);
+      uoff[a][b] = (int64_t)(v >> TILE_SHIFT) * tstride * (3 * TILE3) +
+                   ((v & (TILE - 1)) << (TILE_SHIFT * a));
+    }
+    __syncthreads();
 #pragma unroll 2
     for (int i = threadIdx.x; interp && i < BOX3; i += WG) {
-      const int bx = i % BOX, by = (i / BOX) % BOX, bz = i / (BOX * BOX);
-      const int cx = tap_coord(o[0] - 1 + bx, pg.n[0], pg.bc[0]);
-      const int cy = tap_coord(o[1] - 1 + by, pg.n[1], pg.bc[1]);
-      const int cz = tap_coord(o[2] - 1 + bz, pg.n[2], pg.bc[2]);
-      const int64_t c = u_index_cell(pg, cx, cy, cz, 0);
-      sU[0][i] = U[c];
-      sU[1][i] = U[c + TILE3];
-      sU[2][i] = U[c + 2 * TILE3];
+      const int bz = i / (BOX * BOX), r = i - bz * (BOX * BOX);
+      const int by = r / BOX, bx = r - by * BOX;
+      const float* u = U + (uoff[0][bx] + uoff[1][by] + uoff[2][bz]);
+      sU[0][i] = u[0];
+      sU[1][i] = u[TILE3];
+      sU[2][i] = u[2 * TILE3];
     }
     __syncthreads();
     const uint32_t p0 = start_own[t], p1 = start_own[t + 1];
@@ -836,6 +868,15 @@ __global__ __launch_bounds__(WG, 8) void k_sweep_tiles(
       peskin4(fr.x, wx);
       peskin4(fr.y, wy);
       peskin4(fr.z, wz);
+      // the x weights times the vector, once per point: a tap's value is
+      // then one product per component, wz wy (wx v)
+      float ax[4], ay[4], az[4];
+#pragma unroll
+      for (int cx = 0; cx < 4; ++cx) {
+        ax[cx] = wx[cx] * v0;
+        ay[cx] = wx[cx] * v1;
+        az[cx] = wx[cx] * v2;
+      }
       const int l0 = (b.x - o[0]) + BOX * ((b.y - o[1]) + BOX * (b.z - o[2]));
 #pragma unroll 1
       for (int jz = 0; jz < 4; ++jz) {
@@ -847,26 +888,24 @@ __global__ __launch_bounds__(WG, 8) void k_sweep_tiles(
           const int row = l0 + BOX * (cy + BOX * cz);
 #pragma unroll
           for (int cx = 0; cx < 4; ++cx) {
-            const float w = wyz * wx[cx];
-            const long long ix = __float2int_rn(w * v0), iy = __float2int_rn(w * v1);
-            atomicAdd(&accxy[row + cx],
-                      (unsigned long long)ix + ((unsigned long long)iy << 32));
-            atomicAdd(&accz[row + cx], __float2int_rn(w * v2));
+            const int ix = __float2int_rn(wyz * ax[cx]), iy = __float2int_rn(wyz * ay[cx]);
+            // x sign-extended in the low word, y added into the high word
+            atomicAdd(&accxy[row + cx], (unsigned long long)(long long)ix +
+                                            ((unsigned long long)(uint32_t)iy << 32));
+            atomicAdd(&accz[row + cx], __float2int_rn(wyz * az[cx]));
           }
         }
       }
     }
     __syncthreads();
-    const float unit = B / FIX_ONE;
-    float* box = boxbuf + (int64_t)e * 3 * BOX3;
+    unsigned char* slot = boxbuf + (int64_t)e * BOX_SLOT_BYTES;
+    unsigned long long* sxy = reinterpret_cast<unsigned long long*>(slot);
+    int* sz = reinterpret_cast<int*>(slot + BOX_Z_OFF);
     for (int i = threadIdx.x; i < BOX3; i += WG) {
-      const unsigned long long sxy = accxy[i];
-      const int sx = (int)(uint32_t)sxy;
-      const int sy = (int)(uint32_t)((sxy - (unsigned long long)(long long)sx) >> 32);
-      box[i] = (float)sx * unit;
-      box[BOX3 + i] = (float)sy * unit;
-      box[2 * BOX3 + i] = (float)accz[i] * unit;
+      sxy[i] = accxy[i];
+      sz[i] = accz[i];
     }
+    if (threadIdx.x == 0) *reinterpret_cast<float*>(slot + BOX_UNIT_OFF) = B / FIX_ONE;
   }
   if (interp) {  // this workgroup's residual partial (zero if it had no tile)
     const double rv = wave_sum(res);
@@ -908,7 +947,7 @@ __device__ __forceinline__ int covering(int x, int n, int bc, int ntiles_axis, i
 constexpr int MERGE_WG = 256;
 __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
     const uint32_t* __restrict__ touch_tiles, const uint32_t* __restrict__ meta,
-    const int32_t* __restrict__ own_slot, const float* __restrict__ boxbuf,
+    const int32_t* __restrict__ own_slot, const unsigned char* __restrict__ boxbuf,
     const uint8_t* __restrict__ bflag, float* __restrict__ target, PointGeom pg, int mode,
     const uint32_t* __restrict__ gate) {
   __shared__ int16_t ct[3][TILE][MAXCOV], cb[3][TILE][MAXCOV];
@@ -983,10 +1022,7 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
               const int32_t slot = nslot[(nd[0][jx] + 1) + 3 * (nd[1][jy] + 1) + 9 * (nd[2][jz] + 1)];
               if (slot < 0) continue;
               const int bi = nb[0][jx] + BOX * (nb[1][jy] + BOX * nb[2][jz]);
-              const float* box = boxbuf + (int64_t)slot * 3 * BOX3;
-              s0 += box[bi];
-              s1 += box[BOX3 + bi];
-              s2 += box[2 * BOX3 + bi];
+              add_box_cell(boxbuf + (int64_t)slot * BOX_SLOT_BYTES, bi, s0, s1, s2);
             }
       } else {
         const int nx_ = cn[0][lx], ny_ = cn[1][ly], nz_ = cn[2][lz];
@@ -997,10 +1033,7 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
               const int32_t slot = own_slot[A];
               if (slot < 0) continue;
               const int bi = cb[0][lx][jx] + BOX * (cb[1][ly][jy] + BOX * cb[2][lz][jz]);
-              const float* box = boxbuf + (int64_t)slot * 3 * BOX3;
-              s0 += box[bi];
-              s1 += box[BOX3 + bi];
-              s2 += box[2 * BOX3 + bi];
+              add_box_cell(boxbuf + (int64_t)slot * BOX_SLOT_BYTES, bi, s0, s1, s2);
             }
       }
       if (mode == 2) {  // G, in the lattice layout read by the stream-collide
@@ -1268,13 +1301,15 @@ hipError_t launch_forcing(lbm_ctx* c) {
   }
   auto sweep = [&](int it, int mode, const uint32_t* gate, float4* g_orig) {
     k_sweep_tiles<<<lg, WG, 0, st>>>(c->own_tiles, c->meta, c->start_own, c->sp_base, c->sp_frac,
-                                     c->sp_ub, c->sp_g, c->sp_du, c->U, c->boxbuf, pg, mode | uw,
+                                     c->sp_ub, c->sp_g, c->sp_du, c->U,
+                                     (unsigned char*)c->boxbuf, pg, mode | uw,
                                      c->pt_partials + (2 + it) * rs, gate, g_orig, c->du_prev,
                                      c->status);
     return hipGetLastError();
   };
   auto merge = [&](bool final_, const uint32_t* gate) {
-    k_merge_tiles<<<tg, MERGE_WG, 0, st>>>(c->touch_tiles, c->meta, c->own_slot, c->boxbuf,
+    k_merge_tiles<<<tg, MERGE_WG, 0, st>>>(c->touch_tiles, c->meta, c->own_slot,
+                                        (const unsigned char*)c->boxbuf,
                                         c->bflag, final_ ? c->G : c->U, pg, final_ ? 2 : 0, gate);
     return hipGetLastError();
   };

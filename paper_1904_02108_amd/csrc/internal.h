@@ -12,8 +12,6 @@
 #include "device_common.h"
 #include "lbmibm.h"
 
-constexpr int LBM_MAX_BODIES = 65536;
-constexpr int LBM_BLOCK = 256;  // threads per workgroup of the cell and point kernels
 
 // Per-body motion coefficients computed on the device each step:
 // normalised axis, centre, cos/sin of theta_n, and the differences of cos and
@@ -23,6 +21,8 @@ struct BodyMotion {
   double axis[3];
   double c, s, dc, ds;
 };
+static_assert(sizeof(BodyMotion) == BODY_MOTION_BYTES, "BodyMotion size");
+static_assert(sizeof(float4) == VEC4_BYTES && sizeof(int4) == VEC4_BYTES, "vector sizes");
 
 struct lbm_ctx {
   lbm_params p{};
@@ -76,7 +76,7 @@ struct lbm_ctx {
   void* theta_packed = nullptr; // BF16 matrix-core operands of the network
   uint32_t* ctl = nullptr;      // [4] residual stop: converged flag, sweeps run
   double* resid_thr = nullptr;  // [1] eps^2 sum s |u_b|^2
-  float* boxbuf = nullptr;          // [max_boxes][3][11^3] spread boxes of owner tiles
+  void* boxbuf = nullptr;           // [max_boxes] slots of BOX_SLOT_BYTES: spread boxes of owner tiles
   int64_t max_boxes = 0;
   // scratch
   double* sum_partials = nullptr;   // [n_cell_blocks][4]
@@ -146,4 +146,3 @@ hipError_t launch_features_warm(lbm_ctx* c, bool predict);
 hipError_t launch_export_pairs(lbm_ctx* c, float* feat, float* targets);
 hipError_t launch_mlp_pack(lbm_ctx* c);
 hipError_t launch_warm_mfma(lbm_ctx* c, bool from_stored_features);
-constexpr size_t MLP_PACKED_BYTES = 22 * 64 * 16;  // 22 operands x 64 lanes x 8 BF16

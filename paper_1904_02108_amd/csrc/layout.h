@@ -1,0 +1,24 @@
+// Sizes and constants shared by the host-side planning code (host_plan.cpp,
+// which is plain C++ without HIP) and the HIP sources: the D3Q19 population
+// count, the tile and force-block edges, workgroup and table sizes, and the
+// byte sizes of the device structures the host carves room for.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbmd {
+constexpr int Q = 19;         // D3Q19 populations
+constexpr int TILE = 8;       // edge of the cubic tiles the forcing works on
+constexpr int TILE_SHIFT = 3;
+constexpr int FBLK = 4;       // edge of the cubic blocks flagged as touched by a support
+constexpr int FBLK_SHIFT = 2;
+}  // namespace lbmd
+
+constexpr int LBM_MAX_BODIES = 65536;
+constexpr int LBM_BLOCK = 256;  // threads per workgroup of the cell and point kernels
+// bytes per stored spread box (11^3 cells: packed x/y sums, z sums, unit)
+constexpr int BOX_SLOT_BYTES = 16384;
+constexpr size_t MLP_PACKED_BYTES = 22 * 64 * 16;  // 22 operands x 64 lanes x 8 BF16
+constexpr size_t BODY_MOTION_BYTES = 10 * sizeof(double);  // struct BodyMotion
+constexpr size_t VEC4_BYTES = 16;                          // float4 / int4

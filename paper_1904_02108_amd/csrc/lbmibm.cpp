@@ -10,185 +10,12 @@
 #include <string>
 #include <vector>
 
+#include "host_plan.h"
 #include "internal.h"
 
 namespace {
 
 thread_local std::string g_create_error;
-
-constexpr size_t ALIGN = 256;
-size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
-
-// Byte offsets of every array inside the caller buffers.
-struct Plan {
-  size_t size[LBM_NBUF];
-  // lattice
-  size_t elem, pop_stride, lat_bytes;
-  // points
-  size_t o_rest, o_body_of, o_key, o_rank, o_base, o_frac, o_ub, o_g, o_du, o_bodies, o_motion;
-  size_t o_nbr, o_g0, o_duprev, o_feat, o_vref, o_theta, o_packed, o_ubox;
-  size_t o_box, o_G;
-  int64_t max_boxes;
-  // tiles
-  size_t o_cnt_own, o_cnt_touch, o_start_own, o_own_slot, o_own_tiles, o_touch_tiles, o_meta,
-      o_bflag, o_chunk;
-  int64_t nblocks4, nbflag_words;
-  int fblk[3];
-  // scratch
-  size_t o_sum_part, o_pt_part, o_small, o_ctl, o_thr, o_status;
-  int64_t part_row;
-  int64_t n_cell_blocks, n_pt_blocks;
-  int64_t ncell, ntiles;
-  int tiles[3];
-};
-
-struct Cursor {
-  size_t at = 0;
-  size_t take(size_t bytes) {
-    size_t o = at;
-    at = align_up(at + bytes);
-    return o;
-  }
-};
-
-lbm_status check_params(const lbm_params* p, std::string& msg) {
-  if (!p) {
-    msg = "params is NULL";
-    return LBM_ERR_ARG;
-  }
-  if (p->nx < 1 || p->ny < 1 || p->nz < 1) {
-    msg = "lattice sizes must be >= 1";
-    return LBM_ERR_ARG;
-  }
-  const int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
-  if (ncell > ((int64_t)1 << 31) - 1) {
-    msg = "lattice larger than 2^31 - 1 cells";
-    return LBM_ERR_ARG;
-  }
-  for (int a = 0; a < 3; ++a)
-    if (p->bc[a] != LBM_BC_PERIODIC && p->bc[a] != LBM_BC_BOUNCEBACK) {
-      msg = "bc must be LBM_BC_PERIODIC or LBM_BC_BOUNCEBACK";
-      return LBM_ERR_ARG;
-    }
-  if (p->storage < LBM_STORE_F32 || p->storage > LBM_STORE_BF16) {
-    msg = "unknown storage";
-    return LBM_ERR_ARG;
-  }
-  if (p->forcing != LBM_FORCE_GUO && p->forcing != LBM_FORCE_SHIFT) {
-    msg = "unknown forcing";
-    return LBM_ERR_ARG;
-  }
-  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) {
-    msg = "tau must be finite and > 0.5";
-    return LBM_ERR_ARG;
-  }
-  if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0) || !std::isfinite(p->rho_wall)) {
-    msg = "rho0 must be > 0 and rho_wall finite";
-    return LBM_ERR_ARG;
-  }
-  const double* d = &p->wall_u[0][0][0];
-  for (int k = 0; k < 18; ++k)
-    if (!std::isfinite(d[k])) {
-      msg = "wall_u must be finite";
-      return LBM_ERR_ARG;
-    }
-  for (int a = 0; a < 3; ++a)
-    if (!std::isfinite(p->g_ext[a]) || !std::isfinite(p->u0[a])) {
-      msg = "g_ext and u0 must be finite";
-      return LBM_ERR_ARG;
-    }
-  if (p->max_points < 0 || p->max_points > ((int64_t)1 << 31) - 1) {
-    msg = "max_points must be in [0, 2^31 - 1]";
-    return LBM_ERR_ARG;
-  }
-  if (p->max_iter < 1 || p->max_iter > LBM_MAX_ITER) {
-    msg = "max_iter must be in [1, 64]";
-    return LBM_ERR_ARG;
-  }
-  if (p->reserved_ != 0) {
-    msg = "reserved_ must be 0";
-    return LBM_ERR_ARG;
-  }
-  return LBM_OK;
-}
-
-void make_plan(const lbm_params* p, Plan& pl) {
-  pl.ncell = (int64_t)p->nx * p->ny * p->nz;
-  pl.elem = p->storage == LBM_STORE_F32 ? 4 : 2;
-  pl.pop_stride = align_up((size_t)pl.ncell * pl.elem) / pl.elem;
-  pl.lat_bytes = pl.pop_stride * pl.elem * lbmd::Q;
-  pl.size[LBM_BUF_LATTICE] = 2 * pl.lat_bytes;
-  const size_t M = (size_t)std::max<int64_t>(p->max_points, 1);
-  const int dims[3] = {p->nx, p->ny, p->nz};
-  for (int a = 0; a < 3; ++a) {
-    pl.tiles[a] = (dims[a] + lbmd::TILE - 1) / lbmd::TILE;
-    pl.fblk[a] = (dims[a] + lbmd::FBLK - 1) / lbmd::FBLK;
-  }
-  pl.ntiles = (int64_t)pl.tiles[0] * pl.tiles[1] * pl.tiles[2];
-  // U (tile-major, whole tiles), G (lattice layout), and the spread boxes of
-  // the tiles that own points (at most one per tile and one per point)
-  pl.o_G = align_up((size_t)pl.ntiles * 3 * lbmd::TILE * lbmd::TILE * lbmd::TILE * sizeof(float));
-  pl.size[LBM_BUF_FIELDS] = pl.o_G + align_up(3 * (size_t)pl.ncell * sizeof(float));
-  pl.max_boxes = std::max<int64_t>(1, std::min<int64_t>(pl.ntiles, p->max_points));
-  pl.o_box = pl.size[LBM_BUF_FIELDS];
-  pl.size[LBM_BUF_FIELDS] += align_up((size_t)pl.max_boxes * 3 * 11 * 11 * 11 * sizeof(float));
-  pl.nblocks4 = (int64_t)pl.fblk[0] * pl.fblk[1] * pl.fblk[2];
-  pl.nbflag_words = (pl.nblocks4 + 3) / 4;
-
-  Cursor pc;
-  pl.o_rest = pc.take(M * sizeof(float4));
-  pl.o_body_of = pc.take(M * sizeof(int32_t));
-  pl.o_key = pc.take(M * sizeof(uint32_t));
-  pl.o_rank = pc.take(M * sizeof(uint32_t));
-  pl.o_base = pc.take(M * sizeof(int4));
-  pl.o_frac = pc.take(M * sizeof(float4));
-  pl.o_ub = pc.take(M * sizeof(float4));
-  pl.o_g = pc.take(M * sizeof(float4));
-  pl.o_du = pc.take(M * sizeof(float4));
-  pl.o_bodies = pc.take((size_t)LBM_MAX_BODIES * 8 * sizeof(double));
-  pl.o_motion = pc.take((size_t)LBM_MAX_BODIES * sizeof(BodyMotion));
-  pl.o_nbr = pc.take(M * IBM_MLP_NNBR * sizeof(int32_t));
-  pl.o_g0 = pc.take(M * sizeof(float4));
-  pl.o_duprev = pc.take(M * sizeof(float4));
-  pl.o_feat = pc.take(M * IBM_MLP_NFEAT * sizeof(float));
-  pl.o_vref = pc.take((size_t)LBM_MAX_BODIES * sizeof(float));
-  pl.o_ubox = pc.take((size_t)LBM_MAX_BODIES * 6 * sizeof(float));
-  pl.o_theta = pc.take((size_t)IBM_MLP_NPARAM * sizeof(float));
-  pl.o_packed = pc.take(MLP_PACKED_BYTES);
-  pl.size[LBM_BUF_POINTS] = pc.at;
-
-  const size_t NT = (size_t)pl.ntiles;
-  Cursor tc;
-  const size_t NTpad = (NT + 16383) / 16384 * 16384;  // whole chunks of the tile scan
-  pl.o_cnt_own = tc.take(NTpad * 4);
-  pl.o_cnt_touch = tc.take(NTpad * 4);
-  pl.o_start_own = tc.take((NT + 1) * 4);
-  pl.o_own_slot = tc.take(NT * 4);
-  pl.o_own_tiles = tc.take(NT * 4);
-  pl.o_touch_tiles = tc.take(NT * 4);
-  pl.o_meta = tc.take(4 * 4);
-  pl.o_bflag = tc.take((size_t)pl.nbflag_words * 4);
-  pl.o_chunk = tc.take((NTpad / 2048) * 4 * 4);  // totals of the 2048-tile scan chunks
-  pl.size[LBM_BUF_TILES] = tc.at;
-
-  {  // blocks of the stream-collide launch (see stream_collide_shape)
-    int bx = ((p->nx + 63) / 64) * 64;
-    if (bx > LBM_BLOCK) bx = LBM_BLOCK;
-    const int by = LBM_BLOCK / bx;
-    pl.n_cell_blocks = (int64_t)((p->nx + bx - 1) / bx) * ((p->ny + by - 1) / by) * p->nz;
-    pl.n_cell_blocks = std::max<int64_t>(pl.n_cell_blocks, (pl.ncell + LBM_BLOCK - 1) / LBM_BLOCK);
-  }
-  pl.n_pt_blocks = ((int64_t)M + LBM_BLOCK - 1) / LBM_BLOCK;
-  pl.part_row = std::max<int64_t>(pl.n_pt_blocks, (pl.ntiles + 7) / 8 * 8);
-  Cursor sc;
-  pl.o_sum_part = sc.take((size_t)pl.n_cell_blocks * 4 * sizeof(double));
-  pl.o_pt_part = sc.take((size_t)(p->max_iter + 2) * pl.part_row * sizeof(double));
-  pl.o_small = sc.take(256 * sizeof(double));
-  pl.o_ctl = sc.take(4 * sizeof(uint32_t));
-  pl.o_thr = sc.take(sizeof(double));
-  pl.o_status = sc.take(4 * sizeof(uint32_t));
-  pl.size[LBM_BUF_SCRATCH] = sc.at;
-}
 
 lbm_status fail(lbm_ctx* c, lbm_status st, const std::string& msg) {
   c->err = msg;
@@ -379,7 +206,7 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->ubox = (float*)(P + pl.o_ubox);
   c->theta = (float*)(P + pl.o_theta);
   c->theta_packed = (void*)(P + pl.o_packed);
-  c->boxbuf = (float*)(F + pl.o_box);
+  c->boxbuf = (void*)(F + pl.o_box);
   c->max_boxes = pl.max_boxes;
   char* T = (char*)bufs[LBM_BUF_TILES];
   for (int a = 0; a < 3; ++a) c->fblk[a] = pl.fblk[a];
@@ -462,97 +289,16 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
     if (e != hipSuccess) return hip_fail(c, e, "clear force-block flags");
     return LBM_OK;
   }
-  if (!rest_xyz || !area || !body_off || !bodies)
-    return fail(c, LBM_ERR_ARG, "NULL point array");
-  if (nbodies < 1 || nbodies > LBM_MAX_BODIES)
-    return fail(c, LBM_ERR_ARG, "nbodies must be in [1, 65536]");
-  if (n_iter < 1 || n_iter > c->p.max_iter)
-    return fail(c, LBM_ERR_ARG, "n_iter must be in [1, max_iter]");
-  const uint32_t known =
-      IBM_INNER_UNWEIGHTED | IBM_STOP_RESIDUAL | IBM_WARM_START | IBM_KEEP_FEATURES | IBM_MLP_FP32 |
-      IBM_WARM_PREV | IBM_U_BOX | IBM_U_KERNEL;
-  if (flags & ~known) return fail(c, LBM_ERR_ARG, "unknown flags");
-  if ((flags & IBM_WARM_START) && (flags & IBM_WARM_PREV))
-    return fail(c, LBM_ERR_ARG, "IBM_WARM_START and IBM_WARM_PREV exclude each other");
-  if ((flags & IBM_U_BOX) && (flags & IBM_U_KERNEL))
-    return fail(c, LBM_ERR_ARG, "IBM_U_BOX and IBM_U_KERNEL exclude each other");
-  if ((flags & IBM_WARM_START) && (flags & IBM_INNER_UNWEIGHTED))
-    return fail(c, LBM_ERR_ARG, "IBM_WARM_START needs the weighted inner sweep");
-  if (flags & IBM_STOP_RESIDUAL) {
-    if (!(eps >= 0.0f) || !std::isfinite(eps))
-      return fail(c, LBM_ERR_ARG, "eps must be finite and >= 0");
-  } else if (eps != 0.0f) {
-    return fail(c, LBM_ERR_ARG, "eps must be 0 without IBM_STOP_RESIDUAL");
-  }
-  if (body_off[0] != 0 || body_off[nbodies] != n)
-    return fail(c, LBM_ERR_ARG, "body_off must start at 0 and end at n");
-  for (int b = 0; b < nbodies; ++b)
-    if (body_off[b + 1] < body_off[b]) return fail(c, LBM_ERR_ARG, "body_off must not decrease");
-  std::vector<float4> rest((size_t)n);
-  std::vector<int32_t> body_of((size_t)n);
-  std::vector<double> btab((size_t)nbodies * 8);
-  std::vector<float> vref((size_t)nbodies);
-  std::vector<float> ubox((size_t)nbodies * 6, 0.0f);
-  double ubox_reach = 0.0;  // largest distance of a rest-box corner from its centre
-  const int dims[3] = {c->p.nx, c->p.ny, c->p.nz};
-  for (int b = 0; b < nbodies; ++b) {
-    const ibm_body& B = bodies[b];
-    const double al = std::sqrt(B.axis[0] * B.axis[0] + B.axis[1] * B.axis[1] + B.axis[2] * B.axis[2]);
-    if (!(al > 0.0) || !std::isfinite(al) || !std::isfinite(B.theta0) || !std::isfinite(B.omega))
-      return fail(c, LBM_ERR_ARG, "body axis must be nonzero and finite; theta0, omega finite");
-    double rmax = 0.0;
-    for (int64_t k = body_off[b]; k < body_off[b + 1]; ++k) {
-      const float* r = rest_xyz + 3 * k;
-      if (!std::isfinite(r[0]) || !std::isfinite(r[1]) || !std::isfinite(r[2]) ||
-          !std::isfinite(area[k]) || area[k] < 0.0f)
-        return fail(c, LBM_ERR_ARG, "rest positions must be finite and areas finite, >= 0");
-      rest[(size_t)k] = make_float4(r[0], r[1], r[2], area[k]);
-      body_of[(size_t)k] = b;
-      rmax = std::max(rmax, std::sqrt((double)r[0] * r[0] + (double)r[1] * r[1] + (double)r[2] * r[2]));
-    }
-    for (int a = 0; a < 3; ++a) {
-      if (!std::isfinite(B.center[a])) return fail(c, LBM_ERR_ARG, "body centre must be finite");
-      if (c->p.bc[a] == LBM_BC_BOUNCEBACK && body_off[b + 1] > body_off[b]) {
-        // every support must stay inside: 1 <= x < n - 2 for all angles
-        const double margin = 1e-6 * (1.0 + rmax + std::fabs(B.center[a]));
-        if (B.center[a] - rmax < 1.0 + margin || B.center[a] + rmax >= dims[a] - 2.0 - margin)
-          return fail(c, LBM_ERR_DOMAIN, "a body's kernel support can cross a wall");
-      }
-    }
-    for (int a = 0; a < 3; ++a) {
-      btab[8 * b + a] = B.center[a];
-      btab[8 * b + 3 + a] = B.axis[a];
-    }
-    btab[8 * b + 6] = B.theta0;
-    btab[8 * b + 7] = B.omega;
-    // reference speed of the learned features: the fastest rest point's
-    // speed bound |omega| max |r|, or 1 for a body at rest
-    const double vr = std::fabs(B.omega) * rmax;
-    vref[(size_t)b] = vr > 0.0 ? (float)vr : 1.0f;
-    // rest-position bounding box of the body's points (box U pre-pass)
-    if (body_off[b + 1] > body_off[b]) {
-      float lo[3] = {rest_xyz[3 * body_off[b]], rest_xyz[3 * body_off[b] + 1], rest_xyz[3 * body_off[b] + 2]};
-      float hi[3] = {lo[0], lo[1], lo[2]};
-      for (int64_t k = body_off[b]; k < body_off[b + 1]; ++k)
-        for (int a = 0; a < 3; ++a) {
-          lo[a] = std::min(lo[a], rest_xyz[3 * k + a]);
-          hi[a] = std::max(hi[a], rest_xyz[3 * k + a]);
-        }
-      double reach2 = 0.0;
-      for (int a = 0; a < 3; ++a) {
-        ubox[6 * (size_t)b + a] = lo[a];
-        ubox[6 * (size_t)b + 3 + a] = hi[a];
-        const double m = std::max(std::fabs((double)lo[a]), std::fabs((double)hi[a]));
-        reach2 += m * m;
-      }
-      ubox_reach = std::max(ubox_reach, std::sqrt(reach2));
-    }
-  }
-  HIP_TRY(c, hipMemcpyAsync(c->rest, rest.data(), rest.size() * sizeof(float4), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->body_of, body_of.data(), body_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->bodies, btab.data(), btab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->vref, vref.data(), vref.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->ubox, ubox.data(), ubox.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  SurfaceHost sh;
+  std::string msg;
+  const lbm_status vst =
+      prepare_surface(c->p, n, rest_xyz, area, body_off, nbodies, bodies, n_iter, flags, eps, sh, msg);
+  if (vst != LBM_OK) return fail(c, vst, msg);
+  HIP_TRY(c, hipMemcpyAsync(c->rest, sh.rest4.data(), sh.rest4.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->body_of, sh.body_of.data(), sh.body_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->bodies, sh.btab.data(), sh.btab.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->vref, sh.vref.data(), sh.vref.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->ubox, sh.ubox.data(), sh.ubox.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->npts = n;
   c->nbodies = nbodies;
@@ -561,10 +307,7 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
   c->eps = (flags & IBM_STOP_RESIDUAL) ? eps : 0.0f;
   c->nbr_valid = false;
   c->du_prev_valid = false;
-  // a moved box lies in the cube of half-edge reach around the centre; the
-  // pre-pass widens it to floor(lo) - 2 .. floor(hi) + 3, at most 2 reach + 7
-  // cells per axis (one more for rounding)
-  c->ubox_sub = (int)std::ceil((2.0 * ubox_reach + 8.0) / lbmd::TILE);
+  c->ubox_sub = sh.ubox_sub;
   c->meta_pending = false;  // the stream has been synchronised above
   c->prev_len_valid = false;
   c->g_valid_step = -1;
