@@ -233,8 +233,9 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
 /* Destroys the context (host memory only; the caller frees its buffers). */
 void lbm_destroy(lbm_ctx* ctx);
 
-/* Last error message of ctx, or of the last failed lbm_create on this thread
- * when ctx is NULL.  Valid until the next call on the context. */
+/* Last error message of ctx, or of the last failed lbm_create or
+ * mlp_loss_grad_noalloc on this thread when ctx is NULL.  Valid until the
+ * next call on the context. */
 const char* lbm_last_error(const lbm_ctx* ctx);
 
 /* Sets the immersed surface (§3, §4.2): n points with rest positions
@@ -322,6 +323,24 @@ lbm_status mlp_loss_grad(const float* theta, int64_t n, const float* x, const fl
 lbm_status mlp_train(float* theta, float* m, float* v, int64_t* step_t, int64_t n,
                      const float* x, const float* t, int64_t batch, int32_t n_epochs,
                      double lr, double* loss_per_epoch, void* workspace, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): mlp_loss_grad
+ * with the library's own workspace instead of a caller one.  The workspace
+ * is a fixed device array held by the library (about 2.7 MB on each device
+ * it runs on, until the process ends), sized for n <= MLP_NOALLOC_MAX_BATCH
+ * samples; a larger n returns LBM_ERR_ARG (message in lbm_last_error(NULL)).
+ * The call allocates nothing (no hipMalloc, no allocating library routine);
+ * its first call on a device looks up the array's device address there.
+ * Arguments, layouts and results as mlp_loss_grad: theta, x [n][12], t [n][3],
+ * grad [IBM_MLP_NPARAM] and loss_out (nullable, double[1]) are caller device
+ * memory; work is enqueued on `stream`.  Every call on a device shares that
+ * device's workspace, which keeps the last call's contents (each call writes
+ * every byte it reads first): calls that overlap on one device, on different
+ * streams or threads, race and must be serialised by the caller. */
+#define MLP_NOALLOC_MAX_BATCH 1024
+lbm_status mlp_loss_grad_noalloc(const float* theta, int64_t n, const float* x, const float* t,
+                                 float* grad, double* loss_out, void* stream);
 
 /* Optional per-phase timing with HIP events on the context's stream.
  * lbm_get_timing returns {ms forcing, ms stream-collide, forcing calls,

@@ -122,6 +122,10 @@ struct lbm_ctx {
   std::string err;
 };
 
+// message returned by lbm_last_error(NULL) on this thread (calls without a
+// context: lbm_create, mlp_loss_grad_noalloc)
+void set_noalloc_error(const std::string& msg);
+
 // lattice kernels (lbm_kernels.hip)
 hipError_t launch_init_equilibrium(lbm_ctx* c);
 hipError_t launch_unstream_from(lbm_ctx* c, const void* pops, int f64);

@@ -17,6 +17,12 @@ namespace {
 
 thread_local std::string g_create_error;
 
+}  // namespace
+
+void set_noalloc_error(const std::string& msg) { g_create_error = msg; }
+
+namespace {
+
 lbm_status fail(lbm_ctx* c, lbm_status st, const std::string& msg) {
   c->err = msg;
   return st;

@@ -5,6 +5,9 @@
 //
 // Parameter layout (row-major, out x in):
 //   W1[64][12] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[3][64] b4[3]
+#include <mutex>
+#include <string>
+
 #include "internal.h"
 
 using namespace lbmd;
@@ -713,7 +716,25 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ theta, const f
   theta[p] -= lr * (mp / c1) / (sqrtf(vp / c2) + 1e-8f);
 }
 
-size_t ws_align(size_t v) { return (v + 255) / 256 * 256; }
+constexpr size_t ws_align(size_t v) { return (v + 255) / 256 * 256; }
+
+// Workspace bytes of a training batch of B samples (the carving of carve_ws).
+constexpr size_t ws_bytes(int64_t batch) {
+  const int64_t B = batch < 1 ? 1 : batch;
+  const int64_t nch = (B + CHUNK - 1) / CHUNK;
+  return 9 * ws_align((size_t)B * NH * 4) + ws_align((size_t)B * NOUT * 4) +
+         ws_align((size_t)NPARAM * 4) + ws_align((size_t)nch * NPARAM * 4) +
+         ws_align((size_t)((B + 255) / 256) * 8) + ws_align(4 * 8);
+}
+
+// Library-held workspace of mlp_loss_grad_noalloc, for callers that cannot
+// allocate device memory: one copy per device, sized for batches of at most
+// MLP_NOALLOC_MAX_BATCH samples (about 2.7 MB).  Every byte a batch reads is
+// written earlier in the same call (activations, chunk partials, loss
+// partials), so nothing needs clearing between calls; calls that overlap on
+// one device share it and race.
+constexpr size_t MLP_NOALLOC_BYTES = ws_bytes(MLP_NOALLOC_MAX_BATCH);
+__device__ __align__(256) unsigned char scratch[MLP_NOALLOC_BYTES];
 
 TrainWS carve_ws(void* ws, int64_t B) {
   TrainWS w;
@@ -819,20 +840,38 @@ hipError_t launch_export_pairs(lbm_ctx* c, float* feat, float* targets) {
   return hipGetLastError();
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current (the array's name is only a host-side
+// stand-in for it).
+static lbm_status noalloc_workspace(void** out) {
+  constexpr int MAX_DEV = 64;
+  static std::mutex mu;
+  static void* addr[MAX_DEV] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= MAX_DEV) {
+    set_noalloc_error(std::string("mlp_loss_grad_noalloc: no usable current device: ") +
+                      hipGetErrorString(e));
+    return LBM_ERR_HIP;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_noalloc_error(std::string("mlp_loss_grad_noalloc: hipGetSymbolAddress: ") +
+                        hipGetErrorString(e));
+      return LBM_ERR_HIP;
+    }
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return LBM_OK;
+}
+
 extern "C" {
 
-size_t mlp_workspace_size(int64_t batch) {
-  if (batch < 1) batch = 1;
-  const int64_t nch = (batch + CHUNK - 1) / CHUNK;
-  size_t s = 0;
-  s += 9 * ws_align((size_t)batch * NH * 4);
-  s += ws_align((size_t)batch * NOUT * 4);
-  s += ws_align((size_t)NPARAM * 4);
-  s += ws_align((size_t)nch * NPARAM * 4);
-  s += ws_align((size_t)((batch + 255) / 256) * 8);
-  s += ws_align(4 * 8);
-  return s;
-}
+size_t mlp_workspace_size(int64_t batch) { return ws_bytes(batch); }
 
 lbm_status mlp_forward(const float* theta, int64_t n, const float* x, float* y, int32_t precision,
                        void* workspace, void* stream) {
@@ -857,6 +896,30 @@ lbm_status mlp_loss_grad(const float* theta, int64_t n, const float* x, const fl
   const TrainWS w = carve_ws(workspace, n);
   hipError_t e = batch_grad(theta, n, x, t, grad, loss_out, w, (hipStream_t)stream);
   return e == hipSuccess ? LBM_OK : LBM_ERR_HIP;
+}
+
+lbm_status mlp_loss_grad_noalloc(const float* theta, int64_t n, const float* x, const float* t,
+                                 float* grad, double* loss_out, void* stream) {
+  if (!theta || n < 1 || !x || !t || !grad) {
+    set_noalloc_error("mlp_loss_grad_noalloc: a pointer is NULL or n < 1");
+    return LBM_ERR_ARG;
+  }
+  if (n > MLP_NOALLOC_MAX_BATCH) {
+    set_noalloc_error("mlp_loss_grad_noalloc: n = " + std::to_string(n) +
+                      " exceeds the library workspace's batch limit of " +
+                      std::to_string(MLP_NOALLOC_MAX_BATCH) + " samples");
+    return LBM_ERR_ARG;
+  }
+  void* ws = nullptr;
+  const lbm_status st = noalloc_workspace(&ws);
+  if (st != LBM_OK) return st;
+  const TrainWS w = carve_ws(ws, n);
+  hipError_t e = batch_grad(theta, n, x, t, grad, loss_out, w, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    set_noalloc_error(std::string("mlp_loss_grad_noalloc: ") + hipGetErrorString(e));
+    return LBM_ERR_HIP;
+  }
+  return LBM_OK;
 }
 
 lbm_status mlp_train(float* theta, float* m, float* v, int64_t* step_t, int64_t n, const float* x,

@@ -35,6 +35,7 @@ IBM_WARM_PREV, IBM_U_BOX, IBM_U_KERNEL = 32, 64, 128
 MLP_FP32, MLP_BF16 = 0, 1
 IBM_MLP_NPARAM, IBM_MLP_NFEAT, IBM_MLP_NNBR = 9347, 12, 16
 LBM_MAX_ITER = 64
+MLP_NOALLOC_MAX_BATCH = 1024
 (LBM_F_RHO, LBM_F_VEL, LBM_F_FORCE, LBM_F_POPS, LBM_F_PT_X, LBM_F_PT_UB, LBM_F_PT_G, LBM_F_PT_DU,
  LBM_F_SUMS, LBM_F_STEP) = (1 << k for k in range(10))
 
@@ -42,7 +43,7 @@ ABI_FUNCTIONS = ("lbm_buffer_sizes", "lbm_create", "lbm_destroy", "lbm_last_erro
                  "ibm_set_points", "ibm_force_iterate", "lbm_step", "lbm_read_fields",
                  "lbm_write_fields", "lbm_set_timing", "lbm_get_timing", "ibm_set_mlp",
                  "ibm_log_pairs", "ibm_last_stats", "mlp_workspace_size", "mlp_forward",
-                 "mlp_loss_grad", "mlp_train", "lbm_set_check")
+                 "mlp_loss_grad", "mlp_train", "lbm_set_check", "mlp_loss_grad_noalloc")
 
 
 class lbm_params(ct.Structure):
@@ -98,6 +99,8 @@ _lib.mlp_forward.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, 
                              ct.c_void_p, ct.c_void_p]
 _lib.mlp_loss_grad.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                ct.c_void_p, ct.c_void_p, ct.c_void_p]
+_lib.mlp_loss_grad_noalloc.argtypes = [ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_void_p,
+                                       ct.c_void_p, ct.c_void_p, ct.c_void_p]
 _lib.mlp_train.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.POINTER(ct.c_int64),
                            ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32,
                            ct.c_double, ct.c_void_p, ct.c_void_p, ct.c_void_p]
@@ -221,6 +224,12 @@ def mlp_loss_grad(theta_ptr, n, x_ptr, t_ptr, grad_ptr, loss_ptr, workspace_ptr,
     _check(_lib.mlp_loss_grad(ct.c_void_p(theta_ptr), int(n), ct.c_void_p(x_ptr),
                               ct.c_void_p(t_ptr), ct.c_void_p(grad_ptr), ct.c_void_p(loss_ptr),
                               ct.c_void_p(workspace_ptr), ct.c_void_p(stream_ptr)))
+
+
+def mlp_loss_grad_noalloc(theta_ptr, n, x_ptr, t_ptr, grad_ptr, loss_ptr, stream_ptr):
+    _check(_lib.mlp_loss_grad_noalloc(ct.c_void_p(theta_ptr), int(n), ct.c_void_p(x_ptr),
+                                      ct.c_void_p(t_ptr), ct.c_void_p(grad_ptr),
+                                      ct.c_void_p(loss_ptr), ct.c_void_p(stream_ptr)))
 
 
 def mlp_train(theta_ptr, m_ptr, v_ptr, step_t, n, x_ptr, t_ptr, batch, n_epochs, lr,
