@@ -32,6 +32,14 @@ lbm_status check_params(const lbm_params* p, std::string& msg) {
     msg = "lattice larger than 2^31 - 1 cells";
     return LBM_ERR_ARG;
   }
+  // the forcing indexes cells of whole 8^3 tiles with 32-bit unsigned offsets
+  const int64_t T = lbmd::TILE;
+  const int64_t tile_cells =
+      ((p->nx + T - 1) / T) * ((p->ny + T - 1) / T) * ((p->nz + T - 1) / T) * T * T * T;
+  if (tile_cells > ((int64_t)1 << 32) - 1) {
+    msg = "lattice padded to whole 8^3 tiles larger than 2^32 - 1 cells";
+    return LBM_ERR_ARG;
+  }
   for (int a = 0; a < 3; ++a)
     if (p->bc[a] != LBM_BC_PERIODIC && p->bc[a] != LBM_BC_BOUNCEBACK) {
       msg = "bc must be LBM_BC_PERIODIC or LBM_BC_BOUNCEBACK";
@@ -92,9 +100,10 @@ void make_plan(const lbm_params* p, Plan& pl) {
     pl.fblk[a] = (dims[a] + lbmd::FBLK - 1) / lbmd::FBLK;
   }
   pl.ntiles = (int64_t)pl.tiles[0] * pl.tiles[1] * pl.tiles[2];
-  // U (tile-major, whole tiles), G (lattice layout), and the spread boxes of
-  // the tiles that own points (at most one per tile and one per point)
-  pl.o_G = align_up((size_t)pl.ntiles * 3 * lbmd::TILE * lbmd::TILE * lbmd::TILE * sizeof(float));
+  // U (tile-major, whole tiles, one float4 per cell), G (lattice layout),
+  // and the spread boxes of the tiles that own points (at most one per tile
+  // and one per point)
+  pl.o_G = align_up((size_t)pl.ntiles * lbmd::TILE * lbmd::TILE * lbmd::TILE * VEC4_BYTES);
   pl.size[LBM_BUF_FIELDS] = pl.o_G + align_up(3 * (size_t)pl.ncell * sizeof(float));
   pl.max_boxes = std::max<int64_t>(1, std::min<int64_t>(pl.ntiles, p->max_points));
   pl.o_box = pl.size[LBM_BUF_FIELDS];
@@ -112,6 +121,7 @@ void make_plan(const lbm_params* p, Plan& pl) {
   pl.o_ub = pc.take(M * VEC4_BYTES);
   pl.o_g = pc.take(M * VEC4_BYTES);
   pl.o_du = pc.take(M * VEC4_BYTES);
+  pl.o_tmp = pc.take(M * VEC4_BYTES);
   pl.o_bodies = pc.take((size_t)LBM_MAX_BODIES * 8 * sizeof(double));
   pl.o_motion = pc.take((size_t)LBM_MAX_BODIES * BODY_MOTION_BYTES);
   pl.o_nbr = pc.take(M * IBM_MLP_NNBR * sizeof(int32_t));
@@ -126,16 +136,22 @@ void make_plan(const lbm_params* p, Plan& pl) {
 
   const size_t NT = (size_t)pl.ntiles;
   Cursor tc;
-  const size_t NTpad = (NT + 16383) / 16384 * 16384;  // whole chunks of the tile scan
-  pl.o_cnt_own = tc.take(NTpad * 4);
-  pl.o_cnt_touch = tc.take(NTpad * 4);
-  pl.o_start_own = tc.take((NT + 1) * 4);
+  // positions of the tile scan: the tile grid padded to whole 4^3 blocks of
+  // tiles, in whole chunks of 2048
+  size_t NP = 1;
+  for (int a = 0; a < 3; ++a) NP *= (size_t)(pl.tiles[a] + 3) / 4 * 4;
+  const size_t NPpad = (NP + 2047) / 2048 * 2048;
+  pl.o_cnt_own = tc.take(NT * 4);
+  pl.o_cnt_touch = tc.take(NT * 4);
+  pl.o_start_own = tc.take(NT * 4);
+  pl.o_end_own = tc.take(NT * 4);
   pl.o_own_slot = tc.take(NT * 4);
   pl.o_own_tiles = tc.take(NT * 4);
   pl.o_touch_tiles = tc.take(NT * 4);
   pl.o_meta = tc.take(4 * 4);
   pl.o_bflag = tc.take((size_t)pl.nbflag_words * 4);
-  pl.o_chunk = tc.take((NTpad / 2048) * 4 * 4);  // totals of the 2048-tile scan chunks
+  pl.o_chunk = tc.take((NPpad / 2048) * 4 * 4);  // totals of the scan chunks
+
   pl.size[LBM_BUF_TILES] = tc.at;
 
   {  // blocks of the stream-collide launch (see stream_collide_shape)

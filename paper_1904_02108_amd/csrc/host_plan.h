@@ -22,12 +22,13 @@ struct Plan {
   // lattice
   size_t elem, pop_stride, lat_bytes;
   // points
-  size_t o_rest, o_body_of, o_key, o_rank, o_base, o_frac, o_ub, o_g, o_du, o_bodies, o_motion;
+  size_t o_rest, o_body_of, o_key, o_rank, o_base, o_frac, o_ub, o_g, o_du, o_tmp, o_bodies,
+      o_motion;
   size_t o_nbr, o_g0, o_duprev, o_feat, o_vref, o_theta, o_packed, o_ubox;
   size_t o_box, o_G;
   int64_t max_boxes;
   // tiles
-  size_t o_cnt_own, o_cnt_touch, o_start_own, o_own_slot, o_own_tiles, o_touch_tiles, o_meta,
+  size_t o_cnt_own, o_cnt_touch, o_start_own, o_end_own, o_own_slot, o_own_tiles, o_touch_tiles, o_meta,
       o_bflag, o_chunk;
   int64_t nblocks4, nbflag_words;
   int fblk[3];

@@ -29,6 +29,17 @@ constexpr int BOX3 = BOX * BOX * BOX;
 constexpr int TILE3 = TILE * TILE * TILE;
 constexpr int WG = 256;                   // threads of the per-tile point kernels
 
+// The slot of an owner tile's spread box in boxbuf (BOX_SLOT_BYTES): the
+// packed x/y sums of the 11^3 cells (64-bit, as accumulated), the z sums
+// (32-bit), the support mask (bit i set when cell i of the box is a tap of
+// some point of the tile; written once per forcing by k_tile_order), and the
+// box's fixed-point unit B / 2^30 (FP32) in the slot's last word.
+constexpr int BOX_Z_OFF = BOX3 * 8;
+constexpr int BOX_MASK_WORDS = (BOX3 + 31) / 32;
+constexpr int BOX_MASK_OFF = (BOX_Z_OFF + BOX3 * 4 + 7) / 8 * 8;
+constexpr int BOX_UNIT_OFF = BOX_SLOT_BYTES - 4;
+static_assert(BOX_MASK_OFF + BOX_MASK_WORDS * 4 <= BOX_UNIT_OFF, "box slot too small");
+
 struct PointGeom {
   int n[3];
   int bc[3];
@@ -166,6 +177,12 @@ __device__ __forceinline__ uint32_t agg_increment(uint32_t* counters, uint32_t k
   return slot;
 }
 
+// Cell of a base position within its tile (x fastest).
+__device__ __forceinline__ uint32_t local_cell(const int base[3]) {
+  return (uint32_t)(base[0] & (TILE - 1)) +
+         TILE * ((uint32_t)(base[1] & (TILE - 1)) + TILE * (uint32_t)(base[2] & (TILE - 1)));
+}
+
 // Pass 1: owner tile and rank of each point; flags of the touched tiles.
 __global__ __launch_bounds__(LBM_BLOCK) void k_point_count(
     const float4* __restrict__ rest, const int32_t* __restrict__ body_of,
@@ -205,25 +222,45 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_point_count(
 // writes the list lengths, to the device and to pinned host memory for the
 // next forcing's grid sizes), and the chunk rescans that write the outputs
 // and clear the counters and this step's force-block flags.  A chunk is
-// SCAN_WG threads x SCAN_PER consecutive tiles (the count arrays are padded
-// with zeros to whole chunks).
+// SCAN_WG threads x SCAN_PER consecutive scan positions.
+//
+// The scan visits the tiles by 4 x 4 x 4 blocks of tiles (x fastest within a
+// block, blocks x fastest): consecutive list entries, which the forcing
+// kernels deal to one XCD in contiguous runs, are then neighbours in all
+// three directions, and the U, box and lattice data the halos of a run
+// share stay in that XCD's L2.  Positions of the padded block grid outside
+// the tile grid hold no tile.
 constexpr int SCAN_WG = 256, SCAN_PER = 8, SCAN_CHUNK = SCAN_WG * SCAN_PER;
+constexpr int SB = 4;  // tiles per edge of a scan block
+
+// Tile at scan position p, or -1.
+__device__ __forceinline__ int64_t scan_tile(const PointGeom& pg, int64_t p) {
+  const int64_t sb = p / (SB * SB * SB);
+  const int w = (int)(p - sb * (SB * SB * SB));
+  const int nbx = (pg.tiles[0] + SB - 1) / SB, nby = (pg.tiles[1] + SB - 1) / SB;
+  const int64_t r = sb / nbx;
+  const int x = SB * (int)(sb - r * nbx) + (w % SB);
+  const int y = SB * (int)(r % nby) + ((w / SB) % SB);
+  const int z = SB * (int)(r / nby) + (w / (SB * SB));
+  if (x >= pg.tiles[0] || y >= pg.tiles[1] || z >= pg.tiles[2]) return -1;
+  return (int64_t)x + (int64_t)pg.tiles[0] * ((int64_t)y + (int64_t)pg.tiles[1] * z);
+}
 constexpr int SCAN_WAVES = SCAN_WG / 64;
 // scanned per tile: points owned, owner tile with more than HEAVY_TILE
 // points, other owner tile, touched tile
 constexpr int SCAN_NV = 4;
 constexpr uint32_t HEAVY_TILE = WG;
 
-__device__ __forceinline__ void load_counts(const uint32_t* __restrict__ cnt_own,
-                                            const uint32_t* __restrict__ cnt_touch, int64_t t0,
-                                            uint32_t a[SCAN_PER], uint32_t b[SCAN_PER],
-                                            uint32_t s[SCAN_NV]) {
+__device__ __forceinline__ void load_counts(const PointGeom& pg,
+                                            const uint32_t* __restrict__ cnt_own,
+                                            const uint32_t* __restrict__ cnt_touch, int64_t p0,
+                                            int64_t tl[SCAN_PER], uint32_t a[SCAN_PER],
+                                            uint32_t b[SCAN_PER], uint32_t s[SCAN_NV]) {
 #pragma unroll
-  for (int j = 0; j < SCAN_PER; j += 4) {
-    const uint4 va = *reinterpret_cast<const uint4*>(cnt_own + t0 + j);
-    const uint4 vb = *reinterpret_cast<const uint4*>(cnt_touch + t0 + j);
-    a[j] = va.x; a[j + 1] = va.y; a[j + 2] = va.z; a[j + 3] = va.w;
-    b[j] = vb.x; b[j + 1] = vb.y; b[j + 2] = vb.z; b[j + 3] = vb.w;
+  for (int j = 0; j < SCAN_PER; ++j) {
+    tl[j] = scan_tile(pg, p0 + j);
+    a[j] = tl[j] >= 0 ? cnt_own[tl[j]] : 0u;
+    b[j] = tl[j] >= 0 ? cnt_touch[tl[j]] : 0u;
   }
   s[0] = s[1] = s[2] = s[3] = 0u;
 #pragma unroll
@@ -267,20 +304,21 @@ __device__ __forceinline__ void block_scan(const uint32_t s[SCAN_NV], uint32_t e
   __syncthreads();
 }
 
-__global__ __launch_bounds__(SCAN_WG) void k_scan_totals(const uint32_t* __restrict__ cnt_own,
+__global__ __launch_bounds__(SCAN_WG) void k_scan_totals(PointGeom pg,
+                                                         const uint32_t* __restrict__ cnt_own,
                                                          const uint32_t* __restrict__ cnt_touch,
                                                          uint32_t* __restrict__ chunk) {
-  const int64_t t0 = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+  const int64_t p0 = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+  int64_t tl[SCAN_PER];
   uint32_t a[SCAN_PER], b[SCAN_PER], s[SCAN_NV], ex[SCAN_NV], tot[SCAN_NV];
-  load_counts(cnt_own, cnt_touch, t0, a, b, s);
+  load_counts(pg, cnt_own, cnt_touch, p0, tl, a, b, s);
   block_scan<SCAN_WAVES>(s, ex, tot);
   if (threadIdx.x < SCAN_NV) chunk[SCAN_NV * blockIdx.x + threadIdx.x] = tot[threadIdx.x];
 }
 
 constexpr int SCAN2_WG = 1024;
 __global__ __launch_bounds__(SCAN2_WG) void k_scan_chunks(uint32_t* __restrict__ chunk, int64_t nch,
-                                                          uint32_t* __restrict__ start_own,
-                                                          int64_t ntiles, uint32_t* __restrict__ meta,
+                                                          uint32_t* __restrict__ meta,
                                                           uint32_t* __restrict__ meta_host) {
   __shared__ uint32_t carry[SCAN_NV];
   if (threadIdx.x < SCAN_NV) carry[threadIdx.x] = 0u;
@@ -300,7 +338,6 @@ __global__ __launch_bounds__(SCAN2_WG) void k_scan_chunks(uint32_t* __restrict__
   }
   if (threadIdx.x == 0) {
     // meta: owner tiles, touched tiles, heavy owner tiles (listed first)
-    start_own[ntiles] = carry[0];
     meta[0] = carry[1] + carry[2];
     meta[1] = carry[3];
     meta[2] = carry[1];
@@ -312,14 +349,15 @@ __global__ __launch_bounds__(SCAN2_WG) void k_scan_chunks(uint32_t* __restrict__
 }
 
 __global__ __launch_bounds__(SCAN_WG) void k_scan_write(
-    uint32_t* __restrict__ cnt_own, uint32_t* __restrict__ cnt_touch,
-    const uint32_t* __restrict__ chunk, int64_t ntiles, uint32_t* __restrict__ start_own,
-    int32_t* __restrict__ own_slot, uint32_t* __restrict__ own_tiles,
-    uint32_t* __restrict__ touch_tiles, uint32_t* __restrict__ bflag_words, int64_t nbflag_words,
-    const uint32_t* __restrict__ meta) {
-  const int64_t t0 = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+    PointGeom pg, uint32_t* __restrict__ cnt_own, uint32_t* __restrict__ cnt_touch,
+    const uint32_t* __restrict__ chunk, uint32_t* __restrict__ start_own,
+    uint32_t* __restrict__ end_own, int32_t* __restrict__ own_slot,
+    uint32_t* __restrict__ own_tiles, uint32_t* __restrict__ touch_tiles,
+    uint32_t* __restrict__ bflag_words, int64_t nbflag_words, const uint32_t* __restrict__ meta) {
+  const int64_t p0 = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
+  int64_t tl[SCAN_PER];
   uint32_t a[SCAN_PER], b[SCAN_PER], s[SCAN_NV], ex[SCAN_NV], tot[SCAN_NV];
-  load_counts(cnt_own, cnt_touch, t0, a, b, s);
+  load_counts(pg, cnt_own, cnt_touch, p0, tl, a, b, s);
   block_scan<SCAN_WAVES>(s, ex, tot);
   uint32_t run[SCAN_NV];
 #pragma unroll
@@ -327,23 +365,20 @@ __global__ __launch_bounds__(SCAN_WG) void k_scan_write(
   run[2] += meta[2];  // the other owner tiles follow the heavy ones
 #pragma unroll
   for (int j = 0; j < SCAN_PER; ++j) {
-    const int64_t t = t0 + j;
-    if (t < ntiles) {
+    const int64_t t = tl[j];
+    if (t >= 0) {
       start_own[t] = run[0];
+      end_own[t] = run[0] + a[j];
       int32_t slot = -1;
       if (a[j]) slot = (int32_t)(a[j] > HEAVY_TILE ? run[1]++ : run[2]++);
       own_slot[t] = slot;
       if (slot >= 0) own_tiles[slot] = (uint32_t)t;
       if (b[j]) touch_tiles[run[3]++] = (uint32_t)t;
       run[0] += a[j];
+      cnt_own[t] = 0u;
+      cnt_touch[t] = 0u;
     }
   }
-#pragma unroll
-  for (int j = 0; j < SCAN_PER; j += 4)
-    if (t0 + j < ntiles) {
-      *reinterpret_cast<uint4*>(cnt_own + t0 + j) = make_uint4(0u, 0u, 0u, 0u);
-      *reinterpret_cast<uint4*>(cnt_touch + t0 + j) = make_uint4(0u, 0u, 0u, 0u);
-    }
   // this chunk's share of the force-block flags
   const int64_t per = (nbflag_words + gridDim.x - 1) / gridDim.x;
   const int64_t w1 = min(nbflag_words, per * (blockIdx.x + 1));
@@ -351,14 +386,15 @@ __global__ __launch_bounds__(SCAN_WG) void k_scan_write(
 }
 
 // Pass 3: move every point again (same arithmetic), store it at its slot in
-// owner-tile order and flag the 4^3 force blocks of its support.  FP64
-// partial sums of s and s |u_b|^2 per workgroup.
+// owner-tile order (in the temporaries t_base, t_frac, t_ub; k_tile_order
+// then orders each tile's points by cell) and flag the 4^3 force blocks of
+// its support.  FP64 partial sums of s and s |u_b|^2 per workgroup.
 __global__ __launch_bounds__(LBM_BLOCK) void k_point_scatter(
     const float4* __restrict__ rest, const int32_t* __restrict__ body_of,
     const BodyMotion* __restrict__ motion, int64_t npts, PointGeom pg,
     const uint32_t* __restrict__ key, const uint32_t* __restrict__ rank,
-    const uint32_t* __restrict__ start_own, int4* __restrict__ sp_base,
-    float4* __restrict__ sp_frac, float4* __restrict__ sp_ub, uint8_t* __restrict__ bflag,
+    const uint32_t* __restrict__ start_own, int4* __restrict__ t_base,
+    float4* __restrict__ t_frac, float4* __restrict__ t_ub, uint8_t* __restrict__ bflag,
     double* __restrict__ part_s, double* __restrict__ part_sub2) {
   const int64_t k = (int64_t)blockIdx.x * LBM_BLOCK + threadIdx.x;
   double ps_s = 0.0, ps_ub2 = 0.0;
@@ -366,9 +402,9 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_point_scatter(
     const float4 r4 = rest[k];
     const PointState ps = move_point(motion[body_of[k]], r4, pg);
     const uint32_t slot = start_own[key[k]] + rank[k];
-    sp_base[slot] = make_int4(ps.base[0], ps.base[1], ps.base[2], (int)k);
-    sp_frac[slot] = make_float4(ps.frac[0], ps.frac[1], ps.frac[2], r4.w);
-    sp_ub[slot] = make_float4(ps.ub[0], ps.ub[1], ps.ub[2], 0.0f);
+    t_base[slot] = make_int4(ps.base[0], ps.base[1], ps.base[2], (int)k);
+    t_frac[slot] = make_float4(ps.frac[0], ps.frac[1], ps.frac[2], r4.w);
+    t_ub[slot] = make_float4(ps.ub[0], ps.ub[1], ps.ub[2], 0.0f);
     // flag the force blocks of the support (idempotent byte stores)
     const Span1 fx = span_axis(ps.base[0], pg.n[0], pg.bc[0], FBLK_SHIFT);
     const Span1 fy = span_axis(ps.base[1], pg.n[1], pg.bc[1], FBLK_SHIFT);
@@ -429,9 +465,9 @@ __device__ __forceinline__ ListRange list_range(uint32_t n) {
 
 // Owner-tile entries of a sweep workgroup: the nh heavy tiles at the front
 // of the list go one per workgroup to the first workgroups of the launch
-// (dispatched first, spread over the XCDs); the others to the remaining
-// workgroups as in list_range.  A grid too small for that interleaves every
-// entry over all workgroups.
+// (dispatched first; each XCD takes a contiguous run of them); the others to
+// the remaining workgroups as in list_range.  A grid too small for that
+// interleaves every entry over all workgroups.
 struct OwnOrder {
   uint32_t h, h_end, h_step;
   ListRange l;
@@ -460,9 +496,12 @@ __device__ __forceinline__ OwnOrder own_order(uint32_t n, uint32_t nh) {
     o.h_step = G;
     return o;
   }
-  o.h = b;
-  o.h_end = nh;
-  o.h_step = G;
+  // heavy entries, one per workgroup b < H, in contiguous runs per XCD
+  // (workgroup b runs on XCD b mod 8)
+  const uint32_t he = (b & 7u) * (H / 8u) + (b >> 3);
+  o.h = he;
+  o.h_end = (b < H && he < nh) ? he + 1u : he;
+  o.h_step = 1u;
   if (b >= H) {
     const uint32_t m = n - nh, chunk = (m + 7u) / 8u, xcd = (b - H) & 7u;
     o.l.e = nh + xcd * chunk + ((b - H) >> 3);
@@ -478,18 +517,143 @@ __device__ __forceinline__ void tile_origin(const PointGeom& pg, uint32_t t, int
   o[2] = (int)(t / ((uint32_t)pg.tiles[0] * (uint32_t)pg.tiles[1])) * TILE;
 }
 
-// U (the forcing's velocity scratch) is stored tile-major: tile t holds its
-// 512 cells (x fastest) for component 0, then 1, then 2, so that a tile's
-// U is 6 KB of consecutive words.
-__device__ __forceinline__ int64_t u_index(uint32_t tile, int comp, int local) {
-  return ((int64_t)tile * 3 + comp) * TILE3 + local;
+// Workgroup-wide exclusive scan of one value per thread (CELL_WG threads).
+constexpr int CELL_WG = 256;
+__device__ __forceinline__ uint32_t block_scan1(uint32_t v, uint32_t* __restrict__ wtot) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t u = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += u;
+  }
+  if (lane == 63) wtot[wv] = inc;
+  __syncthreads();
+  uint32_t base = 0u;
+  for (int w = 0; w < wv; ++w) base += wtot[w];
+  __syncthreads();
+  return base + inc - v;
 }
-__device__ __forceinline__ int64_t u_index_cell(const PointGeom& pg, int x, int y, int z, int comp) {
+
+// Pass 4: the points of every owner tile ordered by their base cell (x
+// fastest), from the temporaries into sp_base, sp_frac and sp_ub, with the
+// LDS box index of the point's first tap in u_b's fourth word.  Lanes that
+// interpolate neighbouring slots then read the same or neighbouring LDS
+// words.  A counting sort in LDS: cell counts with the rank of each point
+// within its cell (the order of equal cells is that of the LDS atomics), an
+// exclusive scan over the 512 cells, the move.  The ranks of a thread's
+// first ORDER_KEEP points stay in registers, further ones go through `rank`
+// (free after the scatter).  Also the support mask of the tile's box (the
+// cells its points' taps reach), in the box slot.
+constexpr int ORDER_KEEP = 4;
+static_assert(TILE3 == 2 * CELL_WG, "two cells per thread");
+__global__ __launch_bounds__(CELL_WG) void k_tile_order(
+    const uint32_t* __restrict__ own_tiles, const uint32_t* __restrict__ meta,
+    const uint32_t* __restrict__ start_own, const uint32_t* __restrict__ end_own,
+    const int4* __restrict__ t_base, const float4* __restrict__ t_frac,
+    const float4* __restrict__ t_ub,
+    uint32_t* __restrict__ rank, int4* __restrict__ sp_base, float4* __restrict__ sp_frac,
+    float4* __restrict__ sp_ub, unsigned char* __restrict__ boxbuf) {
+  __shared__ uint32_t hist[TILE3];
+  __shared__ uint32_t wtot[CELL_WG / 64];
+  __shared__ uint32_t smask[BOX_MASK_WORDS];
+  __shared__ uint32_t drow[TILE * TILE];
+  const ListRange lr = list_range(meta[0]);
+  for (uint32_t e = lr.e; e < lr.end; e += lr.step) {
+    const uint32_t t = own_tiles[e];
+    const uint32_t p0 = start_own[t], P = end_own[t] - p0;
+    hist[threadIdx.x] = 0u;
+    hist[threadIdx.x + CELL_WG] = 0u;
+    if (threadIdx.x < BOX_MASK_WORDS) smask[threadIdx.x] = 0u;
+    __syncthreads();
+    uint32_t kr[ORDER_KEEP];
+    uint32_t j = 0;
+    for (uint32_t i = threadIdx.x; i < P; i += CELL_WG, ++j) {
+      const int4 b = t_base[p0 + i];
+      const int bb[3] = {b.x, b.y, b.z};
+      const uint32_t c = local_cell(bb);
+      const uint32_t r = atomicAdd(&hist[c], 1u);  // rank within the cell
+      if (j < ORDER_KEEP) {
+#pragma unroll
+        for (int q = 0; q < ORDER_KEEP; ++q)
+          if (q == (int)j) kr[q] = r;
+      } else {
+        rank[p0 + i] = r;
+      }
+    }
+    __syncthreads();
+    // the support mask: the tile's occupied cells dilated by the taps
+    // -1 .. +2 per axis; in box coordinates a point at cell l reaches box
+    // positions l .. l + 3.  Rows of 8 occupancy bits, dilated along x, then
+    // the 4 x 4 rows around each box row.
+    if (threadIdx.x < TILE * TILE) {
+      uint32_t occ = 0u;
+#pragma unroll
+      for (int lx = 0; lx < TILE; ++lx) occ |= (hist[lx + TILE * threadIdx.x] ? 1u : 0u) << lx;
+      drow[threadIdx.x] = occ | (occ << 1) | (occ << 2) | (occ << 3);
+    }
+    __syncthreads();
+    if (threadIdx.x < BOX * BOX) {
+      const int by = threadIdx.x % BOX, bz = threadIdx.x / BOX;
+      uint32_t m = 0u;
+#pragma unroll
+      for (int cz = 0; cz < 4; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 4; ++cy) {
+          const int ly = by - cy, lz = bz - cz;
+          if (ly >= 0 && ly < TILE && lz >= 0 && lz < TILE) m |= drow[ly + TILE * lz];
+        }
+      const int bit = BOX * threadIdx.x;  // first cell of box row (by, bz)
+      const int w = bit >> 5, sh = bit & 31;
+      if (m) {
+        atomicOr(&smask[w], m << sh);
+        if (sh > 32 - BOX) atomicOr(&smask[w + 1], m >> (32 - sh));
+      }
+    }
+    const uint32_t c0 = hist[2 * threadIdx.x], c1 = hist[2 * threadIdx.x + 1];
+    const uint32_t ex = block_scan1(c0 + c1, wtot);  // (synchronises)
+    hist[2 * threadIdx.x] = ex;
+    hist[2 * threadIdx.x + 1] = ex + c0;
+    __syncthreads();
+    j = 0;
+    for (uint32_t i = threadIdx.x; i < P; i += CELL_WG, ++j) {
+      uint32_t r = 0u;
+      if (j < ORDER_KEEP) {
+#pragma unroll
+        for (int q = 0; q < ORDER_KEEP; ++q)
+          if (q == (int)j) r = kr[q];
+      } else {
+        r = rank[p0 + i];
+      }
+      const int4 b = t_base[p0 + i];
+      const int bb[3] = {b.x, b.y, b.z};
+      const uint32_t dst = p0 + hist[local_cell(bb)] + r;
+      const float4 u = t_ub[p0 + i];
+      // box index of the tap (-1, -1, -1): the box starts one cell before the tile
+      const int l0 = (b.x & (TILE - 1)) + BOX * ((b.y & (TILE - 1)) + BOX * (b.z & (TILE - 1)));
+      sp_base[dst] = b;
+      sp_frac[dst] = t_frac[p0 + i];
+      sp_ub[dst] = make_float4(u.x, u.y, u.z, __int_as_float(l0));
+    }
+    __syncthreads();  // the mask is complete; hist is cleared for the next tile
+    if (threadIdx.x < BOX_MASK_WORDS)
+      reinterpret_cast<uint32_t*>(boxbuf + (int64_t)e * BOX_SLOT_BYTES + BOX_MASK_OFF)[threadIdx.x] =
+          smask[threadIdx.x];
+  }
+}
+
+// U (the forcing's velocity scratch) is stored tile-major, one float4
+// (x, y, z, 0) per cell: tile t holds its 512 cells (x fastest) as 8 KB of
+// consecutive memory, so that a cell is one 16-byte access.
+__device__ __forceinline__ int64_t u_index(uint32_t tile, int local) {
+  return (int64_t)tile * TILE3 + local;
+}
+__device__ __forceinline__ int64_t u_index_cell(const PointGeom& pg, int x, int y, int z) {
   const uint32_t t = (uint32_t)(x >> TILE_SHIFT) +
                      (uint32_t)pg.tiles[0] * ((uint32_t)(y >> TILE_SHIFT) +
                                               (uint32_t)pg.tiles[1] * (uint32_t)(z >> TILE_SHIFT));
   const int l = (x & (TILE - 1)) + TILE * ((y & (TILE - 1)) + TILE * (z & (TILE - 1)));
-  return u_index(t, comp, l);
+  return u_index(t, l);
 }
 
 // Velocity U = sum e f / rho (eq. 1) of the post-stream populations at one
@@ -498,7 +662,7 @@ __device__ __forceinline__ int64_t u_index_cell(const PointGeom& pg, int x, int 
 template <int S>
 __device__ __forceinline__ void cell_velocity(const typename Store<S>::T* __restrict__ lat,
                                               const LatticeGeom& g, const PointGeom& pg, int x,
-                                              int y, int z, float* __restrict__ U) {
+                                              int y, int z, float4* __restrict__ U) {
   float f[Q];
   gather_any<S>(lat, g, x, y, z, f);
   float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
@@ -510,29 +674,107 @@ __device__ __forceinline__ void cell_velocity(const typename Store<S>::T* __rest
     jz += EZ[i] * f[i];
   }
   const float inv = 1.0f / (1.0f + drho);
-  const int64_t c = u_index_cell(pg, x, y, z, 0);
-  U[c] = jx * inv;
-  U[c + TILE3] = jy * inv;
-  U[c + 2 * TILE3] = jz * inv;
+  U[u_index_cell(pg, x, y, z)] = make_float4(jx * inv, jy * inv, jz * inv, 0.0f);
 }
 
-// U pre-pass, tile-mask strategy (default): the flagged 4^3 blocks of every
-// touched tile, i.e. the paper's lbm_u_start limited to the blocks the
-// supports reach.  512 threads: one wave per 8x8 z-plane.
+// Boxes covering local coordinate l (0..7) of a tile along one axis when the
+// tile and both neighbours are full tiles without a wrap: the own tile's box
+// (position l + 1), the previous tile's when l <= 1 (position l + 9) and the
+// next tile's when l == 7 (position 0).  nd: tile offset, nb: box position.
+struct Cover1 {
+  int nd[2], nb[2], n;
+};
+__device__ __forceinline__ Cover1 simple_cover(int l) {
+  Cover1 c;
+  c.nd[0] = 0;
+  c.nb[0] = l + 1;
+  c.n = 1;
+  c.nd[1] = 0;
+  c.nb[1] = 0;
+  if (l <= 1) {
+    c.nd[1] = -1;
+    c.nb[1] = l + 9;
+    c.n = 2;
+  } else if (l == TILE - 1) {
+    c.nd[1] = 1;
+    c.n = 2;
+  }
+  return c;
+}
+
+// Whether tile coordinates tc and both neighbours on every axis are full
+// tiles without a periodic wrap (the fast covering of simple_cover holds).
+__device__ __forceinline__ bool simple_tile(const PointGeom& pg, const int tc[3]) {
+  bool simple = true;
+  for (int a = 0; a < 3; ++a) simple = simple && tc[a] >= 1 && (tc[a] + 2) * TILE <= pg.n[a];
+  return simple;
+}
+
+// Owner-list slots and support masks of the 27 tiles around tile tc (slot
+// -1 and an empty mask for a tile without points), into LDS; ends with a
+// barrier.
+template <int NT>
+__device__ __forceinline__ void load_neighbour_masks(const PointGeom& pg, const int tc[3],
+                                                     const int32_t* __restrict__ own_slot,
+                                                     const unsigned char* __restrict__ boxbuf,
+                                                     int32_t nslot[27],
+                                                     uint32_t nmask[27][BOX_MASK_WORDS]) {
+  if (threadIdx.x < 27) {
+    const int dx = threadIdx.x % 3 - 1, dy = (threadIdx.x / 3) % 3 - 1, dz = threadIdx.x / 9 - 1;
+    nslot[threadIdx.x] = own_slot[tile_index(pg, tc[0] + dx, tc[1] + dy, tc[2] + dz)];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 27 * BOX_MASK_WORDS; i += NT) {
+    const int nbr = i / BOX_MASK_WORDS, w = i - nbr * BOX_MASK_WORDS;
+    const int32_t slot = nslot[nbr];
+    nmask[nbr][w] = slot >= 0 ? reinterpret_cast<const uint32_t*>(
+                                    boxbuf + (int64_t)slot * BOX_SLOT_BYTES + BOX_MASK_OFF)[w]
+                              : 0u;
+  }
+  __syncthreads();
+}
+
+// U pre-pass, tile-mask strategy (default): the cells of the flagged 4^3
+// blocks of every touched tile, i.e. the paper's lbm_u_start limited to the
+// blocks the supports reach, and of those (away from seams and short axes)
+// only the cells that are a tap of some point: the union of the support
+// masks of the owner boxes covering the cell.  512 threads: one wave per 8x8
+// z-plane.
 template <int S>
 __global__ __launch_bounds__(TILE3) void k_moments_blocks(
     const typename Store<S>::T* __restrict__ lat, const LatticeGeom g, PointGeom pg,
     const uint32_t* __restrict__ touch_tiles, const uint32_t* __restrict__ meta,
-    const uint8_t* __restrict__ bflag, float* __restrict__ U) {
+    const uint8_t* __restrict__ bflag, const int32_t* __restrict__ own_slot,
+    const unsigned char* __restrict__ boxbuf, float4* __restrict__ U) {
+  __shared__ int32_t nslot[27];
+  __shared__ uint32_t nmask[27][BOX_MASK_WORDS];
   const ListRange lr = list_range(meta[1]);
   for (uint32_t e = lr.e; e < lr.end; e += lr.step) {
-    int o[3];
+    int o[3], tc[3];
     tile_origin(pg, touch_tiles[e], o);
-    const int x = o[0] + (threadIdx.x & (TILE - 1));
-    const int y = o[1] + ((threadIdx.x >> TILE_SHIFT) & (TILE - 1));
-    const int z = o[2] + (threadIdx.x >> (2 * TILE_SHIFT));
+    for (int a = 0; a < 3; ++a) tc[a] = o[a] / TILE;
+    const bool simple = simple_tile(pg, tc);
+    __syncthreads();  // the previous tile's masks are no longer read
+    if (simple) load_neighbour_masks<TILE3>(pg, tc, own_slot, boxbuf, nslot, nmask);
+    const int lx = threadIdx.x & (TILE - 1), ly = (threadIdx.x >> TILE_SHIFT) & (TILE - 1),
+              lz = threadIdx.x >> (2 * TILE_SHIFT);
+    const int x = o[0] + lx, y = o[1] + ly, z = o[2] + lz;
     if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
     if (!bflag[fblock_of(g, x, y, z)]) continue;
+    if (simple) {
+      const Cover1 cx = simple_cover(lx), cy = simple_cover(ly), cz = simple_cover(lz);
+      bool tap = false;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int jx = j & 1, jy = (j >> 1) & 1, jz = j >> 2;
+        if (jx < cx.n && jy < cy.n && jz < cz.n) {
+          const int ni = (cx.nd[jx] + 1) + 3 * (cy.nd[jy] + 1) + 9 * (cz.nd[jz] + 1);
+          const int bi = cx.nb[jx] + BOX * (cy.nb[jy] + BOX * cz.nb[jz]);
+          tap = tap || ((nmask[ni][bi >> 5] >> (bi & 31)) & 1u);
+        }
+      }
+      if (!tap) continue;
+    }
     cell_velocity<S>(lat, g, pg, x, y, z, U);
   }
 }
@@ -549,7 +791,7 @@ template <int S>
 __global__ __launch_bounds__(TILE3) void k_moments_box(
     const typename Store<S>::T* __restrict__ lat, const LatticeGeom g, PointGeom pg,
     const BodyMotion* __restrict__ motion, const float* __restrict__ ubox, int sub,
-    float* __restrict__ U) {
+    float4* __restrict__ U) {
   const int sub3 = sub * sub * sub;
   const int b = blockIdx.x / sub3, sblk = blockIdx.x - b * sub3;
   const BodyMotion m = motion[b];
@@ -598,7 +840,7 @@ __global__ __launch_bounds__(TILE3) void k_moments_box(
 template <int S>
 __global__ __launch_bounds__(WG) void k_moments_points(
     const typename Store<S>::T* __restrict__ lat, const LatticeGeom g, PointGeom pg,
-    const int4* __restrict__ sp_base, int64_t npts, float* __restrict__ U) {
+    const int4* __restrict__ sp_base, int64_t npts, float4* __restrict__ U) {
   const int64_t k = (int64_t)blockIdx.x * (WG / 64) + (threadIdx.x >> 6);
   if (k >= npts) return;
   const int lane = threadIdx.x & 63;
@@ -650,12 +892,6 @@ __device__ __forceinline__ void peskin4(float r, float w[4]) {
 // workgroup writes its FP64 partial of s |g|^2 when interpolating.
 constexpr float FIX_ONE = 1073741824.0f;  // 2^30
 
-// A stored spread box in its BOX_SLOT_BYTES slot of boxbuf: the packed x/y
-// sums of the 11^3 cells (64-bit, as accumulated), then the z sums (32-bit),
-// and the box's fixed-point unit B / 2^30 (FP32) in the slot's last word.
-constexpr int BOX_Z_OFF = BOX3 * 8;
-constexpr int BOX_UNIT_OFF = BOX_SLOT_BYTES - 4;
-static_assert(BOX_Z_OFF + BOX3 * 4 <= BOX_UNIT_OFF, "box slot too small");
 
 // Adds cell bi of a stored box to (s0, s1, s2): each sum times the unit.
 __device__ __forceinline__ void add_box_cell(const unsigned char* __restrict__ slot, int bi,
@@ -697,38 +933,223 @@ enum : int {
   SW_UNWEIGHTED = 16,
   SW_LOAD_PREV = 32,  // spreading du: take it from du_prev (caller order) into sp_du
   SW_SAVE_DU = 64,    // spreading du: also store it into du_prev (caller order)
+  SW_STORE_G = 128,   // interpolating: store every point's g into sp_g
 };
 
-// At most 64 VGPRs (8 waves per SIMD; the box and accumulators take 16 KB of
-// LDS per workgroup, so 8 workgroups fit a CU): measured slightly faster than
-// 7 waves and clearly faster than 6.
-__global__ __launch_bounds__(WG, 8) void k_sweep_tiles(
+// The box's U as one float4 (x, y, z, 0) per cell, padded to whole waves of
+// the staging (LDS direct loads write 64 consecutive cells per wave).
+constexpr int BOX3P = (BOX3 + 63) / 64 * 64;
+// Points whose spread vector a thread keeps in registers between the two
+// passes (its first KEEP points of the tile; the fraction is read again);
+// further points go through sp_g / sp_du.
+constexpr int KEEP = 2;
+
+struct KeptPoint {
+  int l0;            // box index of the point's tap (-1, -1, -1)
+  float v0, v1, v2;  // raw spread vector (g, or du when spreading du)
+};
+
+__device__ __forceinline__ float sel4(const float w[4], int c) {
+  return c == 0 ? w[0] : (c == 1 ? w[1] : (c == 2 ? w[2] : w[3]));
+}
+
+// The factor of a point's raw spread vector: s for the weighted inner sweep,
+// 1 for the unweighted one and for du.
+__device__ __forceinline__ float spread_weight(int mode, float s) {
+  return ((mode & SW_SPREAD_DU) || (mode & SW_UNWEIGHTED)) ? 1.0f : s;
+}
+
+// Range check and bound term of the vector vs v that a point spreads.
+__device__ __forceinline__ void spread_bound(const KeptPoint& kp, float vs,
+                                             unsigned long long& bsum, uint32_t* __restrict__ bad) {
+  const float a0 = vs * kp.v0, a1 = vs * kp.v1, a2 = vs * kp.v2;
+  spread_guard(a0, a1, a2, bad);
+  bsum += bound_units(fmaxf(fabsf(a0), fmaxf(fabsf(a1), fabsf(a2))));
+}
+
+// The interpolation pass of one point (§3; Algorithm 1): u = sum_taps U W
+// from the staged box, g = u_b - u, du = (first ? 0 : du) + s g (stored);
+// returns the raw spread vector and adds the residual and bound terms.
+__device__ __forceinline__ KeptPoint interp_point(
+    uint32_t k, const float4* __restrict__ sU, const float4* __restrict__ sp_frac,
+    const float4* __restrict__ sp_ub, float4* __restrict__ sp_g, float4* __restrict__ sp_du,
+    const int4* __restrict__ sp_base, float4* __restrict__ g_orig, int mode, bool store_g,
+    double& res, unsigned long long& bsum, uint32_t* __restrict__ bad) {
+  const float4 fr = sp_frac[k];
+  const float4 ub = sp_ub[k];
+  KeptPoint kp;
+  kp.l0 = __float_as_int(ub.w);
+  float wx[4], wy[4], wz[4];
+  peskin4(fr.x, wx);
+  peskin4(fr.y, wy);
+  peskin4(fr.z, wz);
+  float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+#pragma unroll 1
+  for (int cz = 0; cz < 4; ++cz) {
+    const float wzc = sel4(wz, cz);
+#pragma unroll
+    for (int cy = 0; cy < 4; ++cy) {
+      const float wyz = wzc * wy[cy];
+      const int row = kp.l0 + BOX * (cy + BOX * cz);
+#pragma unroll
+      for (int cx = 0; cx < 4; ++cx) {
+        const float w = wyz * wx[cx];
+        const float4 u = sU[row + cx];
+        u0 += w * u.x;
+        u1 += w * u.y;
+        u2 += w * u.z;
+      }
+    }
+  }
+  const float g0 = ub.x - u0, g1 = ub.y - u1, g2 = ub.z - u2;
+  const float s = fr.w;
+  float4 du = (mode & SW_FIRST) ? make_float4(0.f, 0.f, 0.f, 0.f) : sp_du[k];
+  du.x += s * g0;
+  du.y += s * g1;
+  du.z += s * g2;
+  du.w = 0.0f;
+  sp_du[k] = du;
+  if (store_g) sp_g[k] = make_float4(g0, g1, g2, 0.0f);
+  if (g_orig) g_orig[sp_base[k].w] = make_float4(g0, g1, g2, 0.0f);
+  res += (double)s * ((double)g0 * g0 + (double)g1 * g1 + (double)g2 * g2);
+  const bool spread_du = mode & SW_SPREAD_DU;
+  kp.v0 = spread_du ? du.x : g0;
+  kp.v1 = spread_du ? du.y : g1;
+  kp.v2 = spread_du ? du.z : g2;
+  const float vs = spread_weight(mode, s);
+  const float a0 = vs * kp.v0, a1 = vs * kp.v1, a2 = vs * kp.v2;
+  if (mode & (SW_SPREAD_G | SW_SPREAD_DU)) spread_guard(a0, a1, a2, bad);
+  bsum += bound_units(fmaxf(fabsf(a0), fmaxf(fabsf(a1), fabsf(a2))));
+  return kp;
+}
+
+// The raw spread vector of a point when no interpolation runs this sweep
+// (spreading a predicted or previous du) or when the interpolation pass
+// stored it: from sp_du or sp_g, or from du_prev in the caller's order (then
+// also stored into sp_du).
+__device__ __forceinline__ KeptPoint load_point(uint32_t k, const float4* __restrict__ sp_ub,
+                                                const float4* __restrict__ sp_g,
+                                                float4* __restrict__ sp_du,
+                                                const int4* __restrict__ sp_base,
+                                                const float4* __restrict__ du_prev, int mode) {
+  KeptPoint kp;
+  kp.l0 = __float_as_int(sp_ub[k].w);
+  float4 v;
+  if (mode & SW_SPREAD_DU) {
+    if (mode & SW_LOAD_PREV) {
+      v = du_prev[sp_base[k].w];
+      sp_du[k] = v;  // read again only by later launches or this thread
+    } else {
+      v = sp_du[k];
+    }
+  } else {
+    v = sp_g[k];
+  }
+  kp.v0 = v.x;
+  kp.v1 = v.y;
+  kp.v2 = v.z;
+  return kp;
+}
+
+// Fixed-point spread of one point into the LDS accumulators: the raw vector
+// times f (its weight times the box scale) times each tap weight, rounded to
+// the fixed-point unit.  Lanes holding points of the same cell (the slots
+// are in cell order) start at different rows of the 4 x 4 (y, z) tap rows,
+// so that they rarely add into the same word at the same time.
+__device__ __forceinline__ void spread_point(const KeptPoint& kp, float4 fr, float f,
+                                             unsigned long long* __restrict__ accxy,
+                                             int* __restrict__ accz, int rot) {
+  float wx[4], wy[4], wz[4];
+  peskin4(fr.x, wx);
+  peskin4(fr.y, wy);
+  peskin4(fr.z, wz);
+  const float v0 = kp.v0 * f, v1 = kp.v1 * f, v2 = kp.v2 * f;
+  // the x weights times the vector, once per point: a tap's value is then
+  // one product per component, wz wy (wx v)
+  float ax[4], ay[4], az[4];
+#pragma unroll
+  for (int cx = 0; cx < 4; ++cx) {
+    ax[cx] = wx[cx] * v0;
+    ay[cx] = wx[cx] * v1;
+    az[cx] = wx[cx] * v2;
+  }
+#pragma unroll 1
+  for (int j = 0; j < 16; ++j) {
+    const int rr = (j + rot) & 15;
+    const int cy = rr & 3, cz = rr >> 2;
+    const float wyz = sel4(wz, cz) * sel4(wy, cy);
+    const int row = kp.l0 + BOX * (cy + BOX * cz);
+#pragma unroll
+    for (int cx = 0; cx < 4; ++cx) {
+      const int ix = __float2int_rn(wyz * ax[cx]), iy = __float2int_rn(wyz * ay[cx]);
+      // x sign-extended in the low word, y added into the high word
+      atomicAdd(&accxy[row + cx], (unsigned long long)(long long)ix +
+                                      ((unsigned long long)(uint32_t)iy << 32));
+      atomicAdd(&accz[row + cx], __float2int_rn(wyz * az[cx]));
+    }
+  }
+}
+
+// One sweep of the multi-direct forcing for the points of one owner tile
+// (§3; Algorithms 1 and 2), in parts chosen by the mode bits:
+//   SW_INTERP:  u = sum_taps U W, g = u_b - u, du = (first ? 0 : du) + s g
+//                                                                   (Alg. 1)
+//   SW_SPREAD_G / SW_SPREAD_DU: the spread vector
+//               v = s g (inner sweep), g (SW_UNWEIGHTED: paper-literal inner
+//               sweep) or du (last sweep, or a predicted warm start), and
+//               box(X) = sum_k v(k) W_k(X) over the tile's points     (Alg. 2)
+// With neither spread bit only the interpolation runs; with SW_INTERP clear
+// only the spread.  g_orig (nullable) receives g in the caller's order.
+// U is staged, by LDS direct loads, over the 11^3 box [o-1, o+10)^3 that
+// holds every tap of the tile's points (coordinates wrapped on periodic
+// axes).  The box sum is accumulated in LDS in fixed point with the unit
+// B / 2^30, where B = (1/8) sum_k max_c |v_k,c| bounds every box cell (a tap
+// weight is at most 1/8; the sum is formed exactly in fixed point,
+// bound_units): no overflow is possible while every |v_k,c| is finite and at
+// most SPREAD_CAP (else the status word is raised), and integer addition
+// makes the box independent of the order of the atomics and of the points.
+// Components x and y share one 64-bit atomic (x sign-extended in the low
+// word, y in the high word: the 64-bit sum is exactly sum_y 2^32 + sum_x,
+// and |sum_x| < 2^31 recovers both), z has its own 32-bit one.  The box is
+// stored as these integer sums with its unit in the tile's slot of boxbuf
+// (box_slot layout); the merge converts them.
+//
+// A thread handles the points i = threadIdx.x + WG j of the tile (in cell
+// order, see k_tile_order) in both passes; the spread vectors of its first
+// KEEP points stay in registers.  Each workgroup takes a stride of the
+// owner-tile list (contiguous per XCD; one tile per workgroup unless the
+// list is longer than the grid).  A nonzero *gate (the forcing has
+// converged) makes the launch a no-op.  Each workgroup writes its FP64
+// partial of s |g|^2 when interpolating.
+//
+// 21 KB of LDS per workgroup: 7 workgroups of 4 waves fit a CU.
+__global__ __launch_bounds__(WG, 7) void k_sweep_tiles(
     const uint32_t* __restrict__ own_tiles, const uint32_t* __restrict__ meta,
-    const uint32_t* __restrict__ start_own, const int4* __restrict__ sp_base,
-    const float4* __restrict__ sp_frac, const float4* __restrict__ sp_ub,
-    float4* __restrict__ sp_g, float4* __restrict__ sp_du, const float* __restrict__ U,
-    unsigned char* __restrict__ boxbuf, PointGeom pg, int mode, double* __restrict__ part_res,
-    const uint32_t* __restrict__ gate, float4* __restrict__ g_orig, float4* __restrict__ du_prev,
-    uint32_t* __restrict__ bad) {
+    const uint32_t* __restrict__ start_own, const uint32_t* __restrict__ end_own,
+    const int4* __restrict__ sp_base, const float4* __restrict__ sp_frac,
+    const float4* __restrict__ sp_ub, float4* __restrict__ sp_g, float4* __restrict__ sp_du,
+    const float4* __restrict__ U, unsigned char* __restrict__ boxbuf, PointGeom pg, int mode,
+    double* __restrict__ part_res, const uint32_t* __restrict__ gate, float4* __restrict__ g_orig,
+    float4* __restrict__ du_prev, uint32_t* __restrict__ bad) {
   // U of the box during the interpolation, then (same storage) the integer
   // accumulators of the spread: x and y packed in 64 bits, z in 32 bits
-  __shared__ __align__(16) float sU[3][BOX3];
-  unsigned long long* accxy = reinterpret_cast<unsigned long long*>(&sU[0][0]);
-  int* accz = reinterpret_cast<int*>(&sU[0][0]) + 2 * BOX3;
+  __shared__ __align__(16) float4 sU[BOX3P];
+  unsigned long long* accxy = reinterpret_cast<unsigned long long*>(sU);
+  int* accz = reinterpret_cast<int*>(accxy + BOX3);
+  static_assert(BOX3 * 12 <= BOX3P * 16, "accumulators fit the staged box");
   __shared__ unsigned long long bred[WG / 64];
   __shared__ double dred[WG / 64];
-  // index of the box's cells in the tile-major U: a sum of one term per
-  // axis (the wrapped coordinate's tile times the tile stride plus its
+  // float4 index of the box's cells in the tile-major U: a sum of one term
+  // per axis (the wrapped coordinate's tile times the tile stride plus its
   // position in the tile), tabulated once per tile
-  __shared__ int64_t uoff[3][BOX];
+  __shared__ uint32_t uoff[3][BOX];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (gate && *gate) return;  // the forcing has already converged
   const bool interp = mode & SW_INTERP;
-  const bool spread_g = mode & SW_SPREAD_G, spread_du = mode & SW_SPREAD_DU;
-  const bool spread = spread_g || spread_du;
-  const bool inner_weighted = !(mode & SW_UNWEIGHTED);
-  const bool load_prev = spread_du && (mode & SW_LOAD_PREV);
+  const bool spread = mode & (SW_SPREAD_G | SW_SPREAD_DU);
+  const bool spread_du = mode & SW_SPREAD_DU;
   const bool save_du = spread_du && (mode & SW_SAVE_DU);
+  const bool store_g = mode & SW_STORE_G;
   double res = 0.0;  // this thread's part of sum s |g|^2 over the workgroup's tiles
   OwnOrder order = own_order(meta[0], meta[2]);
   uint32_t e;
@@ -740,83 +1161,56 @@ __global__ __launch_bounds__(WG, 8) void k_sweep_tiles(
     if (interp && threadIdx.x < 3 * BOX) {
       const int a = threadIdx.x / BOX, b = threadIdx.x - a * BOX;
       const int v = tap_coord(o[a] - 1 + b, pg.n[a], pg.bc[a]);
-      const int64_t tstride = a == 0 ? 1 : (a == 1 ? (int64_t)pg.tiles[0]
-                                                   : (int64_t)pg.tiles[0] * pg.tiles[1]);
-      uoff[a][b] = (int64_t)(v >> TILE_SHIFT) * tstride * (3 * TILE3) +
-                   ((v & (TILE - 1)) << (TILE_SHIFT * a));
+      const uint32_t tstride = a == 0 ? 1u : (a == 1 ? (uint32_t)pg.tiles[0]
+                                                     : (uint32_t)pg.tiles[0] * pg.tiles[1]);
+      uoff[a][b] = (uint32_t)(v >> TILE_SHIFT) * tstride * TILE3 +
+                   ((uint32_t)(v & (TILE - 1)) << (TILE_SHIFT * a));
     }
     __syncthreads();
-#pragma unroll 2
-    for (int i = threadIdx.x; interp && i < BOX3; i += WG) {
-      const int bz = i / (BOX * BOX), r = i - bz * (BOX * BOX);
-      const int by = r / BOX, bx = r - by * BOX;
-      const float* u = U + (uoff[0][bx] + uoff[1][by] + uoff[2][bz]);
-      sU[0][i] = u[0];
-      sU[1][i] = u[TILE3];
-      sU[2][i] = u[2 * TILE3];
-    }
-    __syncthreads();
-    const uint32_t p0 = start_own[t], p1 = start_own[t + 1];
-    const uint32_t P = p1 - p0;
-    // pass 1: interpolation, deficit, correction (or, spreading only, the
-    // bound of the spread vector)
-    unsigned long long bsum = 0ull;  // in units of 2^-32 (see bound_units)
-    for (uint32_t k = p0 + threadIdx.x; !interp && k < p1; k += WG) {
-      const float4 fr = sp_frac[k];
-      float4 v;
-      if (load_prev) {
-        v = du_prev[sp_base[k].w];
-        sp_du[k] = v;  // read again only by later launches
-      } else {
-        v = spread_du ? sp_du[k] : sp_g[k];
+    if (interp) {
+      // wave w stages the 64-cell chunks w, w + 4, ...; the padding lanes of
+      // the last chunk load cell 0 again into the unused tail
+      for (int j = wave; j < BOX3P / 64; j += WG / 64) {
+        const int i = j * 64 + lane;
+        const int ii = i < BOX3 ? i : 0;
+        const int bz = ii / (BOX * BOX), r = ii - bz * (BOX * BOX);
+        const int by = r / BOX, bx = r - by * BOX;
+        const float4* src = U + (uoff[0][bx] + uoff[1][by] + uoff[2][bz]);
+        __builtin_amdgcn_global_load_lds(
+            src, (__attribute__((address_space(3))) void*)(sU + __builtin_amdgcn_readfirstlane(j * 64)),
+            16, 0, 0);
       }
-      const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
-      spread_guard(vs * v.x, vs * v.y, vs * v.z, bad);
-      bsum += bound_units(vs * fmaxf(fabsf(v.x), fmaxf(fabsf(v.y), fabsf(v.z))));
+      __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0): this wave's loads have landed in LDS
     }
-    for (uint32_t i = threadIdx.x; interp && i < P; i += WG) {
-      const uint32_t k = p0 + i;
-      const int4 b = sp_base[k];
-      const float4 fr = sp_frac[k];
-      float wx[4], wy[4], wz[4];
-      peskin4(fr.x, wx);
-      peskin4(fr.y, wy);
-      peskin4(fr.z, wz);
-      // box index of tap (-1, -1, -1): the box starts one cell before the tile
-      const int l0 = (b.x - o[0]) + BOX * ((b.y - o[1]) + BOX * (b.z - o[2]));
-      float u0 = 0.f, u1 = 0.f, u2 = 0.f;
-#pragma unroll 1
-      for (int cz = 0; cz < 4; ++cz) {
-        const float wzc = cz == 0 ? wz[0] : (cz == 1 ? wz[1] : (cz == 2 ? wz[2] : wz[3]));
+    __syncthreads();
+    const uint32_t p0 = start_own[t], P = end_own[t] - p0;
+    // pass 1: interpolation, deficit, correction (or, spreading only, the
+    // spread vectors); each thread keeps its first KEEP points
+    unsigned long long bsum = 0ull;  // in units of 2^-32 (see bound_units)
+    KeptPoint keep[KEEP];
 #pragma unroll
-        for (int cy = 0; cy < 4; ++cy) {
-          const float wyz = wzc * wy[cy];
-          const int row = l0 + BOX * (cy + BOX * cz);
-#pragma unroll
-          for (int cx = 0; cx < 4; ++cx) {
-            const float w = wyz * wx[cx];
-            u0 += w * sU[0][row + cx];
-            u1 += w * sU[1][row + cx];
-            u2 += w * sU[2][row + cx];
-          }
+    for (int q = 0; q < KEEP; ++q) {
+      const uint32_t i = threadIdx.x + q * WG;
+      keep[q].l0 = 0;
+      if (i < P) {
+        if (interp) {
+          keep[q] = interp_point(p0 + i, sU, sp_frac, sp_ub, sp_g, sp_du, sp_base, g_orig, mode,
+                                 store_g, res, bsum, bad);
+        } else {
+          keep[q] = load_point(p0 + i, sp_ub, sp_g, sp_du, sp_base, du_prev, mode);
+          spread_bound(keep[q], spread_weight(mode, sp_frac[p0 + i].w), bsum, bad);
         }
       }
-      const float4 ub = sp_ub[k];
-      const float g0 = ub.x - u0, g1 = ub.y - u1, g2 = ub.z - u2;
-      float4 du = (mode & SW_FIRST) ? make_float4(0.f, 0.f, 0.f, 0.f) : sp_du[k];
-      du.x += fr.w * g0;
-      du.y += fr.w * g1;
-      du.z += fr.w * g2;
-      du.w = 0.0f;
-      sp_g[k] = make_float4(g0, g1, g2, 0.0f);
-      sp_du[k] = du;
-      if (g_orig) g_orig[b.w] = make_float4(g0, g1, g2, 0.0f);
-      res += (double)fr.w * ((double)g0 * g0 + (double)g1 * g1 + (double)g2 * g2);
-      const float vs = spread_du ? 1.0f : (inner_weighted ? fr.w : 1.0f);
-      const float v0 = spread_du ? du.x : vs * g0, v1 = spread_du ? du.y : vs * g1,
-                  v2 = spread_du ? du.z : vs * g2;
-      if (spread) spread_guard(v0, v1, v2, bad);
-      bsum += bound_units(fmaxf(fabsf(v0), fmaxf(fabsf(v1), fabsf(v2))));
+    }
+    for (uint32_t i = threadIdx.x + KEEP * WG; i < P; i += WG) {
+      if (interp) {
+        // the spread pass reads this point's vector back from sp_g / sp_du
+        (void)interp_point(p0 + i, sU, sp_frac, sp_ub, sp_g, sp_du, sp_base, g_orig, mode,
+                           store_g || (spread && !spread_du), res, bsum, bad);
+      } else {
+        const KeptPoint kp = load_point(p0 + i, sp_ub, sp_g, sp_du, sp_base, du_prev, mode);
+        spread_bound(kp, spread_weight(mode, sp_frac[p0 + i].w), bsum, bad);
+      }
     }
     if (!spread) continue;
     // block bound B: an exact integer sum, whatever the order of the points
@@ -834,69 +1228,21 @@ __global__ __launch_bounds__(WG, 8) void k_sweep_tiles(
       accz[i] = 0;
     }
     __syncthreads();
-    // pass 2: spread into the box (every tap of an owned point is inside
-    // it).  Neighbouring slots hold neighbouring points, which add into the
-    // same LDS words tap after tap; a stride coprime to the point count deals
-    // them to the lanes in scattered order, and each lane starts at its own
-    // z-plane.
-    const uint32_t L = P;
-    const uint32_t stride = (L % 97u) ? 97u : 89u;
-    const uint32_t step = L ? (uint32_t)(((uint64_t)WG * stride) % L) : 0u;
-    uint32_t pos = L ? (uint32_t)(((uint64_t)threadIdx.x * stride) % L) : 0u;
-    const int zrot = lane & 3;
-    for (uint32_t i = threadIdx.x; i < L; i += WG) {
-      const uint32_t k = p0 + pos;
-      pos += step;
-      if (pos >= L) pos -= L;
-      const int4 b = sp_base[k];
+    // pass 2: spread into the box (every tap of an owned point is inside it)
+    const int rot = lane & 15;
+    auto spread_one = [&](const KeptPoint& kp, uint32_t k) {
       const float4 fr = sp_frac[k];
-      float v0, v1, v2;
-      if (spread_du) {
-        const float4 du = load_prev ? du_prev[b.w] : sp_du[k];
-        if (save_du) du_prev[b.w] = du;
-        v0 = du.x * scale;
-        v1 = du.y * scale;
-        v2 = du.z * scale;
-      } else {
-        const float4 g = sp_g[k];
-        const float vs = (inner_weighted ? fr.w : 1.0f) * scale;
-        v0 = g.x * vs;
-        v1 = g.y * vs;
-        v2 = g.z * vs;
-      }
-      float wx[4], wy[4], wz[4];
-      peskin4(fr.x, wx);
-      peskin4(fr.y, wy);
-      peskin4(fr.z, wz);
-      // the x weights times the vector, once per point: a tap's value is
-      // then one product per component, wz wy (wx v)
-      float ax[4], ay[4], az[4];
+      if (save_du) du_prev[sp_base[k].w] = make_float4(kp.v0, kp.v1, kp.v2, 0.f);
+      spread_point(kp, fr, spread_weight(mode, fr.w) * scale, accxy, accz, rot);
+    };
 #pragma unroll
-      for (int cx = 0; cx < 4; ++cx) {
-        ax[cx] = wx[cx] * v0;
-        ay[cx] = wx[cx] * v1;
-        az[cx] = wx[cx] * v2;
-      }
-      const int l0 = (b.x - o[0]) + BOX * ((b.y - o[1]) + BOX * (b.z - o[2]));
-#pragma unroll 1
-      for (int jz = 0; jz < 4; ++jz) {
-        const int cz = (jz + zrot) & 3;
-        const float wzc = cz == 0 ? wz[0] : (cz == 1 ? wz[1] : (cz == 2 ? wz[2] : wz[3]));
-#pragma unroll
-        for (int cy = 0; cy < 4; ++cy) {
-          const float wyz = wzc * wy[cy];
-          const int row = l0 + BOX * (cy + BOX * cz);
-#pragma unroll
-          for (int cx = 0; cx < 4; ++cx) {
-            const int ix = __float2int_rn(wyz * ax[cx]), iy = __float2int_rn(wyz * ay[cx]);
-            // x sign-extended in the low word, y added into the high word
-            atomicAdd(&accxy[row + cx], (unsigned long long)(long long)ix +
-                                            ((unsigned long long)(uint32_t)iy << 32));
-            atomicAdd(&accz[row + cx], __float2int_rn(wyz * az[cx]));
-          }
-        }
-      }
+    for (int q = 0; q < KEEP; ++q) {
+      const uint32_t i = threadIdx.x + q * WG;
+      if (i < P) spread_one(keep[q], p0 + i);
     }
+    for (uint32_t i = threadIdx.x + KEEP * WG; i < P; i += WG)
+      spread_one(load_point(p0 + i, sp_ub, sp_g, sp_du, sp_base, du_prev, mode & ~SW_LOAD_PREV),
+                 p0 + i);
     __syncthreads();
     unsigned char* slot = boxbuf + (int64_t)e * BOX_SLOT_BYTES;
     unsigned long long* sxy = reinterpret_cast<unsigned long long*>(slot);
@@ -944,15 +1290,18 @@ __device__ __forceinline__ int covering(int x, int n, int bc, int ntiles_axis, i
 // Merge of the stored boxes into one touched tile: for every cell of a
 // flagged force block, the sum over the boxes that cover it (fixed order):
 //   mode 0: U += sum on cells with a nonzero sum;   mode 2: G = sum.
+// (x + 0 = x exactly, so skipping zero sums changes no value of U.)
 constexpr int MERGE_WG = 256;
 __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
     const uint32_t* __restrict__ touch_tiles, const uint32_t* __restrict__ meta,
     const int32_t* __restrict__ own_slot, const unsigned char* __restrict__ boxbuf,
-    const uint8_t* __restrict__ bflag, float* __restrict__ target, PointGeom pg, int mode,
-    const uint32_t* __restrict__ gate) {
+    const uint8_t* __restrict__ bflag, float* __restrict__ G, float4* __restrict__ U,
+    PointGeom pg, int mode, const uint32_t* __restrict__ gate) {
   __shared__ int16_t ct[3][TILE][MAXCOV], cb[3][TILE][MAXCOV];
   __shared__ int cn[3][TILE];
   __shared__ int32_t nslot[27];
+  __shared__ float nunit[27];
+  __shared__ uint8_t tflag[8];
   if (gate && *gate) return;  // the forcing has already converged
   const ListRange lr = list_range(meta[1]);
   for (uint32_t e = lr.e; e < lr.end; e += lr.step) {
@@ -968,10 +1317,22 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
     bool simple = true;
     for (int a = 0; a < 3; ++a)
       simple = simple && tc[a] >= 1 && (tc[a] + 2) * TILE <= pg.n[a];
-    if (simple) {  // list slots of the 27 tiles around this one
+    if (simple) {
+      // list slots and box units of the 27 tiles around this one, and the
+      // flags of the tile's eight force blocks
       if (threadIdx.x < 27) {
         const int dx = threadIdx.x % 3 - 1, dy = (threadIdx.x / 3) % 3 - 1, dz = threadIdx.x / 9 - 1;
-        nslot[threadIdx.x] = own_slot[tile_index(pg, tc[0] + dx, tc[1] + dy, tc[2] + dz)];
+        const int32_t slot = own_slot[tile_index(pg, tc[0] + dx, tc[1] + dy, tc[2] + dz)];
+        nslot[threadIdx.x] = slot;
+        nunit[threadIdx.x] =
+            slot >= 0 ? *reinterpret_cast<const float*>(boxbuf + (int64_t)slot * BOX_SLOT_BYTES +
+                                                        BOX_UNIT_OFF)
+                      : 0.0f;
+      } else if (threadIdx.x >= 64 && threadIdx.x < 72) {
+        const int b = threadIdx.x - 64;
+        const int bx = (o[0] >> FBLK_SHIFT) + (b & 1), by = (o[1] >> FBLK_SHIFT) + ((b >> 1) & 1),
+                  bz = (o[2] >> FBLK_SHIFT) + (b >> 2);
+        tflag[b] = bflag[(int64_t)bx + (int64_t)pg.fblk[0] * ((int64_t)by + (int64_t)pg.fblk[1] * bz)];
       }
       __syncthreads();
     } else {  // general covering tables (short axes, seams, short tiles)
@@ -989,9 +1350,14 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
       if (x >= pg.n[0] || y >= pg.n[1] || z >= pg.n[2]) continue;
       // only cells of flagged force blocks can receive a contribution, and
       // only there is G read by the stream-collide
-      if (!bflag[(int64_t)(x >> FBLK_SHIFT) +
-                 (int64_t)pg.fblk[0] * ((int64_t)(y >> FBLK_SHIFT) + (int64_t)pg.fblk[1] * (z >> FBLK_SHIFT))])
+      if (simple ? !tflag[(lx >> FBLK_SHIFT) + 2 * ((ly >> FBLK_SHIFT) + 2 * (lz >> FBLK_SHIFT))]
+                 : !bflag[(int64_t)(x >> FBLK_SHIFT) +
+                          (int64_t)pg.fblk[0] * ((int64_t)(y >> FBLK_SHIFT) +
+                                                 (int64_t)pg.fblk[1] * (z >> FBLK_SHIFT))])
         continue;
+      float4* uc = U + u_index(t, cell);
+      // the old U is loaded with the boxes (latency overlapped)
+      const float4 uold = mode == 2 ? make_float4(0.f, 0.f, 0.f, 0.f) : *uc;
       float s0 = 0.f, s1 = 0.f, s2 = 0.f;
       if (simple) {
         const int l[3] = {lx, ly, lz};
@@ -1012,18 +1378,39 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
             nn[a] = 2;
           }
         }
+        // every covering box's sums are loaded before any is added (all loads
+        // in flight at once); absent boxes contribute exactly zero, which
+        // leaves the sums bit-identical to skipping them
+        unsigned long long xy[8];
+        int zz[8];
+        float un[8];
   #pragma unroll
-        for (int jz = 0; jz < 2; ++jz)
+        for (int j = 0; j < 8; ++j) {
+          const int jx = j & 1, jy = (j >> 1) & 1, jz = j >> 2;
+          const bool in = jx < nn[0] && jy < nn[1] && jz < nn[2];
+          const int ni = (nd[0][jx] + 1) + 3 * (nd[1][jy] + 1) + 9 * (nd[2][jz] + 1);
+          const int32_t slot = in ? nslot[ni] : -1;
+          xy[j] = 0ull;
+          zz[j] = 0;
+          un[j] = 0.0f;
+          if (slot >= 0) {
+            const unsigned char* sl = boxbuf + (int64_t)slot * BOX_SLOT_BYTES;
+            const int bi = nb[0][jx] + BOX * (nb[1][jy] + BOX * nb[2][jz]);
+            xy[j] = reinterpret_cast<const unsigned long long*>(sl)[bi];
+            zz[j] = reinterpret_cast<const int*>(sl + BOX_Z_OFF)[bi];
+            un[j] = nunit[ni];
+          }
+        }
   #pragma unroll
-          for (int jy = 0; jy < 2; ++jy)
-  #pragma unroll
-            for (int jx = 0; jx < 2; ++jx) {
-              if (jx >= nn[0] || jy >= nn[1] || jz >= nn[2]) continue;
-              const int32_t slot = nslot[(nd[0][jx] + 1) + 3 * (nd[1][jy] + 1) + 9 * (nd[2][jz] + 1)];
-              if (slot < 0) continue;
-              const int bi = nb[0][jx] + BOX * (nb[1][jy] + BOX * nb[2][jz]);
-              add_box_cell(boxbuf + (int64_t)slot * BOX_SLOT_BYTES, bi, s0, s1, s2);
-            }
+        for (int j = 0; j < 8; ++j) {
+          const int sx = (int)(uint32_t)xy[j];
+          const int sy = (int)(uint32_t)((xy[j] - (unsigned long long)(long long)sx) >> 32);
+          if (un[j] != 0.0f) {
+            s0 += (float)sx * un[j];
+            s1 += (float)sy * un[j];
+            s2 += (float)zz[j] * un[j];
+          }
+        }
       } else {
         const int nx_ = cn[0][lx], ny_ = cn[1][ly], nz_ = cn[2][lz];
         for (int jz = 0; jz < nz_; ++jz)
@@ -1038,14 +1425,11 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
       }
       if (mode == 2) {  // G, in the lattice layout read by the stream-collide
         const int64_t c = (int64_t)x + (int64_t)pg.n[0] * ((int64_t)y + (int64_t)pg.n[1] * z);
-        target[c] = s0;
-        target[pg.ncell + c] = s1;
-        target[2 * pg.ncell + c] = s2;
+        G[c] = s0;
+        G[pg.ncell + c] = s1;
+        G[2 * pg.ncell + c] = s2;
       } else if (s0 != 0.0f || s1 != 0.0f || s2 != 0.0f) {  // U, tile-major
-        const int64_t c = u_index(t, 0, cell);
-        target[c] += s0;
-        target[c + TILE3] += s1;
-        target[c + 2 * TILE3] += s2;
+        *uc = make_float4(uold.x + s0, uold.y + s1, uold.z + s2, uold.w);
       }
     }
   }
@@ -1230,9 +1614,17 @@ hipError_t launch_u_prepass(lbm_ctx* c, const typename Store<S>::T* lat, const P
                                                          c->U);
   } else {
     k_moments_blocks<S><<<tg, TILE3, 0, st>>>(lat, c->geom, pg, c->touch_tiles, c->meta,
-                                              c->bflag, c->U);
+                                              c->bflag, c->own_slot,
+                                              (const unsigned char*)c->boxbuf, c->U);
   }
   return hipGetLastError();
+}
+
+// Positions of the tile scan: the tile grid padded to whole 4 x 4 x 4 blocks.
+int64_t scan_positions(const lbm_ctx* c) {
+  int64_t n = 1;
+  for (int a = 0; a < 3; ++a) n *= (c->tiles[a] + SB - 1) / SB * SB;
+  return n;
 }
 
 // The forcing of one time step: motion, binning, U near the surface,
@@ -1260,23 +1652,30 @@ hipError_t launch_forcing(lbm_ctx* c) {
                                           c->cnt_own, c->cnt_touch);
   LAUNCH_CHECK();
   {
-    const int64_t nch = (c->ntiles + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    const int64_t nch = (scan_positions(c) + SCAN_CHUNK - 1) / SCAN_CHUNK;
     // a pending host copy of the lengths is not overwritten before it is read
     uint32_t* mh = c->meta_pending ? nullptr : c->meta_host_dev;
-    k_scan_totals<<<(unsigned)nch, SCAN_WG, 0, st>>>(c->cnt_own, c->cnt_touch, c->chunk_tot);
+    k_scan_totals<<<(unsigned)nch, SCAN_WG, 0, st>>>(pg, c->cnt_own, c->cnt_touch, c->chunk_tot);
     LAUNCH_CHECK();
-    k_scan_chunks<<<1, SCAN2_WG, 0, st>>>(c->chunk_tot, nch, c->start_own, c->ntiles, c->meta, mh);
+    k_scan_chunks<<<1, SCAN2_WG, 0, st>>>(c->chunk_tot, nch, c->meta, mh);
     LAUNCH_CHECK();
     if (mh && hipEventRecord(c->meta_event, st) == hipSuccess) c->meta_pending = true;
-    k_scan_write<<<(unsigned)nch, SCAN_WG, 0, st>>>(c->cnt_own, c->cnt_touch, c->chunk_tot,
-                                                    c->ntiles, c->start_own, c->own_slot,
+    k_scan_write<<<(unsigned)nch, SCAN_WG, 0, st>>>(pg, c->cnt_own, c->cnt_touch, c->chunk_tot,
+                                                    c->start_own, c->end_own, c->own_slot,
                                                     c->own_tiles, c->touch_tiles,
                                                     (uint32_t*)c->bflag, c->nbflag_words, c->meta);
     LAUNCH_CHECK();
   }
+  // the scatter's temporaries: base in sp_tmp, fraction in sp_g, u_b in sp_du
+  // (both written by sweep 0 before they are read)
   k_point_scatter<<<nb, LBM_BLOCK, 0, st>>>(c->rest, c->body_of, c->motion, n, pg, c->key, c->rank,
-                                            c->start_own, c->sp_base, c->sp_frac, c->sp_ub,
-                                            c->bflag, c->pt_partials, c->pt_partials + rs);
+                                            c->start_own, c->sp_tmp, c->sp_g, c->sp_du, c->bflag,
+                                            c->pt_partials, c->pt_partials + rs);
+  LAUNCH_CHECK();
+  k_tile_order<<<lg, CELL_WG, 0, st>>>(c->own_tiles, c->meta, c->start_own, c->end_own, c->sp_tmp,
+                                       c->sp_g,
+                                       c->sp_du, c->rank, c->sp_base, c->sp_frac, c->sp_ub,
+                                       (unsigned char*)c->boxbuf);
   LAUNCH_CHECK();
   {
     hipError_t e = hipSuccess;
@@ -1300,7 +1699,8 @@ hipError_t launch_forcing(lbm_ctx* c) {
     c->nbr_valid = true;
   }
   auto sweep = [&](int it, int mode, const uint32_t* gate, float4* g_orig) {
-    k_sweep_tiles<<<lg, WG, 0, st>>>(c->own_tiles, c->meta, c->start_own, c->sp_base, c->sp_frac,
+    k_sweep_tiles<<<lg, WG, 0, st>>>(c->own_tiles, c->meta, c->start_own, c->end_own,
+                                     c->sp_base, c->sp_frac,
                                      c->sp_ub, c->sp_g, c->sp_du, c->U,
                                      (unsigned char*)c->boxbuf, pg, mode | uw,
                                      c->pt_partials + (2 + it) * rs, gate, g_orig, c->du_prev,
@@ -1309,8 +1709,8 @@ hipError_t launch_forcing(lbm_ctx* c) {
   };
   auto merge = [&](bool final_, const uint32_t* gate) {
     k_merge_tiles<<<tg, MERGE_WG, 0, st>>>(c->touch_tiles, c->meta, c->own_slot,
-                                        (const unsigned char*)c->boxbuf,
-                                        c->bflag, final_ ? c->G : c->U, pg, final_ ? 2 : 0, gate);
+                                        (const unsigned char*)c->boxbuf, c->bflag, c->G, c->U, pg,
+                                        final_ ? 2 : 0, gate);
     return hipGetLastError();
   };
 #define TRY(x)                               \
@@ -1323,7 +1723,9 @@ hipError_t launch_forcing(lbm_ctx* c) {
     // fixed number of sweeps; the last one spreads du into G
     for (int it = 0; it < N; ++it) {
       const bool last = it == N - 1;
-      const int mode = SW_INTERP | (it == 0 ? SW_FIRST : 0) | (last ? SW_SPREAD_DU : SW_SPREAD_G);
+      // g is kept for the export (last sweep) and the warm-start features (sweep 0)
+      const int mode = SW_INTERP | (it == 0 ? SW_FIRST : 0) | (last ? SW_SPREAD_DU : SW_SPREAD_G) |
+                       ((last || (it == 0 && feats)) ? SW_STORE_G : 0);
       TRY(sweep(it, mode, nullptr, it == 0 && feats ? c->g0_orig : nullptr));
       if (it == 0 && feats) TRY(launch_features_warm(c, false));
       TRY(merge(last, nullptr));
@@ -1345,7 +1747,9 @@ hipError_t launch_forcing(lbm_ctx* c) {
     // sweep 0 under a warm start only interpolates: the predicted (or the
     // previous forcing's) du is spread in place of s g0
     const bool spread = !last && !((warm || from_prev) && it == 0);
-    const int mode = SW_INTERP | (it == 0 ? SW_FIRST : 0) | (spread ? SW_SPREAD_G : 0);
+    // any sweep may be the last one: g is always kept
+    const int mode =
+        SW_INTERP | SW_STORE_G | (it == 0 ? SW_FIRST : 0) | (spread ? SW_SPREAD_G : 0);
     TRY(sweep(it, mode, gate, it == 0 && feats ? c->g0_orig : nullptr));
     k_resid_check<<<1, RESID_WG, 0, st>>>(c->pt_partials + (2 + it) * rs, lg,
                                            c->pt_partials + rs, na, eps2, c->resid_thr, it,

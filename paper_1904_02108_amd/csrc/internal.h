@@ -37,7 +37,7 @@ struct lbm_ctx {
   // caller buffers, carved
   void* lat[2] = {nullptr, nullptr};
   int cur = 0;  // lattice holding the post-collision state of the previous step
-  float* U = nullptr;  // [3][ncell] velocity scratch for the forcing
+  float4* U = nullptr;  // [ntiles][512] velocity scratch of the forcing (tile-major, x y z 0)
   float* G = nullptr;  // [3][ncell] force
   // points (capacity max_points)
   float4* rest = nullptr;     // (x, y, z, s) relative to the body centre
@@ -49,6 +49,7 @@ struct lbm_ctx {
   float4* sp_ub = nullptr;    // sorted: point velocity u_b
   float4* sp_g = nullptr;     // sorted: deficit g
   float4* sp_du = nullptr;    // sorted: accumulated correction du
+  int4* sp_tmp = nullptr;     // binning temporary: base cells in tile order
   double* bodies = nullptr;   // [LBM_MAX_BODIES][8] as given
   BodyMotion* motion = nullptr;
   // tiles (8^3) and force blocks (4^3)
@@ -57,7 +58,8 @@ struct lbm_ctx {
   int64_t nbflag_words = 0;    // bflag size in 32-bit words
   uint32_t* cnt_own = nullptr;     // [ntiles] points owned per tile (pass 1)
   uint32_t* cnt_touch = nullptr;   // [ntiles] 1 where a support reaches the tile (pass 1)
-  uint32_t* start_own = nullptr;   // [ntiles + 1]
+  uint32_t* start_own = nullptr;   // [ntiles] first slot of each tile's points
+  uint32_t* end_own = nullptr;     // [ntiles] one past its last slot
   int32_t* own_slot = nullptr;     // [ntiles] index in own_tiles, or -1
   uint32_t* own_tiles = nullptr;   // compact list of tiles owning points
   uint32_t* touch_tiles = nullptr; // compact list of touched tiles

@@ -190,7 +190,7 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->lat[0] = L;
   c->lat[1] = L + pl.lat_bytes;
   char* F = (char*)bufs[LBM_BUF_FIELDS];
-  c->U = (float*)F;
+  c->U = (float4*)F;
   c->G = (float*)(F + pl.o_G);
   char* P = (char*)bufs[LBM_BUF_POINTS];
   c->rest = (float4*)(P + pl.o_rest);
@@ -202,6 +202,7 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->sp_ub = (float4*)(P + pl.o_ub);
   c->sp_g = (float4*)(P + pl.o_g);
   c->sp_du = (float4*)(P + pl.o_du);
+  c->sp_tmp = (int4*)(P + pl.o_tmp);
   c->bodies = (double*)(P + pl.o_bodies);
   c->motion = (BodyMotion*)(P + pl.o_motion);
   c->nbr = (int32_t*)(P + pl.o_nbr);
@@ -221,6 +222,7 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->cnt_own = (uint32_t*)(T + pl.o_cnt_own);
   c->cnt_touch = (uint32_t*)(T + pl.o_cnt_touch);
   c->start_own = (uint32_t*)(T + pl.o_start_own);
+  c->end_own = (uint32_t*)(T + pl.o_end_own);
   c->own_slot = (int32_t*)(T + pl.o_own_slot);
   c->own_tiles = (uint32_t*)(T + pl.o_own_tiles);
   c->touch_tiles = (uint32_t*)(T + pl.o_touch_tiles);
@@ -238,14 +240,13 @@ lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx**
   c->status = (uint32_t*)(S + pl.o_status);
 
   hipError_t e = hipSuccess;
-  const int64_t ntpad = (c->ntiles + 16383) / 16384 * 16384;
-  if (e == hipSuccess) e = launch_fill_u32(c, c->cnt_own, 0u, ntpad);
-  if (e == hipSuccess) e = launch_fill_u32(c, c->cnt_touch, 0u, ntpad);
+  if (e == hipSuccess) e = launch_fill_u32(c, c->cnt_own, 0u, c->ntiles);
+  if (e == hipSuccess) e = launch_fill_u32(c, c->cnt_touch, 0u, c->ntiles);
   if (e == hipSuccess) e = launch_fill_u32(c, c->meta, 0u, 4);
   if (e == hipSuccess) e = launch_fill_u32(c, c->ctl, 0u, 4);
   if (e == hipSuccess) e = launch_fill_u32(c, c->status, 0u, 4);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->bflag, 0u, c->nbflag_words);
-  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->U, 0u, pl.o_G / sizeof(float));
+  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->U, 0u, pl.o_G / sizeof(uint32_t));
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->G, 0u, 3 * c->ncell);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->sum_partials, 0u, 8 * c->n_cell_blocks);
   if (e == hipSuccess) e = launch_init_equilibrium(c);

@@ -430,9 +430,10 @@ __device__ __forceinline__ float lat_sep(int b0, float f0, int b1, float f1, int
 }
 
 __global__ __launch_bounds__(256) void k_neighbours(
-    const uint32_t* __restrict__ start_own, const int4* __restrict__ sp_base,
-    const float4* __restrict__ sp_frac, const float4* __restrict__ rest,
-    const int32_t* __restrict__ body_of, int64_t npts, NbrGeom ng, int32_t* __restrict__ nbr) {
+    const uint32_t* __restrict__ start_own, const uint32_t* __restrict__ end_own,
+    const int4* __restrict__ sp_base, const float4* __restrict__ sp_frac,
+    const float4* __restrict__ rest, const int32_t* __restrict__ body_of, int64_t npts, NbrGeom ng,
+    int32_t* __restrict__ nbr) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= npts) return;
   const int4 b = sp_base[k];
@@ -456,7 +457,7 @@ __global__ __launch_bounds__(256) void k_neighbours(
       for (int ix = 0; ix < nx; ++ix) {
         const uint32_t t = (uint32_t)tx[ix] +
                            (uint32_t)ng.tiles[0] * ((uint32_t)ty[iy] + (uint32_t)ng.tiles[1] * (uint32_t)tz[iz]);
-        const uint32_t q1 = start_own[t + 1];
+        const uint32_t q1 = end_own[t];
 #pragma unroll 4
         for (uint32_t q = start_own[t]; q < q1; ++q) {
           // cheap filter in the lattice frame (the rigid motion keeps
@@ -804,7 +805,7 @@ hipError_t launch_neighbours(lbm_ctx* c) {
   }
   const unsigned nb = (unsigned)((c->npts + 255) / 256);
   if (nb == 0) return hipSuccess;
-  k_neighbours<<<nb, 256, 0, c->stream>>>(c->start_own, c->sp_base, c->sp_frac, c->rest,
+  k_neighbours<<<nb, 256, 0, c->stream>>>(c->start_own, c->end_own, c->sp_base, c->sp_frac, c->rest,
                                           c->body_of, c->npts, ng, c->nbr);
   return hipGetLastError();
 }

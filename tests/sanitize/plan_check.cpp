@@ -39,11 +39,13 @@ void check_plan(const lbm_params& p) {
   const size_t M = (size_t)(p.max_points > 0 ? p.max_points : 1);
   const size_t nc = (size_t)p.nx * p.ny * p.nz;
   const size_t nt = (size_t)pl.ntiles;
+  const size_t np4 = (size_t)((pl.tiles[0] + 3) / 4 * 4) * ((pl.tiles[1] + 3) / 4 * 4) *
+                     ((pl.tiles[2] + 3) / 4 * 4);
   const size_t elem = p.storage == LBM_STORE_F32 ? 4 : 2;
   const size_t nb4 = (size_t)((p.nx + 3) / 4) * ((p.ny + 3) / 4) * ((p.nz + 3) / 4);
   std::vector<Region> r = {
       {LBM_BUF_LATTICE, 0, 2 * 19 * nc * elem, "lattices"},
-      {LBM_BUF_FIELDS, 0, nt * 3 * 512 * 4, "U"},
+      {LBM_BUF_FIELDS, 0, nt * 512 * 16, "U"},
       {LBM_BUF_FIELDS, pl.o_G, 3 * nc * 4, "G"},
       {LBM_BUF_FIELDS, pl.o_box, (size_t)pl.max_boxes * BOX_SLOT_BYTES, "boxes"},
       {LBM_BUF_POINTS, pl.o_rest, M * 16, "rest"},
@@ -55,6 +57,7 @@ void check_plan(const lbm_params& p) {
       {LBM_BUF_POINTS, pl.o_ub, M * 16, "ub"},
       {LBM_BUF_POINTS, pl.o_g, M * 16, "g"},
       {LBM_BUF_POINTS, pl.o_du, M * 16, "du"},
+      {LBM_BUF_POINTS, pl.o_tmp, M * 16, "binning temporary"},
       {LBM_BUF_POINTS, pl.o_bodies, (size_t)LBM_MAX_BODIES * 64, "bodies"},
       {LBM_BUF_POINTS, pl.o_motion, (size_t)LBM_MAX_BODIES * BODY_MOTION_BYTES, "motion"},
       {LBM_BUF_POINTS, pl.o_nbr, M * 16 * 4, "nbr"},
@@ -65,16 +68,17 @@ void check_plan(const lbm_params& p) {
       {LBM_BUF_POINTS, pl.o_ubox, (size_t)LBM_MAX_BODIES * 24, "ubox"},
       {LBM_BUF_POINTS, pl.o_theta, (size_t)IBM_MLP_NPARAM * 4, "theta"},
       {LBM_BUF_POINTS, pl.o_packed, MLP_PACKED_BYTES, "packed"},
-      // the tile scan reads whole chunks of 2048 tiles
-      {LBM_BUF_TILES, pl.o_cnt_own, (nt + 2047) / 2048 * 2048 * 4, "cnt_own"},
-      {LBM_BUF_TILES, pl.o_cnt_touch, (nt + 2047) / 2048 * 2048 * 4, "cnt_touch"},
-      {LBM_BUF_TILES, pl.o_start_own, (nt + 1) * 4, "start_own"},
+      {LBM_BUF_TILES, pl.o_cnt_own, nt * 4, "cnt_own"},
+      {LBM_BUF_TILES, pl.o_cnt_touch, nt * 4, "cnt_touch"},
+      {LBM_BUF_TILES, pl.o_start_own, nt * 4, "start_own"},
+      {LBM_BUF_TILES, pl.o_end_own, nt * 4, "end_own"},
       {LBM_BUF_TILES, pl.o_own_slot, nt * 4, "own_slot"},
       {LBM_BUF_TILES, pl.o_own_tiles, nt * 4, "own_tiles"},
       {LBM_BUF_TILES, pl.o_touch_tiles, nt * 4, "touch_tiles"},
       {LBM_BUF_TILES, pl.o_meta, 16, "meta"},
       {LBM_BUF_TILES, pl.o_bflag, (nb4 + 3) / 4 * 4, "bflag"},
-      {LBM_BUF_TILES, pl.o_chunk, (nt + 2047) / 2048 * 4 * 4, "chunk totals"},
+      // the tile scan: the tile grid padded to whole 4^3 blocks, in chunks of 2048 positions
+      {LBM_BUF_TILES, pl.o_chunk, (np4 + 2047) / 2048 * 4 * 4, "chunk totals"},
       {LBM_BUF_SCRATCH, pl.o_sum_part, (size_t)pl.n_cell_blocks * 32, "sum partials"},
       {LBM_BUF_SCRATCH, pl.o_pt_part, (size_t)(p.max_iter + 2) * pl.part_row * 8, "pt partials"},
       {LBM_BUF_SCRATCH, pl.o_small, 256 * 8, "small"},
