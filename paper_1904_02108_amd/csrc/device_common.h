@@ -96,6 +96,10 @@ struct Store<LBM_STORE_BF16> {
     const uint32_t u = (uint32_t)bits(a) | ((uint32_t)bits(b) << 16);
     __builtin_nontemporal_store(u, reinterpret_cast<uint32_t*>(p));
   }
+  // the pair as one 32-bit word (a in the low half)
+  static __device__ __forceinline__ uint32_t pack2(float a, float b) {
+    return (uint32_t)bits(a) | ((uint32_t)bits(b) << 16);
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -208,6 +212,20 @@ __device__ __forceinline__ void gather_fast(const typename Store<S>::T* __restri
   }
 }
 
+// Pull gather away from walls through buffer resources (FP32 lattices of
+// less than 4 GB): the lattice base sits in scalar registers, each load
+// takes the cell's 32-bit byte offset and the population's byte offset as a
+// scalar, so no 64-bit address is formed per load.  Streaming (nt) loads.
+__device__ __forceinline__ void gather_fast_buf(__amdgpu_buffer_rsrc_t rs, const LatticeGeom& g,
+                                                const PullIdx& p, float f[Q]) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const uint32_t off = (p.xs[EX[i] + 1] + p.ys[EY[i] + 1] + p.zs[EZ[i] + 1]) * 4u;
+    f[i] = __uint_as_float(
+        __builtin_amdgcn_raw_buffer_load_b32(rs, off, (uint32_t)(i * g.stride * 4), 2));
+  }
+}
+
 // Pull gather of two neighbouring cells x0 and x0 + 1 of one row for the
 // 16-bit formats (x0 even, nx even, so that the pair is aligned).  Away from walls each population
 // comes as one pair load at the source row's x0; a population with e_x = +1
@@ -241,6 +259,39 @@ __device__ __forceinline__ void gather_pair(const typename Store<S>::T* __restri
     } else {
       f0[i] = b;
       f1[i] = Store<S>::load_nt(row + xr);
+    }
+  }
+}
+
+// The pair gather through a buffer resource (BF16 lattices of less than
+// 4 GB): one 4-byte load per population pair, one 2-byte load for the outer
+// value of an e_x = +-1 population; 32-bit byte offsets, the population's
+// offset as a scalar.  Streaming (nt) loads.  Away from walls only.
+__device__ __forceinline__ void gather_pair_buf_bf16(__amdgpu_buffer_rsrc_t rs,
+                                                     const LatticeGeom& g, const PullIdx& p,
+                                                     int x0, float f0[Q], float f1[Q]) {
+  const uint32_t xl = p.xs[2];                                   // x0 - 1, wrapped
+  const uint32_t xr = (uint32_t)(x0 + 2 == g.nx ? 0 : x0 + 2);   // x0 + 2, wrapped
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const uint32_t row = p.ys[EY[i] + 1] + p.zs[EZ[i] + 1];
+    const uint32_t soff = (uint32_t)(i * g.stride * 2);
+    const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(rs, (row + (uint32_t)x0) * 2u, soff, 2);
+    const float a = __uint_as_float(u << 16), b = __uint_as_float(u & 0xffff0000u);
+    if (EX[i] == 0) {
+      f0[i] = a;
+      f1[i] = b;
+    } else {
+      const uint32_t xo = EX[i] == 1 ? xl : xr;
+      const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(rs, (row + xo) * 2u, soff, 2);
+      const float o = __uint_as_float(((uint32_t)h) << 16);
+      if (EX[i] == 1) {
+        f0[i] = o;
+        f1[i] = a;
+      } else {
+        f0[i] = b;
+        f1[i] = o;
+      }
     }
   }
 }

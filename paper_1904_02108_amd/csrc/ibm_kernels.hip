@@ -949,8 +949,11 @@ struct KeptPoint {
   float v0, v1, v2;  // raw spread vector (g, or du when spreading du)
 };
 
+// w[c] for a lane-dependent c in 0..3, as two levels of selects (no branches).
 __device__ __forceinline__ float sel4(const float w[4], int c) {
-  return c == 0 ? w[0] : (c == 1 ? w[1] : (c == 2 ? w[2] : w[3]));
+  const bool odd = c & 1;
+  const float lo = odd ? w[1] : w[0], hi = odd ? w[3] : w[2];
+  return (c & 2) ? hi : lo;
 }
 
 // The factor of a point's raw spread vector: s for the weighted inner sweep,

@@ -99,11 +99,17 @@ __device__ __forceinline__ void store_partials(double part[4], int tid, int64_t 
 #ifndef LBM_SC_ROWS
 #define LBM_SC_ROWS 1
 #endif
-template <int S, int FORCING, bool FLAT>
+// BUF (FP32 lattices under 4 GB): buffer-resource loads and stores of the
+// populations (see gather_fast_buf).
+template <int S, int FORCING, bool FLAT, bool BUF = false>
 __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
     const typename Store<S>::T* __restrict__ src, typename Store<S>::T* __restrict__ dst,
     const LatticeGeom g, const float* __restrict__ G, const uint8_t* __restrict__ flags,
     double* __restrict__ partials, uint32_t* __restrict__ bad) {
+  static_assert(!BUF || S == LBM_STORE_F32, "buffer form for FP32 storage");
+  const uint32_t lat_bytes = BUF ? (uint32_t)(Q * g.stride * 4) : 0u;
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)src, 0, lat_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rdst = __builtin_amdgcn_make_buffer_rsrc((void*)dst, 0, lat_bytes, 0x00020000);
   // 3-D launch: blockDim.x spans x, blockDim.y spans y, one z-plane per block
   // row; each workgroup takes LBM_SC_ROWS consecutive block rows along y.
   // FLAT (x extents that are not a multiple of the wavefront): 256 threads
@@ -123,7 +129,15 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
       const uint32_t cell =
           (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
       float f[Q];
-      gather_any<S, true>(src, g, x, y, z, f);
+      if constexpr (BUF) {
+        const PullIdx pi = pull_index(g, x, y, z);
+        if (pi.fast)
+          gather_fast_buf(rsrc, g, pi, f);
+        else
+          gather_pull<S>(src, g, x, y, z, f);
+      } else {
+        gather_any<S, true>(src, g, x, y, z, f);
+      }
       float gx = g.g_ext[0], gy = g.g_ext[1], gz = g.g_ext[2];
       if (flags[fblock_of(g, x, y, z)]) {
         gx += G[cell];
@@ -132,8 +146,15 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
       }
       float drho, jx, jy, jz;
       collide_cell<FORCING>(g, f, gx, gy, gz, drho, jx, jy, jz);
+      if constexpr (BUF) {
 #pragma unroll
-      for (int i = 0; i < Q; ++i) Store<S>::store_nt(dst + (int64_t)i * g.stride + cell, f[i]);
+        for (int i = 0; i < Q; ++i)
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(f[i]), rdst, cell * 4u,
+                                                (uint32_t)(i * g.stride * 4), 2);
+      } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) Store<S>::store_nt(dst + (int64_t)i * g.stride + cell, f[i]);
+      }
       part[0] += drho;
       part[1] += jx;
       part[2] += jy;
@@ -148,11 +169,18 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
 // Two cells per thread (16-bit storage, even x extents): the pair (x0, x0 + 1)
 // is read and written with one 4-byte access per population (see
 // gather_pair); 256 threads over consecutive pairs of an x-y plane.
-template <int S, int FORCING>
+// BUF (BF16 lattices under 4 GB): buffer-resource loads and stores
+// (gather_pair_buf_bf16).  F16 keeps the global-address form, which measured
+// faster for it.
+template <int S, int FORCING, bool BUF = false>
 __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide_pairs(
     const typename Store<S>::T* __restrict__ src, typename Store<S>::T* __restrict__ dst,
     const LatticeGeom g, const float* __restrict__ G, const uint8_t* __restrict__ flags,
     double* __restrict__ partials, uint32_t* __restrict__ bad) {
+  static_assert(!BUF || S == LBM_STORE_BF16, "buffer form for BF16 storage");
+  const uint32_t lat_bytes = BUF ? (uint32_t)(Q * g.stride * 2) : 0u;
+  const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)src, 0, lat_bytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rdst = __builtin_amdgcn_make_buffer_rsrc((void*)dst, 0, lat_bytes, 0x00020000);
   const int px = g.nx >> 1;
   const int pf = blockIdx.x * LBM_BLOCK + threadIdx.x;
   const int y = pf / px;
@@ -163,7 +191,15 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide_pairs(
     const uint32_t cell =
         (uint32_t)x0 + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
     float f0[Q], f1[Q];
-    gather_pair<S>(src, g, x0, y, z, f0, f1);
+    if constexpr (BUF) {
+      const PullIdx pi = pull_index(g, x0, y, z);
+      if (pi.fast && (g.bc[0] == LBM_BC_PERIODIC || x0 + 2 < g.nx))
+        gather_pair_buf_bf16(rsrc, g, pi, x0, f0, f1);
+      else
+        gather_pair<S>(src, g, x0, y, z, f0, f1);
+    } else {
+      gather_pair<S>(src, g, x0, y, z, f0, f1);
+    }
     float ax[2] = {g.g_ext[0], g.g_ext[0]}, ay[2] = {g.g_ext[1], g.g_ext[1]},
           az[2] = {g.g_ext[2], g.g_ext[2]};
     if (flags[fblock_of(g, x0, y, z)]) {  // x0 and x0 + 1 share a force block
@@ -188,9 +224,16 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide_pairs(
     part[1] += jx;
     part[2] += jy;
     part[3] += jz;
+    if constexpr (BUF) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-      Store<S>::store2_nt(dst + (int64_t)i * g.stride + cell, f0[i], f1[i]);
+      for (int i = 0; i < Q; ++i)
+        __builtin_amdgcn_raw_buffer_store_b32(Store<S>::pack2(f0[i], f1[i]), rdst, cell * 2u,
+                                              (uint32_t)(i * g.stride * 2), 2);
+    } else {
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        Store<S>::store2_nt(dst + (int64_t)i * g.stride + cell, f0[i], f1[i]);
+    }
   }
   store_partials(part, threadIdx.x, (int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.z,
                  partials, bad);
@@ -380,6 +423,17 @@ hipError_t stream_collide_s(lbm_ctx* c) {
   dim3 grid, block;
   stream_collide_shape(c, grid, block);
   if constexpr (S != LBM_STORE_F32) {
+    if constexpr (S == LBM_STORE_BF16) {
+      if (stream_collide_pairs(c) && (int64_t)Q * c->geom.stride * 2 < ((int64_t)1 << 32)) {
+        if (c->p.forcing == LBM_FORCE_SHIFT)
+          k_stream_collide_pairs<S, LBM_FORCE_SHIFT, true><<<grid, block, 0, c->stream>>>(
+              src, dst, c->geom, c->G, c->bflag, c->sum_partials, c->status);
+        else
+          k_stream_collide_pairs<S, LBM_FORCE_GUO, true><<<grid, block, 0, c->stream>>>(
+              src, dst, c->geom, c->G, c->bflag, c->sum_partials, c->status);
+        return hipGetLastError();
+      }
+    }
     if (stream_collide_pairs(c)) {
       if (c->p.forcing == LBM_FORCE_SHIFT)
         k_stream_collide_pairs<S, LBM_FORCE_SHIFT><<<grid, block, 0, c->stream>>>(
@@ -391,6 +445,17 @@ hipError_t stream_collide_s(lbm_ctx* c) {
     }
   }
   const bool flat = stream_collide_flat(c);
+  if constexpr (S == LBM_STORE_F32) {
+    if (!flat && (int64_t)Q * c->geom.stride * 4 < ((int64_t)1 << 32)) {
+      if (c->p.forcing == LBM_FORCE_SHIFT)
+        k_stream_collide<S, LBM_FORCE_SHIFT, false, true><<<grid, block, 0, c->stream>>>(
+            src, dst, c->geom, c->G, c->bflag, c->sum_partials, c->status);
+      else
+        k_stream_collide<S, LBM_FORCE_GUO, false, true><<<grid, block, 0, c->stream>>>(
+            src, dst, c->geom, c->G, c->bflag, c->sum_partials, c->status);
+      return hipGetLastError();
+    }
+  }
   if (c->p.forcing == LBM_FORCE_SHIFT) {
     if (flat)
       k_stream_collide<S, LBM_FORCE_SHIFT, true><<<grid, block, 0, c->stream>>>(
