@@ -208,7 +208,10 @@ enum {
 
 typedef struct {
   int32_t on_device;   /* 1: device pointers (async on the stream);
-                          0: host pointers (the call synchronises)          */
+                          0: host pointers (the call synchronises; the
+                          data pass through a device staging buffer that
+                          the context allocates once, grows to the largest
+                          request and keeps until lbm_destroy)              */
   int32_t pops_f64;    /* POPS as double (1) or float (0)                     */
   float* rho;
   float* vel;
@@ -230,7 +233,8 @@ lbm_status lbm_buffer_sizes(const lbm_params* p, size_t sizes_out[LBM_NBUF]);
  * not read before this call and need no initialisation. */
 lbm_status lbm_create(const lbm_params* p, void* const bufs[LBM_NBUF], lbm_ctx** out);
 
-/* Destroys the context (host memory only; the caller frees its buffers). */
+/* Destroys the context and the device staging buffer of host-pointer
+ * field reads and writes; the caller frees its buffers. */
 void lbm_destroy(lbm_ctx* ctx);
 
 /* Last error message of ctx, or of the last failed lbm_create or

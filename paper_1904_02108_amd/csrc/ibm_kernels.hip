@@ -65,12 +65,9 @@ __device__ __forceinline__ int tap_coord(int v, int n, int bc) {
 }
 
 // Per-body rotation coefficients for step n (theta_n = theta0 + omega n) and
-// their change since step n-1, in FP64.
-__global__ void k_body_motion(const double* __restrict__ bodies, int nb, int64_t step,
-                              BodyMotion* __restrict__ out) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
-  const double* B = bodies + 8 * b;
+// their change since step n-1, in FP64, from the body's row (centre, axis,
+// theta0, omega).
+__device__ __forceinline__ BodyMotion body_motion(const double* __restrict__ B, int64_t step) {
   const double len = sqrt(B[3] * B[3] + B[4] * B[4] + B[5] * B[5]);
   const double th = B[6] + B[7] * (double)step;
   const double thp = B[6] + B[7] * (double)(step - 1);
@@ -86,7 +83,7 @@ __global__ void k_body_motion(const double* __restrict__ bodies, int nb, int64_t
   m.s = s;
   m.dc = c - cp;
   m.ds = s - sp;
-  out[b] = m;
+  return m;
 }
 
 // Position (base cell and fraction) and velocity of one point (FP64):
@@ -184,14 +181,35 @@ __device__ __forceinline__ uint32_t local_cell(const int base[3]) {
 }
 
 // Pass 1: owner tile and rank of each point; flags of the touched tiles.
+// The kernel also forms the bodies' motion for this step: into LDS for the
+// bodies of the workgroup's points (a contiguous range, since every body owns
+// a contiguous range of points; a thread computes its own body's when the
+// range is longer than MOTION_LDS), and into `motion` for every body (body b
+// by workgroup b mod the grid), for the later kernels of the forcing.
+constexpr int MOTION_LDS = 32;
 __global__ __launch_bounds__(LBM_BLOCK) void k_point_count(
     const float4* __restrict__ rest, const int32_t* __restrict__ body_of,
-    const BodyMotion* __restrict__ motion, int64_t npts, PointGeom pg, uint32_t* __restrict__ key,
+    const double* __restrict__ bodies, int nbodies, int64_t step,
+    BodyMotion* __restrict__ motion, int64_t npts, PointGeom pg, uint32_t* __restrict__ key,
     uint32_t* __restrict__ rank, uint32_t* __restrict__ cnt_own, uint32_t* __restrict__ cnt_touch) {
-  const int64_t k = (int64_t)blockIdx.x * LBM_BLOCK + threadIdx.x;
+  __shared__ BodyMotion sm[MOTION_LDS];
+  for (int64_t b = blockIdx.x + (int64_t)threadIdx.x * gridDim.x; b < nbodies;
+       b += (int64_t)LBM_BLOCK * gridDim.x)
+    motion[b] = body_motion(bodies + 8 * b, step);
+  const int64_t k0 = (int64_t)blockIdx.x * LBM_BLOCK;
+  const int lo = body_of[k0], hi = body_of[min(k0 + LBM_BLOCK, npts) - 1];
+  const bool in_lds = hi - lo < MOTION_LDS;
+  if (in_lds && (int)threadIdx.x <= hi - lo)
+    sm[threadIdx.x] = body_motion(bodies + 8 * (int64_t)(lo + (int)threadIdx.x), step);
+  __syncthreads();
+  const int64_t k = k0 + threadIdx.x;
   const bool valid = k < npts;
   PointState ps{};
-  if (valid) ps = move_point(motion[body_of[k]], rest[k], pg);
+  if (valid) {
+    const int b = body_of[k];
+    ps = move_point(in_lds ? sm[b - lo] : body_motion(bodies + 8 * (int64_t)b, step), rest[k],
+                    pg);
+  }
   const uint32_t own = valid ? tile_index(pg, ps.base[0] >> TILE_SHIFT, ps.base[1] >> TILE_SHIFT,
                                           ps.base[2] >> TILE_SHIFT)
                              : 0u;
@@ -1158,6 +1176,9 @@ __global__ __launch_bounds__(WG, 7) void k_sweep_tiles(
   uint32_t e;
   while (order.next(e)) {
     const uint32_t t = own_tiles[e];
+    // the point range is loaded before the box is staged (one memory round
+    // trip fewer on the path of a lone tile)
+    const uint32_t p0 = start_own[t], P = end_own[t] - p0;
     int o[3];
     tile_origin(pg, t, o);
     __syncthreads();  // the previous tile's box has been stored
@@ -1186,7 +1207,6 @@ __global__ __launch_bounds__(WG, 7) void k_sweep_tiles(
       __builtin_amdgcn_s_waitcnt(0);  // vmcnt(0): this wave's loads have landed in LDS
     }
     __syncthreads();
-    const uint32_t p0 = start_own[t], P = end_own[t] - p0;
     // pass 1: interpolation, deficit, correction (or, spreading only, the
     // spread vectors); each thread keeps its first KEEP points
     unsigned long long bsum = 0ull;  // in units of 2^-32 (see bound_units)
@@ -1582,14 +1602,17 @@ PointGeom point_geom(const lbm_ctx* c) {
 // (list 0) or touched (list 1) tiles: a multiple of 8, each XCD striding
 // through its contiguous part of the list, so any size is correct.  The
 // lists' lengths are known on the device only; the host sizes the grids from
-// the previous forcing's lengths (copied asynchronously to pinned memory and
-// used once that copy has completed) with a quarter of headroom, so that
+// the lengths of a recent forcing (copied asynchronously to pinned memory at
+// most every META_EVERY forcings, used once that copy has completed) with a
+// quarter of headroom, so that
 // idle or gated-off launches do not dispatch a workgroup per tile of the
 // grid.  Without a previous length every tile gets a workgroup (up to
 // LBM_TILE_GRID_MAX).
 #ifndef LBM_TILE_GRID_MAX
 #define LBM_TILE_GRID_MAX 32768
 #endif
+constexpr uint32_t META_EVERY = 8;
+
 int64_t tile_grid(const lbm_ctx* c, int list) {
   const int64_t full = std::min<int64_t>((c->ntiles + 7) / 8 * 8, LBM_TILE_GRID_MAX);
   if (!c->prev_len_valid) return full;
@@ -1649,15 +1672,19 @@ hipError_t launch_forcing(lbm_ctx* c) {
   const int64_t rs = c->part_row;  // row stride of pt_partials
   hipStream_t st = c->stream;
 
-  k_body_motion<<<(c->nbodies + 63) / 64, 64, 0, st>>>(c->bodies, c->nbodies, c->step, c->motion);
-  LAUNCH_CHECK();
-  k_point_count<<<nb, LBM_BLOCK, 0, st>>>(c->rest, c->body_of, c->motion, n, pg, c->key, c->rank,
-                                          c->cnt_own, c->cnt_touch);
+  k_point_count<<<nb, LBM_BLOCK, 0, st>>>(c->rest, c->body_of, c->bodies, c->nbodies, c->step,
+                                          c->motion, n, pg, c->key, c->rank, c->cnt_own,
+                                          c->cnt_touch);
   LAUNCH_CHECK();
   {
     const int64_t nch = (scan_positions(c) + SCAN_CHUNK - 1) / SCAN_CHUNK;
-    // a pending host copy of the lengths is not overwritten before it is read
-    uint32_t* mh = c->meta_pending ? nullptr : c->meta_host_dev;
+    // a pending host copy of the lengths is not overwritten before it is
+    // read; the copy is refreshed every META_EVERY forcings (the event that
+    // marks its arrival costs a few microseconds of queue time, and the
+    // lengths only size the grids, with a margin)
+    const bool refresh = !c->meta_pending && (!c->prev_len_valid || c->meta_age >= META_EVERY);
+    uint32_t* mh = refresh ? c->meta_host_dev : nullptr;
+    c->meta_age = refresh ? 0u : c->meta_age + 1u;
     k_scan_totals<<<(unsigned)nch, SCAN_WG, 0, st>>>(pg, c->cnt_own, c->cnt_touch, c->chunk_tot);
     LAUNCH_CHECK();
     k_scan_chunks<<<1, SCAN2_WG, 0, st>>>(c->chunk_tot, nch, c->meta, mh);

@@ -87,6 +87,10 @@ struct lbm_ctx {
   int64_t part_row = 0;
   double* small = nullptr;          // [256] reduced results
   uint32_t* status = nullptr;       // [4] sticky: [0] sums not finite, [1] spread out of range
+  // device staging of host sources and destinations in lbm_read_fields /
+  // lbm_write_fields: grown to the largest request, freed by lbm_destroy
+  void* stage = nullptr;
+  size_t stage_bytes = 0;
 
   // state
   int64_t npts = 0;
@@ -112,12 +116,13 @@ struct lbm_ctx {
   bool meta_pending = false;
   bool prev_len_valid = false;
   uint32_t prev_len[2] = {0, 0};
+  uint32_t meta_age = 0;  // forcings since the lengths were last copied to the host
   int64_t own_grid = 8;  // workgroups of the last forcing's sweep launches
 
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<int> ev_kind;  // per recorded interval: 0 forcing, 1 stream-collide
+  std::vector<int> ev_kind;  // per recorded event, the phase it opens: 0 forcing, 1 stream-collide, -1 none
   size_t ev_used = 0;
   double t_acc[4] = {0, 0, 0, 0};
 

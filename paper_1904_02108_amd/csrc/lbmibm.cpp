@@ -62,25 +62,36 @@ void fill_geom(lbm_ctx* c, const Plan& pl) {
   g.fblk_y = pl.fblk[1];
 }
 
-// Timing: events recorded around the forcing and the stream-collide.
-void ev_record(lbm_ctx* c, int kind, bool start) {
+// Timing: events recorded on the stream at the boundaries of the phases.
+// The interval from one event to the next is charged to the phase that
+// began at the first (ev_kind: 0 forcing, 1 stream-collide, -1 none).  With
+// `chain` (nothing enqueued since the last event, which closed a phase) that
+// event also opens the new phase, so consecutive phases share a boundary
+// and each costs one event record.
+void ev_mark(lbm_ctx* c, int kind, bool chain) {
   if (!c->timing) return;
-  if (c->ev_used + 1 >= c->ev_pool.size()) {
+  if (chain && c->ev_used > 0 && c->ev_kind[c->ev_used - 1] < 0) {
+    c->ev_kind[c->ev_used - 1] = kind;
+    return;
+  }
+  if (c->ev_used >= c->ev_pool.size()) {
     size_t old = c->ev_pool.size();
     c->ev_pool.resize(std::max<size_t>(64, 2 * old));
     for (size_t k = old; k < c->ev_pool.size(); ++k) (void)hipEventCreate(&c->ev_pool[k]);
   }
   (void)hipEventRecord(c->ev_pool[c->ev_used++], c->stream);
-  if (start) c->ev_kind.push_back(kind);
+  c->ev_kind.resize(c->ev_used);
+  c->ev_kind[c->ev_used - 1] = kind;
 }
 
 void ev_collect(lbm_ctx* c) {
   if (c->ev_used == 0) return;
   (void)hipEventSynchronize(c->ev_pool[c->ev_used - 1]);
-  for (size_t k = 0; k + 1 < c->ev_used && k / 2 < c->ev_kind.size(); k += 2) {
+  for (size_t k = 0; k + 1 < c->ev_used; ++k) {
+    const int kind = c->ev_kind[k];
+    if (kind < 0) continue;
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]);
-    const int kind = c->ev_kind[k / 2];
     c->t_acc[kind] += ms;
     c->t_acc[2 + kind] += 1.0;
   }
@@ -88,14 +99,14 @@ void ev_collect(lbm_ctx* c) {
   c->ev_kind.clear();
 }
 
-lbm_status do_forcing(lbm_ctx* c) {
+// chain: see ev_mark.
+lbm_status do_forcing(lbm_ctx* c, bool chain) {
   if ((c->flags & IBM_WARM_START) && !c->theta_set)
     return fail(c, LBM_ERR_STATE, "IBM_WARM_START needs ibm_set_mlp first");
-  ev_record(c, 0, true);
+  ev_mark(c, 0, chain);
   hipError_t e = launch_forcing(c);
   if (e != hipSuccess) return hip_fail(c, e, "forcing");
-  ev_record(c, 0, false);
-  if (c->ev_used > 4000) ev_collect(c);
+  ev_mark(c, -1, false);
   if (c->flags & IBM_WARM_PREV) c->du_prev_valid = true;
   c->g_valid_step = c->step;
   return LBM_OK;
@@ -274,6 +285,7 @@ void lbm_destroy(lbm_ctx* c) {
     (void)hipEventDestroy(c->meta_event);
   }
   if (c->meta_host) (void)hipHostFree(c->meta_host);
+  if (c->stage) (void)hipFree(c->stage);
   delete c;
 }
 
@@ -325,7 +337,7 @@ lbm_status ibm_set_points(lbm_ctx* c, int64_t n, const float* rest_xyz, const fl
 lbm_status ibm_force_iterate(lbm_ctx* c, ibm_stats* stats) {
   if (!c) return LBM_ERR_ARG;
   if (c->npts == 0) return fail(c, LBM_ERR_STATE, "no Lagrangian points set");
-  lbm_status st = do_forcing(c);
+  lbm_status st = do_forcing(c, false);
   if (st != LBM_OK) return st;
   if (c->check_every > 0) {
     st = check_status(c, "after the forcing");
@@ -379,21 +391,27 @@ lbm_status ibm_log_pairs(lbm_ctx* c, float* features, float* targets) {
 lbm_status lbm_step(lbm_ctx* c, int32_t n_steps) {
   if (!c) return LBM_ERR_ARG;
   if (n_steps < 0) return fail(c, LBM_ERR_ARG, "n_steps must be >= 0");
+  // chain: the last timing event closed a phase of this call and nothing has
+  // been enqueued since (see ev_mark)
+  bool chain = false;
   for (int32_t s = 0; s < n_steps; ++s) {
     if (c->npts > 0 && c->g_valid_step != c->step) {
-      lbm_status st = do_forcing(c);
+      lbm_status st = do_forcing(c, chain);
       if (st != LBM_OK) return st;
+      chain = true;
     }
-    ev_record(c, 1, true);
+    ev_mark(c, 1, chain);
     hipError_t e = launch_stream_collide(c);
     if (e != hipSuccess) return hip_fail(c, e, "stream_collide");
-    ev_record(c, 1, false);
+    ev_mark(c, -1, false);
+    chain = true;
     if (c->ev_used > 4000) ev_collect(c);
     c->have_sums = true;
     c->step += 1;
     if (c->check_every > 0 && ++c->check_since >= c->check_every) {
       lbm_status st = check_status(c, "after the stream-collide");
       if (st != LBM_OK) return st;
+      chain = false;
     }
   }
   return LBM_OK;
@@ -403,13 +421,27 @@ lbm_status lbm_step(lbm_ctx* c, int32_t n_steps) {
 
 namespace {
 
-// Device staging for host destinations/sources.
-struct Staging {
-  void* p = nullptr;
-  ~Staging() {
-    if (p) (void)hipFree(p);
+// The context's device staging buffer for host destinations and sources,
+// grown to at least `bytes`.  Each use ends with a synchronisation of the
+// context's stream, so a buffer that is replaced is idle.
+hipError_t stage_at_least(lbm_ctx* c, size_t bytes, void** p) {
+  if (bytes > c->stage_bytes) {
+    if (c->stage) {
+      const hipError_t e = hipFree(c->stage);
+      c->stage = nullptr;
+      c->stage_bytes = 0;
+      if (e != hipSuccess) return e;
+    }
+    const hipError_t e = hipMalloc(&c->stage, bytes);
+    if (e != hipSuccess) {
+      c->stage = nullptr;
+      return e;
+    }
+    c->stage_bytes = bytes;
   }
-};
+  *p = c->stage;
+  return hipSuccess;
+}
 
 }  // namespace
 
@@ -445,7 +477,6 @@ lbm_status lbm_read_fields(lbm_ctx* c, uint32_t mask, const lbm_fields* dst) {
   double* ptx = dst->pt_x;
   float *ptub = dst->pt_ub, *ptg = dst->pt_g, *ptdu = dst->pt_du;
   double* sums = dst->sums;
-  Staging st;
   if (!dev) {
     size_t bytes = 0;
     auto want = [&](uint32_t bit, size_t b) -> size_t {
@@ -459,8 +490,9 @@ lbm_status lbm_read_fields(lbm_ctx* c, uint32_t mask, const lbm_fields* dst) {
            o_x = want(LBM_F_PT_X, 24 * np), o_ub = want(LBM_F_PT_UB, 12 * np),
            o_g = want(LBM_F_PT_G, 12 * np), o_du = want(LBM_F_PT_DU, 12 * np),
            o_s = want(LBM_F_SUMS, 32);
-    if (bytes) HIP_TRY(c, hipMalloc(&st.p, bytes));
-    char* b = (char*)st.p;
+    void* stage = nullptr;
+    if (bytes) HIP_TRY(c, stage_at_least(c, bytes, &stage));
+    char* b = (char*)stage;
     rho = (mask & LBM_F_RHO) ? (float*)(b + o_rho) : nullptr;
     vel = (mask & LBM_F_VEL) ? (float*)(b + o_vel) : nullptr;
     force = (mask & LBM_F_FORCE) ? (float*)(b + o_f) : nullptr;
@@ -525,11 +557,11 @@ lbm_status lbm_write_fields(lbm_ctx* c, uint32_t mask, const lbm_fields* src) {
   if (mask & LBM_F_POPS) {
     const size_t b = (src->pops_f64 ? 8 : 4) * 19 * nc;
     const void* p = src->pops;
-    Staging st;
     if (!dev) {
-      HIP_TRY(c, hipMalloc(&st.p, b));
-      HIP_TRY(c, hipMemcpyAsync(st.p, src->pops, b, hipMemcpyHostToDevice, c->stream));
-      p = st.p;
+      void* stage = nullptr;
+      HIP_TRY(c, stage_at_least(c, b, &stage));
+      HIP_TRY(c, hipMemcpyAsync(stage, src->pops, b, hipMemcpyHostToDevice, c->stream));
+      p = stage;
     }
     hipError_t e = launch_unstream_from(c, p, src->pops_f64);
     if (e != hipSuccess) return hip_fail(c, e, "write pops");
@@ -538,12 +570,12 @@ lbm_status lbm_write_fields(lbm_ctx* c, uint32_t mask, const lbm_fields* src) {
     c->du_prev_valid = false;
   }
   if (mask & LBM_F_FORCE) {
-    Staging st;
     const float* p = src->force;
     if (!dev) {
-      HIP_TRY(c, hipMalloc(&st.p, 12 * nc));
-      HIP_TRY(c, hipMemcpyAsync(st.p, src->force, 12 * nc, hipMemcpyHostToDevice, c->stream));
-      p = (const float*)st.p;
+      void* stage = nullptr;
+      HIP_TRY(c, stage_at_least(c, 12 * nc, &stage));
+      HIP_TRY(c, hipMemcpyAsync(stage, src->force, 12 * nc, hipMemcpyHostToDevice, c->stream));
+      p = (const float*)stage;
     }
     hipError_t e = launch_copy_f32(c, c->G, p, 3 * c->ncell);
     if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t*)c->bflag, 0x01010101u, c->nbflag_words);

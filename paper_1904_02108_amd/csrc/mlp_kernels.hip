@@ -737,6 +737,10 @@ constexpr size_t ws_bytes(int64_t batch) {
 constexpr size_t MLP_NOALLOC_BYTES = ws_bytes(MLP_NOALLOC_MAX_BATCH);
 __device__ __align__(256) unsigned char scratch[MLP_NOALLOC_BYTES];
 
+// Sum of an epoch's batch losses on the device, in batch order: s[1] =
+// s[1] + s[0] (s[1] = s[0] for the first batch), read once per epoch.
+__global__ void k_loss_acc(double* s, bool first) { s[1] = (first ? 0.0 : s[1]) + s[0]; }
+
 TrainWS carve_ws(void* ws, int64_t B) {
   TrainWS w;
   char* p = (char*)ws;
@@ -933,7 +937,6 @@ lbm_status mlp_train(float* theta, float* m, float* v, int64_t* step_t, int64_t 
   const TrainWS w = carve_ws(workspace, batch);
   float* grad = w.grad;
   for (int ep = 0; ep < n_epochs; ++ep) {
-    double acc = 0.0;
     int64_t nbatches = 0;
     for (int64_t b0 = 0; b0 < n; b0 += batch) {
       const int64_t B = std::min<int64_t>(batch, n - b0);
@@ -945,15 +948,19 @@ lbm_status mlp_train(float* theta, float* m, float* v, int64_t* step_t, int64_t 
       k_adam<<<(NPARAM + 255) / 256, 256, 0, st>>>(theta, grad, m, v, (float)lr, c1, c2);
       if (hipGetLastError() != hipSuccess) return LBM_ERR_HIP;
       if (loss_per_epoch) {
-        double l = 0.0;
-        if (hipMemcpyAsync(&l, w.small, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-          return LBM_ERR_HIP;
-        acc += l;
+        k_loss_acc<<<1, 1, 0, st>>>(w.small, nbatches == 0);
+        if (hipGetLastError() != hipSuccess) return LBM_ERR_HIP;
       }
       ++nbatches;
     }
-    if (loss_per_epoch) loss_per_epoch[ep] = nbatches ? acc / (double)nbatches : 0.0;
+    if (loss_per_epoch) {
+      double acc = 0.0;
+      if (hipMemcpyAsync(&acc, w.small + 1, sizeof(double), hipMemcpyDeviceToHost, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return LBM_ERR_HIP;
+      loss_per_epoch[ep] = nbatches ? acc / (double)nbatches : 0.0;
+    }
   }
   return LBM_OK;
 }
