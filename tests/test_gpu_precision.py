@@ -100,8 +100,9 @@ def test_c1_100_steps_by_storage(L, c1_oracle_100, storage, tol):
     """C3 on the single-propeller geometry: 100 steps of C1 with FP32, FP16
     and BF16 population storage against the FP64 oracle (velocity, density
     deviation, per-point correction, force; mass drift reported).  The
-    16-bit bounds are about four times the measured errors (FP16: velocity
-    4.3e-4, force 4.8e-4; BF16: 3.3e-3, 3.1e-3): storing f - t_i with an
+    16-bit bounds are 3.5 to 4 times the largest errors of a 16-member
+    realisation ensemble (tests/precision_ensemble.py; FP16: velocity
+    5.0e-4, force 5.4e-4; BF16: 4.2e-3, 4.3e-3): storing f - t_i with an
     11-bit (8-bit) significand, rounded once per step, is the only
     difference from the FP32 path."""
     wl, rho_r, U_r, r = c1_oracle_100
@@ -121,11 +122,19 @@ GOLDEN_500 = __import__("os").path.join(__import__("os").path.dirname(__file__),
                                         "c1_500_steps.npz")
 
 
-# bounds about three times the measured errors (velocity, force, du):
-# FP32 2.4e-5, 6.0e-6, 1.5e-6; FP16 5.7e-3, 4.9e-4, 4.7e-4; BF16 0.16, 5.5e-3,
-# 5.6e-3.  The wake of C1 (Re about 800) amplifies any perturbation of the
-# flow; BF16's 8-bit significand, rounded once per step, perturbs it most.
-C1_500_TOL = {0: (1e-4, 2e-5, 5e-6), 1: (2e-2, 2e-3, 2e-3), 2: (0.5, 2e-2, 2e-2)}
+# The wake of C1 (Re about 800) amplifies any perturbation of the flow, so
+# after 500 steps the error is a random variable over rounding realisations:
+# any change to a kernel's FP32 arithmetic draws another one.  Bounds
+# (velocity, force, du) are twice the largest error of a 16-member ensemble
+# (tests/precision_ensemble.py: 8 realisations each of two forms of the
+# collision arithmetic), rounded up; the FP32 ones are about three times it.
+# Ensemble maxima: FP32 3.1e-5, 4.9e-6, 1.7e-6; FP16 4.1e-2, 2.0e-3, 8.4e-4;
+# BF16 0.41, 1.3e-2, 7.8e-3.  BF16's 8-bit significand, rounded once per
+# step, decorrelates the wake's velocity from the reference (0.04 to 0.41
+# across the ensemble): for it the 500-step velocity bound (1.0) only
+# catches a blow-up; its velocity is checked after 100 steps above, the
+# forces and corrections here.
+C1_500_TOL = {0: (1e-4, 2e-5, 5e-6), 1: (8e-2, 4e-3, 2e-3), 2: (1.0, 3e-2, 2e-2)}
 
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
