@@ -24,6 +24,37 @@ __device__ __forceinline__ void cell_xyz(const LatticeGeom& g, int64_t cell, int
 // workgroup also writes FP64 partial sums of (rho - 1, rho U).
 // ---------------------------------------------------------------------------
 
+// e_i . (ax, ay, az) over the nonzero components of e_i (entries -1, 0, 1),
+// added in x, y, z order: for finite operands the value of the full dot
+// product, without its products by zero.
+__device__ __forceinline__ float edot(int i, float ax, float ay, float az) {
+  float r = 0.0f;
+  bool any = false;
+  if (EX[i]) {
+    r = EX[i] > 0 ? ax : -ax;
+    any = true;
+  }
+  if (EY[i]) {
+    const float t = EY[i] > 0 ? ay : -ay;
+    r = any ? r + t : t;
+    any = true;
+  }
+  if (EZ[i]) {
+    const float t = EZ[i] > 0 ? az : -az;
+    r = any ? r + t : t;
+  }
+  return r;
+}
+
+// The D3Q19 table lists opposite directions in pairs: e_{i+1} = -e_i for odd i.
+constexpr bool opposite_pairs() {
+  for (int i = 1; i < Q; i += 2)
+    if (OPP[i] != i + 1 || EX[i + 1] != -EX[i] || EY[i + 1] != -EY[i] || EZ[i + 1] != -EZ[i])
+      return false;
+  return true;
+}
+static_assert(opposite_pairs(), "opposite directions in consecutive pairs");
+
 // Collision of one cell: f holds the post-stream offsets on entry and the
 // post-collision ones on return; (gx, gy, gz) is the acceleration at the
 // cell.  Returns rho - 1 and rho U before the force.
@@ -59,13 +90,16 @@ __device__ __forceinline__ void collide_cell(const LatticeGeom& g, float f[Q], f
   const float fx = rho * gx, fy = rho * gy, fz = rho * gz;
   const float uF = ux * fx + uy * fy + uz * fz;
   const float guo = 1.0f - 0.5f * om;
+  // e_i . u and e_i . F: formed for the rest and the odd directions, negated
+  // for the even ones (e_{i+1} = -e_i)
+  float eu = 0.0f, eF = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float eu = EX[i] * ux + EY[i] * uy + EZ[i] * uz;
+    eu = (i & 1) || i == 0 ? edot(i, ux, uy, uz) : -eu;
     const float feq = wgt(i) * (drho + rho * (3.0f * eu + 4.5f * eu * eu - 1.5f * uu));
     float post = f[i] + om * (feq - f[i]);
     if (FORCING == LBM_FORCE_GUO) {
-      const float eF = EX[i] * fx + EY[i] * fy + EZ[i] * fz;
+      eF = (i & 1) || i == 0 ? edot(i, fx, fy, fz) : -eF;
       post += guo * wgt(i) * (3.0f * (eF - uF) + 9.0f * eu * eF);
     }
     f[i] = post;
