@@ -991,13 +991,33 @@ __device__ __forceinline__ void spread_bound(const KeptPoint& kp, float vs,
 // The interpolation pass of one point (§3; Algorithm 1): u = sum_taps U W
 // from the staged box, g = u_b - u, du = (first ? 0 : du) + s g (stored);
 // returns the raw spread vector and adds the residual and bound terms.
+// The point's data as the interpolation reads them: fraction and s, u_b and
+// box index, the du of the previous sweeps (zero in the first).
+struct PointIn {
+  float4 fr, ub, du;
+};
+
+__device__ __forceinline__ PointIn load_point_in(uint32_t k, const float4* __restrict__ sp_frac,
+                                                 const float4* __restrict__ sp_ub,
+                                                 const float4* __restrict__ sp_du, int mode) {
+  PointIn pi;
+  pi.fr = sp_frac[k];
+  pi.ub = sp_ub[k];
+  pi.du = (mode & SW_FIRST) ? make_float4(0.f, 0.f, 0.f, 0.f) : sp_du[k];
+  return pi;
+}
+
+// PRE: the point's data come loaded in pin; else they are loaded here (du
+// only after the taps, which keeps it out of the registers of the tap loop).
+template <bool PRE>
 __device__ __forceinline__ KeptPoint interp_point(
-    uint32_t k, const float4* __restrict__ sU, const float4* __restrict__ sp_frac,
-    const float4* __restrict__ sp_ub, float4* __restrict__ sp_g, float4* __restrict__ sp_du,
-    const int4* __restrict__ sp_base, float4* __restrict__ g_orig, int mode, bool store_g,
-    double& res, unsigned long long& bsum, uint32_t* __restrict__ bad) {
-  const float4 fr = sp_frac[k];
-  const float4 ub = sp_ub[k];
+    uint32_t k, const PointIn& pin, const float4* __restrict__ sU,
+    const float4* __restrict__ sp_frac, const float4* __restrict__ sp_ub,
+    float4* __restrict__ sp_g, float4* __restrict__ sp_du, const int4* __restrict__ sp_base,
+    float4* __restrict__ g_orig, int mode, bool store_g, double& res, unsigned long long& bsum,
+    uint32_t* __restrict__ bad) {
+  const float4 fr = PRE ? pin.fr : sp_frac[k];
+  const float4 ub = PRE ? pin.ub : sp_ub[k];
   KeptPoint kp;
   kp.l0 = __float_as_int(ub.w);
   float wx[4], wy[4], wz[4];
@@ -1024,7 +1044,7 @@ __device__ __forceinline__ KeptPoint interp_point(
   }
   const float g0 = ub.x - u0, g1 = ub.y - u1, g2 = ub.z - u2;
   const float s = fr.w;
-  float4 du = (mode & SW_FIRST) ? make_float4(0.f, 0.f, 0.f, 0.f) : sp_du[k];
+  float4 du = PRE ? pin.du : ((mode & SW_FIRST) ? make_float4(0.f, 0.f, 0.f, 0.f) : sp_du[k]);
   du.x += s * g0;
   du.y += s * g1;
   du.z += s * g2;
@@ -1144,7 +1164,13 @@ __device__ __forceinline__ void spread_point(const KeptPoint& kp, float4 fr, flo
 // partial of s |g|^2 when interpolating.
 //
 // 21 KB of LDS per workgroup: 7 workgroups of 4 waves fit a CU.
-__global__ __launch_bounds__(WG, 7) void k_sweep_tiles(
+//
+// PREF (launches over few tiles, whose time is the chain of memory round
+// trips of one workgroup): each thread's first point is loaded before the
+// box is staged, the two loads overlapping, and its fraction is kept for the
+// spread pass; more registers, so fewer waves per SIMD.
+template <bool PREF>
+__global__ __launch_bounds__(WG, PREF ? 4 : 7) void k_sweep_tiles(
     const uint32_t* __restrict__ own_tiles, const uint32_t* __restrict__ meta,
     const uint32_t* __restrict__ start_own, const uint32_t* __restrict__ end_own,
     const int4* __restrict__ sp_base, const float4* __restrict__ sp_frac,
@@ -1179,6 +1205,9 @@ __global__ __launch_bounds__(WG, 7) void k_sweep_tiles(
     // the point range is loaded before the box is staged (one memory round
     // trip fewer on the path of a lone tile)
     const uint32_t p0 = start_own[t], P = end_own[t] - p0;
+    PointIn pf;
+    if (PREF && interp && threadIdx.x < P)
+      pf = load_point_in(p0 + threadIdx.x, sp_frac, sp_ub, sp_du, mode);
     int o[3];
     tile_origin(pg, t, o);
     __syncthreads();  // the previous tile's box has been stored
@@ -1217,8 +1246,12 @@ __global__ __launch_bounds__(WG, 7) void k_sweep_tiles(
       keep[q].l0 = 0;
       if (i < P) {
         if (interp) {
-          keep[q] = interp_point(p0 + i, sU, sp_frac, sp_ub, sp_g, sp_du, sp_base, g_orig, mode,
-                                 store_g, res, bsum, bad);
+          if (PREF && q == 0)
+            keep[q] = interp_point<true>(p0 + i, pf, sU, sp_frac, sp_ub, sp_g, sp_du, sp_base,
+                                         g_orig, mode, store_g, res, bsum, bad);
+          else
+            keep[q] = interp_point<false>(p0 + i, pf, sU, sp_frac, sp_ub, sp_g, sp_du, sp_base,
+                                          g_orig, mode, store_g, res, bsum, bad);
         } else {
           keep[q] = load_point(p0 + i, sp_ub, sp_g, sp_du, sp_base, du_prev, mode);
           spread_bound(keep[q], spread_weight(mode, sp_frac[p0 + i].w), bsum, bad);
@@ -1228,8 +1261,8 @@ __global__ __launch_bounds__(WG, 7) void k_sweep_tiles(
     for (uint32_t i = threadIdx.x + KEEP * WG; i < P; i += WG) {
       if (interp) {
         // the spread pass reads this point's vector back from sp_g / sp_du
-        (void)interp_point(p0 + i, sU, sp_frac, sp_ub, sp_g, sp_du, sp_base, g_orig, mode,
-                           store_g || (spread && !spread_du), res, bsum, bad);
+        (void)interp_point<false>(p0 + i, pf, sU, sp_frac, sp_ub, sp_g, sp_du, sp_base, g_orig,
+                                  mode, store_g || (spread && !spread_du), res, bsum, bad);
       } else {
         const KeptPoint kp = load_point(p0 + i, sp_ub, sp_g, sp_du, sp_base, du_prev, mode);
         spread_bound(kp, spread_weight(mode, sp_frac[p0 + i].w), bsum, bad);
@@ -1253,19 +1286,19 @@ __global__ __launch_bounds__(WG, 7) void k_sweep_tiles(
     __syncthreads();
     // pass 2: spread into the box (every tap of an owned point is inside it)
     const int rot = lane & 15;
-    auto spread_one = [&](const KeptPoint& kp, uint32_t k) {
-      const float4 fr = sp_frac[k];
+    auto spread_one = [&](const KeptPoint& kp, uint32_t k, bool prefetched) {
+      const float4 fr = (PREF && prefetched) ? pf.fr : sp_frac[k];
       if (save_du) du_prev[sp_base[k].w] = make_float4(kp.v0, kp.v1, kp.v2, 0.f);
       spread_point(kp, fr, spread_weight(mode, fr.w) * scale, accxy, accz, rot);
     };
 #pragma unroll
     for (int q = 0; q < KEEP; ++q) {
       const uint32_t i = threadIdx.x + q * WG;
-      if (i < P) spread_one(keep[q], p0 + i);
+      if (i < P) spread_one(keep[q], p0 + i, q == 0 && interp);
     }
     for (uint32_t i = threadIdx.x + KEEP * WG; i < P; i += WG)
       spread_one(load_point(p0 + i, sp_ub, sp_g, sp_du, sp_base, du_prev, mode & ~SW_LOAD_PREV),
-                 p0 + i);
+                 p0 + i, false);
     __syncthreads();
     unsigned char* slot = boxbuf + (int64_t)e * BOX_SLOT_BYTES;
     unsigned long long* sxy = reinterpret_cast<unsigned long long*>(slot);
@@ -1612,6 +1645,9 @@ PointGeom point_geom(const lbm_ctx* c) {
 #define LBM_TILE_GRID_MAX 32768
 #endif
 constexpr uint32_t META_EVERY = 8;
+#ifndef SWEEP_PREF_TILES
+#define SWEEP_PREF_TILES 1024
+#endif
 
 int64_t tile_grid(const lbm_ctx* c, int list) {
   const int64_t full = std::min<int64_t>((c->ntiles + 7) / 8 * 8, LBM_TILE_GRID_MAX);
@@ -1728,13 +1764,14 @@ hipError_t launch_forcing(lbm_ctx* c) {
     if (e != hipSuccess) return e;
     c->nbr_valid = true;
   }
+  // few owner tiles (a recent forcing's count): the latency form of the sweep
+  const bool pref = c->prev_len_valid && c->prev_len[0] <= SWEEP_PREF_TILES;
   auto sweep = [&](int it, int mode, const uint32_t* gate, float4* g_orig) {
-    k_sweep_tiles<<<lg, WG, 0, st>>>(c->own_tiles, c->meta, c->start_own, c->end_own,
-                                     c->sp_base, c->sp_frac,
-                                     c->sp_ub, c->sp_g, c->sp_du, c->U,
-                                     (unsigned char*)c->boxbuf, pg, mode | uw,
-                                     c->pt_partials + (2 + it) * rs, gate, g_orig, c->du_prev,
-                                     c->status);
+    auto kern = pref ? k_sweep_tiles<true> : k_sweep_tiles<false>;
+    kern<<<lg, WG, 0, st>>>(c->own_tiles, c->meta, c->start_own, c->end_own, c->sp_base,
+                            c->sp_frac, c->sp_ub, c->sp_g, c->sp_du, c->U,
+                            (unsigned char*)c->boxbuf, pg, mode | uw,
+                            c->pt_partials + (2 + it) * rs, gate, g_orig, c->du_prev, c->status);
     return hipGetLastError();
   };
   auto merge = [&](bool final_, const uint32_t* gate) {
