@@ -308,6 +308,35 @@ def half_rate_leg(torch, L, W, name, steps, warmup):
             "steps": steps, "warmup": warmup}
 
 
+def blowup_leg(torch, L, W, name, max_steps=300, every=5):
+    """The configured workload from rest with the library's non-finite check
+    on every step (lbm_set_check): the first step after which the FP64 sums
+    or a spread value are no longer finite (LBM_ERR_NONFINITE), and the first
+    probed step whose peak speed exceeds the lattice sound speed."""
+    wl = W.config(name)
+    sim = L.Simulation(wl.shape, wl.tau, bc=wl.bc, forcing=wl.forcing, max_points=wl.n_points,
+                       max_iter=wl.n_iter, device="cuda:0")
+    sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter)
+    sim.set_check(1)
+    out = {"max_steps": max_steps, "first_nonfinite_step": None, "message": None,
+           "first_supersonic_step": None, "speed_probe_every": every}
+    for s in range(1, max_steps + 1):
+        try:
+            sim.step(1)
+        except L.LbmError as e:
+            if e.status != L.LBM_ERR_NONFINITE:
+                raise
+            out["first_nonfinite_step"] = s
+            out["message"] = str(e)
+            break
+        if out["first_supersonic_step"] is None and s % every == 0:
+            vmax = float(sim.read("vel")["vel"].abs().max())
+            if not vmax < 3.0 ** -0.5:
+                out["first_supersonic_step"] = s
+    sim.close()
+    return out
+
+
 def precision_leg(torch, L, W, name, storage, steps=10, warmup=3):
     """C3: the same workload with populations stored as FP16 or BF16 offsets
     (FP32 arithmetic): MLUPS and the stream-collide against the 76 B/cell
@@ -492,6 +521,8 @@ def main():
                     help="skip the velocity-shift vs Guo comparison on closed-form flows")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm-start comparison on the single-propeller case")
+    ap.add_argument("--no-blowup-probe", action="store_true",
+                    help="skip the run of the configured workload with the non-finite check on")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also time a plain streaming kernel (read + write of half the lattice bytes each)")
     args = ap.parse_args()
@@ -596,6 +627,9 @@ def main():
     torch.cuda.empty_cache()
     if args.workload in ("c2", "c2_dense") and not args.no_half_rate:
         out["half_rate"] = half_rate_leg(torch, L, W, args.workload, args.steps, args.warmup)
+        torch.cuda.empty_cache()
+    if args.workload in ("c2", "c2_dense") and not args.no_blowup_probe:
+        out["blowup"] = blowup_leg(torch, L, W, args.workload)
         torch.cuda.empty_cache()
     if not args.no_precision:
         out["precision"] = {sname: precision_leg(torch, L, W, args.workload, st)
