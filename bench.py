@@ -490,8 +490,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     # the dense 64-propeller flow (tip speeds up to Mach 0.72 at tau 0.55, as
-    # configured) stops being finite near step 60: 5 + 30 steps keep the
-    # timed window, whose work does not depend on the values, on a finite flow
+    # configured) exceeds the sound speed from step 15 and spreads values
+    # beyond the fixed-point range after step 36 (the blow-up probe): 5 + 30
+    # steps keep the timed window, whose work does not depend on the values,
+    # before the latter
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2_dense",
