@@ -26,6 +26,9 @@ namespace {
 
 constexpr int BOX = TILE + 3;             // interpolation box edge: tile + taps -1..+2
 constexpr int BOX3 = BOX * BOX * BOX;
+// a point's first tap is box cell l0 = lx + BOX (ly + BOX lz) with its local
+// cell (lx, ly, lz) in 0..TILE-1; its taps add 0..3 per axis: all in the box
+static_assert((TILE - 1 + 3) * (1 + BOX + BOX * BOX) == BOX3 - 1, "taps inside the box");
 constexpr int TILE3 = TILE * TILE * TILE;
 constexpr int WG = 256;                   // threads of the per-tile point kernels
 
