@@ -107,16 +107,31 @@ struct Store<LBM_STORE_BF16> {
 // bb_add[a][face][i]: term added to population i when it is reflected at the
 // wall of axis a (face 0 = low, 1 = high): 6 t_i rho_w e_i . u_w.
 // ---------------------------------------------------------------------------
+// Population layout of a lattice buffer: population i of cell (x, y, z) is
+// element i spop + x + y srow + z splane.  Below 4 GB per lattice the 19
+// populations of each x row of cells are interleaved ([z][y][i][x], rows
+// padded to 128 bytes: spop = padded row, srow = 19 spop), so that a
+// workgroup's accesses to one row of cells stay within one 19-row stretch;
+// else one array per population ([i][z][y][x]: srow = nx, splane = nx ny).
+// Offsets of a cell (x + y srow + z splane) fit in 32 bits in both forms.
 struct LatticeGeom {
   int nx, ny, nz;
   int bc[3];
   int64_t ncell;
-  int64_t stride;  // elements between consecutive population arrays
+  int64_t spop;       // elements between a cell's consecutive populations
+  int64_t srow;       // elements between rows (y) of cells
+  int64_t splane;     // elements between planes (z) of cells
+  int64_t lat_elems;  // elements of one lattice buffer
   float bb_add[3][2][Q];
   float tau, omega;   // omega = 1 / tau
   float g_ext[3];
   int fblk_x, fblk_y;  // grid of 4^3 force blocks (x, y extent) for flag lookups
 };
+
+// Element offset of population 0 of cell (x, y, z) in a lattice buffer.
+__device__ __forceinline__ int64_t lat_cell(const LatticeGeom& g, int x, int y, int z) {
+  return (int64_t)x + (int64_t)y * g.srow + (int64_t)z * g.splane;
+}
 
 
 // Pull-stream gather of the 19 post-stream offsets at cell (x, y, z) from the
@@ -127,7 +142,7 @@ __device__ __forceinline__ void gather_pull(const typename Store<S>::T* __restri
                                             const LatticeGeom& g, int x, int y, int z,
                                             float f[Q]) {
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int64_t here = (int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z);
+  const int64_t here = lat_cell(g, x, y, z);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     int sx = x - EX[i], sy = y - EY[i], sz = z - EZ[i];
@@ -157,10 +172,9 @@ __device__ __forceinline__ void gather_pull(const typename Store<S>::T* __restri
       }
     }
     if (wall_axis < 0) {
-      const int64_t src = (int64_t)sx + (int64_t)nx * ((int64_t)sy + (int64_t)ny * sz);
-      f[i] = Store<S>::load(lat + (int64_t)i * g.stride + src);
+      f[i] = Store<S>::load(lat + (int64_t)i * g.spop + lat_cell(g, sx, sy, sz));
     } else {
-      f[i] = Store<S>::load(lat + (int64_t)OPP[i] * g.stride + here) +
+      f[i] = Store<S>::load(lat + (int64_t)OPP[i] * g.spop + here) +
              g.bb_add[wall_axis][wall_face][i];
     }
   }
@@ -178,7 +192,7 @@ __device__ __forceinline__ PullIdx pull_index(const LatticeGeom& g, int x, int y
   PullIdx p;
   const int n[3] = {g.nx, g.ny, g.nz};
   const int c[3] = {x, y, z};
-  const uint32_t mul[3] = {1u, (uint32_t)g.nx, (uint32_t)g.nx * (uint32_t)g.ny};
+  const uint32_t mul[3] = {1u, (uint32_t)g.srow, (uint32_t)g.splane};
   uint32_t* out[3] = {p.xs, p.ys, p.zs};
   p.fast = true;
 #pragma unroll
@@ -207,7 +221,7 @@ __device__ __forceinline__ void gather_fast(const typename Store<S>::T* __restri
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const typename Store<S>::T* q =
-        lat + (int64_t)i * g.stride + (p.xs[EX[i] + 1] + p.ys[EY[i] + 1] + p.zs[EZ[i] + 1]);
+        lat + (int64_t)i * g.spop + (p.xs[EX[i] + 1] + p.ys[EY[i] + 1] + p.zs[EZ[i] + 1]);
     f[i] = NT ? Store<S>::load_nt(q) : Store<S>::load(q);
   }
 }
@@ -222,7 +236,7 @@ __device__ __forceinline__ void gather_fast_buf(__amdgpu_buffer_rsrc_t rs, const
   for (int i = 0; i < Q; ++i) {
     const uint32_t off = (p.xs[EX[i] + 1] + p.ys[EY[i] + 1] + p.zs[EZ[i] + 1]) * 4u;
     f[i] = __uint_as_float(
-        __builtin_amdgcn_raw_buffer_load_b32(rs, off, (uint32_t)(i * g.stride * 4), 2));
+        __builtin_amdgcn_raw_buffer_load_b32(rs, off, (uint32_t)(i * g.spop * 4), 2));
   }
 }
 
@@ -247,7 +261,7 @@ __device__ __forceinline__ void gather_pair(const typename Store<S>::T* __restri
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const typename Store<S>::T* row =
-        lat + (int64_t)i * g.stride + (p.ys[EY[i] + 1] + p.zs[EZ[i] + 1]);
+        lat + (int64_t)i * g.spop + (p.ys[EY[i] + 1] + p.zs[EZ[i] + 1]);
     float a, b;
     Store<S>::load2_nt(row + x0, a, b);
     if (EX[i] == 0) {
@@ -275,7 +289,7 @@ __device__ __forceinline__ void gather_pair_buf_bf16(__amdgpu_buffer_rsrc_t rs,
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const uint32_t row = p.ys[EY[i] + 1] + p.zs[EZ[i] + 1];
-    const uint32_t soff = (uint32_t)(i * g.stride * 2);
+    const uint32_t soff = (uint32_t)(i * g.spop * 2);
     const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(rs, (row + (uint32_t)x0) * 2u, soff, 2);
     const float a = __uint_as_float(u << 16), b = __uint_as_float(u & 0xffff0000u);
     if (EX[i] == 0) {

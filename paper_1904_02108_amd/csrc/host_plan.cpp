@@ -87,11 +87,34 @@ lbm_status check_params(const lbm_params* p, std::string& msg) {
   return LBM_OK;
 }
 
+// lattices of fewer bytes than this get interleaved populations (at most
+// 4 GB: the stream-collide's buffer descriptors take 32-bit offsets)
+#ifndef LBM_INTERLEAVE_MAX_BYTES
+#define LBM_INTERLEAVE_MAX_BYTES 4294967296ll
+#endif
+static_assert(LBM_INTERLEAVE_MAX_BYTES <= 4294967296ll, "32-bit lattice offsets");
+
 void make_plan(const lbm_params* p, Plan& pl) {
   pl.ncell = (int64_t)p->nx * p->ny * p->nz;
   pl.elem = p->storage == LBM_STORE_F32 ? 4 : 2;
-  pl.pop_stride = align_up((size_t)pl.ncell * pl.elem) / pl.elem;
-  pl.lat_bytes = pl.pop_stride * pl.elem * lbmd::Q;
+  // populations of each x row interleaved, rows padded to 128 bytes, when a
+  // lattice stays below 4 GB (32-bit buffer offsets); else one array per
+  // population
+  const int64_t row_align = 128 / (int64_t)pl.elem;
+  const int64_t nxp = ((int64_t)p->nx + row_align - 1) / row_align * row_align;
+  const int64_t inter = (int64_t)lbmd::Q * nxp * p->ny * p->nz;
+  if (inter * (int64_t)pl.elem < (int64_t)LBM_INTERLEAVE_MAX_BYTES) {
+    pl.spop = nxp;
+    pl.srow = (int64_t)lbmd::Q * nxp;
+    pl.splane = pl.srow * p->ny;
+    pl.lat_elems = inter;
+  } else {
+    pl.spop = (int64_t)(align_up((size_t)pl.ncell * pl.elem) / pl.elem);
+    pl.srow = p->nx;
+    pl.splane = (int64_t)p->nx * p->ny;
+    pl.lat_elems = (int64_t)lbmd::Q * pl.spop;
+  }
+  pl.lat_bytes = align_up((size_t)pl.lat_elems * pl.elem);
   pl.size[LBM_BUF_LATTICE] = 2 * pl.lat_bytes;
   const size_t M = (size_t)std::max<int64_t>(p->max_points, 1);
   const int dims[3] = {p->nx, p->ny, p->nz};

@@ -20,7 +20,8 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 struct Plan {
   size_t size[LBM_NBUF];
   // lattice
-  size_t elem, pop_stride, lat_bytes;
+  size_t elem, lat_bytes;
+  int64_t spop, srow, splane, lat_elems;  // population layout (LatticeGeom)
   // points
   size_t o_rest, o_body_of, o_key, o_rank, o_base, o_frac, o_ub, o_g, o_du, o_tmp, o_bodies,
       o_motion;

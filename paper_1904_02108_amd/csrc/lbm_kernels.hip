@@ -141,7 +141,7 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
     const LatticeGeom g, const float* __restrict__ G, const uint8_t* __restrict__ flags,
     double* __restrict__ partials, uint32_t* __restrict__ bad) {
   static_assert(!BUF || S == LBM_STORE_F32, "buffer form for FP32 storage");
-  const uint32_t lat_bytes = BUF ? (uint32_t)(Q * g.stride * 4) : 0u;
+  const uint32_t lat_bytes = BUF ? (uint32_t)(g.lat_elems * 4) : 0u;
   const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)src, 0, lat_bytes, 0x00020000);
   const __amdgpu_buffer_rsrc_t rdst = __builtin_amdgcn_make_buffer_rsrc((void*)dst, 0, lat_bytes, 0x00020000);
   // 3-D launch: blockDim.x spans x, blockDim.y spans y, one z-plane per block
@@ -162,6 +162,9 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
     if (x < g.nx && y < g.ny) {
       const uint32_t cell =
           (uint32_t)x + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+      // the cell's offset in the lattice buffers (32 bits in either layout)
+      const uint32_t lc =
+          (uint32_t)x + (uint32_t)g.srow * (uint32_t)y + (uint32_t)g.splane * (uint32_t)z;
       float f[Q];
       if constexpr (BUF) {
         const PullIdx pi = pull_index(g, x, y, z);
@@ -183,11 +186,11 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
       if constexpr (BUF) {
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(f[i]), rdst, cell * 4u,
-                                                (uint32_t)(i * g.stride * 4), 2);
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(f[i]), rdst, lc * 4u,
+                                                (uint32_t)(i * g.spop * 4), 2);
       } else {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) Store<S>::store_nt(dst + (int64_t)i * g.stride + cell, f[i]);
+        for (int i = 0; i < Q; ++i) Store<S>::store_nt(dst + (int64_t)i * g.spop + lc, f[i]);
       }
       part[0] += drho;
       part[1] += jx;
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide_pairs(
     const LatticeGeom g, const float* __restrict__ G, const uint8_t* __restrict__ flags,
     double* __restrict__ partials, uint32_t* __restrict__ bad) {
   static_assert(!BUF || S == LBM_STORE_BF16, "buffer form for BF16 storage");
-  const uint32_t lat_bytes = BUF ? (uint32_t)(Q * g.stride * 2) : 0u;
+  const uint32_t lat_bytes = BUF ? (uint32_t)(g.lat_elems * 2) : 0u;
   const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)src, 0, lat_bytes, 0x00020000);
   const __amdgpu_buffer_rsrc_t rdst = __builtin_amdgcn_make_buffer_rsrc((void*)dst, 0, lat_bytes, 0x00020000);
   const int px = g.nx >> 1;
@@ -224,6 +227,8 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide_pairs(
   if (y < g.ny) {
     const uint32_t cell =
         (uint32_t)x0 + (uint32_t)g.nx * ((uint32_t)y + (uint32_t)g.ny * (uint32_t)z);
+    const uint32_t lc =
+        (uint32_t)x0 + (uint32_t)g.srow * (uint32_t)y + (uint32_t)g.splane * (uint32_t)z;
     float f0[Q], f1[Q];
     if constexpr (BUF) {
       const PullIdx pi = pull_index(g, x0, y, z);
@@ -261,12 +266,12 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide_pairs(
     if constexpr (BUF) {
 #pragma unroll
       for (int i = 0; i < Q; ++i)
-        __builtin_amdgcn_raw_buffer_store_b32(Store<S>::pack2(f0[i], f1[i]), rdst, cell * 2u,
-                                              (uint32_t)(i * g.stride * 2), 2);
+        __builtin_amdgcn_raw_buffer_store_b32(Store<S>::pack2(f0[i], f1[i]), rdst, lc * 2u,
+                                              (uint32_t)(i * g.spop * 2), 2);
     } else {
 #pragma unroll
       for (int i = 0; i < Q; ++i)
-        Store<S>::store2_nt(dst + (int64_t)i * g.stride + cell, f0[i], f1[i]);
+        Store<S>::store2_nt(dst + (int64_t)i * g.spop + lc, f0[i], f1[i]);
     }
   }
   store_partials(part, threadIdx.x, (int64_t)blockIdx.x + (int64_t)gridDim.x * blockIdx.z,
@@ -319,7 +324,7 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_unstream(typename Store<S>::T* __
       v = src.get(i, (int64_t)d[0] + (int64_t)g.nx * ((int64_t)d[1] + (int64_t)g.ny * d[2]));
     else
       v = src.get(OPP[i], cell) + (double)g.bb_add[wall_axis][wall_face][i];
-    Store<S>::store(dst + (int64_t)i * g.stride + cell, (float)v);
+    Store<S>::store(dst + (int64_t)i * g.spop + lat_cell(g, x, y, z), (float)v);
   }
 }
 
@@ -458,7 +463,7 @@ hipError_t stream_collide_s(lbm_ctx* c) {
   stream_collide_shape(c, grid, block);
   if constexpr (S != LBM_STORE_F32) {
     if constexpr (S == LBM_STORE_BF16) {
-      if (stream_collide_pairs(c) && (int64_t)Q * c->geom.stride * 2 < ((int64_t)1 << 32)) {
+      if (stream_collide_pairs(c) && c->geom.lat_elems * 2 < ((int64_t)1 << 32)) {
         if (c->p.forcing == LBM_FORCE_SHIFT)
           k_stream_collide_pairs<S, LBM_FORCE_SHIFT, true><<<grid, block, 0, c->stream>>>(
               src, dst, c->geom, c->G, c->bflag, c->sum_partials, c->status);
@@ -480,7 +485,7 @@ hipError_t stream_collide_s(lbm_ctx* c) {
   }
   const bool flat = stream_collide_flat(c);
   if constexpr (S == LBM_STORE_F32) {
-    if (!flat && (int64_t)Q * c->geom.stride * 4 < ((int64_t)1 << 32)) {
+    if (!flat && c->geom.lat_elems * 4 < ((int64_t)1 << 32)) {
       if (c->p.forcing == LBM_FORCE_SHIFT)
         k_stream_collide<S, LBM_FORCE_SHIFT, false, true><<<grid, block, 0, c->stream>>>(
             src, dst, c->geom, c->G, c->bflag, c->sum_partials, c->status);

@@ -47,7 +47,10 @@ void fill_geom(lbm_ctx* c, const Plan& pl) {
   g.nz = p.nz;
   for (int a = 0; a < 3; ++a) g.bc[a] = p.bc[a];
   g.ncell = pl.ncell;
-  g.stride = (int64_t)pl.pop_stride;
+  g.spop = pl.spop;
+  g.srow = pl.srow;
+  g.splane = pl.splane;
+  g.lat_elems = pl.lat_elems;
   for (int a = 0; a < 3; ++a)
     for (int f = 0; f < 2; ++f)
       for (int i = 0; i < lbmd::Q; ++i) {

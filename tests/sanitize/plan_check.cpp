@@ -44,7 +44,7 @@ void check_plan(const lbm_params& p) {
   const size_t elem = p.storage == LBM_STORE_F32 ? 4 : 2;
   const size_t nb4 = (size_t)((p.nx + 3) / 4) * ((p.ny + 3) / 4) * ((p.nz + 3) / 4);
   std::vector<Region> r = {
-      {LBM_BUF_LATTICE, 0, 2 * 19 * nc * elem, "lattices"},
+      {LBM_BUF_LATTICE, 0, 2 * (size_t)pl.lat_elems * elem, "lattices"},
       {LBM_BUF_FIELDS, 0, nt * 512 * 16, "U"},
       {LBM_BUF_FIELDS, pl.o_G, 3 * nc * 4, "G"},
       {LBM_BUF_FIELDS, pl.o_box, (size_t)pl.max_boxes * BOX_SLOT_BYTES, "boxes"},
@@ -95,7 +95,21 @@ void check_plan(const lbm_params& p) {
   expect((size_t)pl.part_row >= (nt + 7) / 8 * 8 && (size_t)pl.part_row >= (M + 255) / 256,
          tag + "partial row");
   expect(pl.max_boxes >= 1 && (size_t)pl.max_boxes >= std::min(nt, M), tag + "box count");
-  expect(pl.pop_stride * elem >= nc * elem && pl.pop_stride * elem % ALIGN == 0, tag + "stride");
+  // population layout: rows of interleaved populations, or one array per
+  // population; every (population, cell) has its own element, inside the
+  // buffer, and cell offsets fit in 32 bits
+  const bool inter = pl.srow == 19 * pl.spop;
+  if (inter)
+    expect(pl.spop >= p.nx && pl.splane == (int64_t)p.ny * pl.srow &&
+               (pl.spop * (int64_t)elem) % 128 == 0 && pl.lat_elems * (int64_t)elem < (1ll << 32),
+           tag + "interleaved rows");
+  else
+    expect(pl.srow == p.nx && pl.splane == (int64_t)p.nx * p.ny && pl.spop >= (int64_t)nc &&
+               (pl.spop * (int64_t)elem) % (int64_t)ALIGN == 0 && pl.lat_elems == 19 * pl.spop,
+           tag + "population arrays");
+  const int64_t last_cell = (p.nx - 1) + (int64_t)(p.ny - 1) * pl.srow + (int64_t)(p.nz - 1) * pl.splane;
+  expect(last_cell < (1ll << 32) && 18 * pl.spop + last_cell < pl.lat_elems, tag + "layout extent");
+  expect((size_t)pl.lat_elems * elem <= pl.lat_bytes && pl.lat_bytes % ALIGN == 0, tag + "lattice bytes");
   for (size_t i = 0; i < r.size(); ++i) {
     expect(r[i].off % ALIGN == 0, tag + r[i].name + " aligned");
     expect(r[i].off + r[i].bytes <= pl.size[r[i].buf], tag + r[i].name + " inside its buffer");
