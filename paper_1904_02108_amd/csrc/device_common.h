@@ -67,6 +67,13 @@ struct Store<LBM_STORE_F16> {
     v.y = (_Float16)b;
     __builtin_nontemporal_store(v, reinterpret_cast<V2*>(p));
   }
+  // the pair as one 32-bit word (a in the low half)
+  static __device__ __forceinline__ uint32_t pack2(float a, float b) {
+    V2 v;
+    v.x = (_Float16)a;
+    v.y = (_Float16)b;
+    return __builtin_bit_cast(uint32_t, v);
+  }
 };
 
 template <>
@@ -277,13 +284,15 @@ __device__ __forceinline__ void gather_pair(const typename Store<S>::T* __restri
   }
 }
 
-// The pair gather through a buffer resource (BF16 lattices of less than
+// The pair gather through a buffer resource (16-bit lattices of less than
 // 4 GB): one 4-byte load per population pair, one 2-byte load for the outer
 // value of an e_x = +-1 population; 32-bit byte offsets, the population's
 // offset as a scalar.  Streaming (nt) loads.  Away from walls only.
-__device__ __forceinline__ void gather_pair_buf_bf16(__amdgpu_buffer_rsrc_t rs,
-                                                     const LatticeGeom& g, const PullIdx& p,
-                                                     int x0, float f0[Q], float f1[Q]) {
+template <int S>
+__device__ __forceinline__ void gather_pair_buf(__amdgpu_buffer_rsrc_t rs, const LatticeGeom& g,
+                                                const PullIdx& p, int x0, float f0[Q],
+                                                float f1[Q]) {
+  static_assert(S != LBM_STORE_F32, "16-bit storage");
   const uint32_t xl = p.xs[2];                                   // x0 - 1, wrapped
   const uint32_t xr = (uint32_t)(x0 + 2 == g.nx ? 0 : x0 + 2);   // x0 + 2, wrapped
 #pragma unroll
@@ -291,14 +300,24 @@ __device__ __forceinline__ void gather_pair_buf_bf16(__amdgpu_buffer_rsrc_t rs,
     const uint32_t row = p.ys[EY[i] + 1] + p.zs[EZ[i] + 1];
     const uint32_t soff = (uint32_t)(i * g.spop * 2);
     const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(rs, (row + (uint32_t)x0) * 2u, soff, 2);
-    const float a = __uint_as_float(u << 16), b = __uint_as_float(u & 0xffff0000u);
+    float a, b;
+    if (S == LBM_STORE_F16) {
+      const typename Store<LBM_STORE_F16>::V2 v =
+          __builtin_bit_cast(typename Store<LBM_STORE_F16>::V2, u);
+      a = (float)v.x;
+      b = (float)v.y;
+    } else {
+      a = __uint_as_float(u << 16);
+      b = __uint_as_float(u & 0xffff0000u);
+    }
     if (EX[i] == 0) {
       f0[i] = a;
       f1[i] = b;
     } else {
       const uint32_t xo = EX[i] == 1 ? xl : xr;
       const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(rs, (row + xo) * 2u, soff, 2);
-      const float o = __uint_as_float(((uint32_t)h) << 16);
+      const float o = S == LBM_STORE_F16 ? (float)__builtin_bit_cast(_Float16, h)
+                                         : __uint_as_float(((uint32_t)h) << 16);
       if (EX[i] == 1) {
         f0[i] = o;
         f1[i] = a;

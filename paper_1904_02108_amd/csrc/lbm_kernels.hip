@@ -206,15 +206,14 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide(
 // Two cells per thread (16-bit storage, even x extents): the pair (x0, x0 + 1)
 // is read and written with one 4-byte access per population (see
 // gather_pair); 256 threads over consecutive pairs of an x-y plane.
-// BUF (BF16 lattices under 4 GB): buffer-resource loads and stores
-// (gather_pair_buf_bf16).  F16 keeps the global-address form, which measured
-// faster for it.
+// BUF (16-bit lattices under 4 GB): buffer-resource loads and stores
+// (gather_pair_buf).
 template <int S, int FORCING, bool BUF = false>
 __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide_pairs(
     const typename Store<S>::T* __restrict__ src, typename Store<S>::T* __restrict__ dst,
     const LatticeGeom g, const float* __restrict__ G, const uint8_t* __restrict__ flags,
     double* __restrict__ partials, uint32_t* __restrict__ bad) {
-  static_assert(!BUF || S == LBM_STORE_BF16, "buffer form for BF16 storage");
+  static_assert(!BUF || S != LBM_STORE_F32, "buffer form for 16-bit storage");
   const uint32_t lat_bytes = BUF ? (uint32_t)(g.lat_elems * 2) : 0u;
   const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)src, 0, lat_bytes, 0x00020000);
   const __amdgpu_buffer_rsrc_t rdst = __builtin_amdgcn_make_buffer_rsrc((void*)dst, 0, lat_bytes, 0x00020000);
@@ -233,7 +232,7 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_stream_collide_pairs(
     if constexpr (BUF) {
       const PullIdx pi = pull_index(g, x0, y, z);
       if (pi.fast && (g.bc[0] == LBM_BC_PERIODIC || x0 + 2 < g.nx))
-        gather_pair_buf_bf16(rsrc, g, pi, x0, f0, f1);
+        gather_pair_buf<S>(rsrc, g, pi, x0, f0, f1);
       else
         gather_pair<S>(src, g, x0, y, z, f0, f1);
     } else {
@@ -462,7 +461,7 @@ hipError_t stream_collide_s(lbm_ctx* c) {
   dim3 grid, block;
   stream_collide_shape(c, grid, block);
   if constexpr (S != LBM_STORE_F32) {
-    if constexpr (S == LBM_STORE_BF16) {
+    {
       if (stream_collide_pairs(c) && c->geom.lat_elems * 2 < ((int64_t)1 << 32)) {
         if (c->p.forcing == LBM_FORCE_SHIFT)
           k_stream_collide_pairs<S, LBM_FORCE_SHIFT, true><<<grid, block, 0, c->stream>>>(
