@@ -239,10 +239,14 @@ __global__ __launch_bounds__(LBM_BLOCK) void k_point_count(
 // that own points / are touched (with each owner tile's slot in its list;
 // tiles with more points than a sweep workgroup has threads come first, so
 // that their longer sweeps start first),
-// in three launches: chunk totals, a scan of the chunk totals (which also
-// writes the list lengths, to the device and to pinned host memory for the
-// next forcing's grid sizes), and the chunk rescans that write the outputs
-// and clear the counters and this step's force-block flags.  A chunk is
+// in two launches: chunk totals, then the chunk rescans that write the
+// outputs and clear the counters and this step's force-block flags, each
+// workgroup scanning the (few) chunk totals itself (k_scan_write); in three
+// when there are many chunks (a separate scan of the chunk totals,
+// k_scan_chunks).  (One workgroup for the whole pass of a small tile grid
+// was slower than two launches: a single CU issues every scattered load and
+// store of the pass.)  The pass also writes the list lengths, to the device and
+// to pinned host memory for the next forcing's grid sizes.  A chunk is
 // SCAN_WG threads x SCAN_PER consecutive scan positions.
 //
 // The scan visits the tiles by 4 x 4 x 4 blocks of tiles (x fastest within a
@@ -272,20 +276,21 @@ constexpr int SCAN_WAVES = SCAN_WG / 64;
 constexpr int SCAN_NV = 4;
 constexpr uint32_t HEAVY_TILE = WG;
 
+template <int PER>
 __device__ __forceinline__ void load_counts(const PointGeom& pg,
                                             const uint32_t* __restrict__ cnt_own,
                                             const uint32_t* __restrict__ cnt_touch, int64_t p0,
-                                            int64_t tl[SCAN_PER], uint32_t a[SCAN_PER],
-                                            uint32_t b[SCAN_PER], uint32_t s[SCAN_NV]) {
+                                            int32_t tl[PER], uint32_t a[PER], uint32_t b[PER],
+                                            uint32_t s[SCAN_NV]) {
 #pragma unroll
-  for (int j = 0; j < SCAN_PER; ++j) {
-    tl[j] = scan_tile(pg, p0 + j);
+  for (int j = 0; j < PER; ++j) {
+    tl[j] = (int32_t)scan_tile(pg, p0 + j);  // tile indices fit 31 bits
     a[j] = tl[j] >= 0 ? cnt_own[tl[j]] : 0u;
     b[j] = tl[j] >= 0 ? cnt_touch[tl[j]] : 0u;
   }
   s[0] = s[1] = s[2] = s[3] = 0u;
 #pragma unroll
-  for (int j = 0; j < SCAN_PER; ++j) {
+  for (int j = 0; j < PER; ++j) {
     s[0] += a[j];
     s[1] += a[j] > HEAVY_TILE ? 1u : 0u;
     s[2] += (a[j] && a[j] <= HEAVY_TILE) ? 1u : 0u;
@@ -325,18 +330,63 @@ __device__ __forceinline__ void block_scan(const uint32_t s[SCAN_NV], uint32_t e
   __syncthreads();
 }
 
+// The outputs of a thread's PER scan positions, from its running offsets
+// (run: points, heavy owner tiles, other owner tiles, touched tiles).
+template <int PER>
+__device__ __forceinline__ void write_scan(const int32_t tl[PER], const uint32_t a[PER],
+                                           const uint32_t b[PER], uint32_t run[SCAN_NV],
+                                           uint32_t* __restrict__ cnt_own,
+                                           uint32_t* __restrict__ cnt_touch,
+                                           uint32_t* __restrict__ start_own,
+                                           uint32_t* __restrict__ end_own,
+                                           int32_t* __restrict__ own_slot,
+                                           uint32_t* __restrict__ own_tiles,
+                                           uint32_t* __restrict__ touch_tiles) {
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int32_t t = tl[j];
+    if (t >= 0) {
+      start_own[t] = run[0];
+      end_own[t] = run[0] + a[j];
+      int32_t slot = -1;
+      if (a[j]) slot = (int32_t)(a[j] > HEAVY_TILE ? run[1]++ : run[2]++);
+      own_slot[t] = slot;
+      if (slot >= 0) own_tiles[slot] = (uint32_t)t;
+      if (b[j]) touch_tiles[run[3]++] = (uint32_t)t;
+      run[0] += a[j];
+      cnt_own[t] = 0u;
+      cnt_touch[t] = 0u;
+    }
+  }
+}
+
+// List lengths from the scan totals: owner tiles, touched tiles, heavy owner
+// tiles (listed first); the first two also to pinned host memory (nullable).
+__device__ __forceinline__ void write_meta(const uint32_t tot[SCAN_NV], uint32_t* __restrict__ meta,
+                                           uint32_t* __restrict__ meta_host) {
+  meta[0] = tot[1] + tot[2];
+  meta[1] = tot[3];
+  meta[2] = tot[1];
+  if (meta_host) {  // zero-copy: a plain (vector) store to pinned host memory
+    meta_host[0] = tot[1] + tot[2];
+    meta_host[1] = tot[3];
+  }
+}
+
 __global__ __launch_bounds__(SCAN_WG) void k_scan_totals(PointGeom pg,
                                                          const uint32_t* __restrict__ cnt_own,
                                                          const uint32_t* __restrict__ cnt_touch,
                                                          uint32_t* __restrict__ chunk) {
   const int64_t p0 = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
-  int64_t tl[SCAN_PER];
+  int32_t tl[SCAN_PER];
   uint32_t a[SCAN_PER], b[SCAN_PER], s[SCAN_NV], ex[SCAN_NV], tot[SCAN_NV];
-  load_counts(pg, cnt_own, cnt_touch, p0, tl, a, b, s);
+  load_counts<SCAN_PER>(pg, cnt_own, cnt_touch, p0, tl, a, b, s);
   block_scan<SCAN_WAVES>(s, ex, tot);
   if (threadIdx.x < SCAN_NV) chunk[SCAN_NV * blockIdx.x + threadIdx.x] = tot[threadIdx.x];
 }
 
+// Scan of many chunk totals in one workgroup (in place: exclusive offsets);
+// writes the list lengths.
 constexpr int SCAN2_WG = 1024;
 __global__ __launch_bounds__(SCAN2_WG) void k_scan_chunks(uint32_t* __restrict__ chunk, int64_t nch,
                                                           uint32_t* __restrict__ meta,
@@ -358,48 +408,59 @@ __global__ __launch_bounds__(SCAN2_WG) void k_scan_chunks(uint32_t* __restrict__
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    // meta: owner tiles, touched tiles, heavy owner tiles (listed first)
-    meta[0] = carry[1] + carry[2];
-    meta[1] = carry[3];
-    meta[2] = carry[1];
-    if (meta_host) {  // zero-copy: a plain (vector) store to pinned host memory
-      meta_host[0] = carry[1] + carry[2];
-      meta_host[1] = carry[3];
-    }
+    const uint32_t tot[SCAN_NV] = {carry[0], carry[1], carry[2], carry[3]};
+    write_meta(tot, meta, meta_host);
   }
 }
 
+// The chunk rescans.  FEW (at most SCAN_WG chunks): every workgroup scans the
+// chunk totals itself and workgroup 0 writes the list lengths; otherwise the
+// totals hold k_scan_chunks' offsets and meta its lengths.
+#ifndef LBM_SCAN_FEW_CHUNKS
+#define LBM_SCAN_FEW_CHUNKS 256
+#endif
+constexpr int64_t SCAN_FEW_CHUNKS = LBM_SCAN_FEW_CHUNKS;
+static_assert(SCAN_FEW_CHUNKS <= SCAN_WG, "a thread per chunk total");
+template <bool FEW>
 __global__ __launch_bounds__(SCAN_WG) void k_scan_write(
     PointGeom pg, uint32_t* __restrict__ cnt_own, uint32_t* __restrict__ cnt_touch,
-    const uint32_t* __restrict__ chunk, uint32_t* __restrict__ start_own,
+    const uint32_t* __restrict__ chunk, int64_t nch, uint32_t* __restrict__ start_own,
     uint32_t* __restrict__ end_own, int32_t* __restrict__ own_slot,
     uint32_t* __restrict__ own_tiles, uint32_t* __restrict__ touch_tiles,
-    uint32_t* __restrict__ bflag_words, int64_t nbflag_words, const uint32_t* __restrict__ meta) {
+    uint32_t* __restrict__ bflag_words, int64_t nbflag_words, uint32_t* __restrict__ meta,
+    uint32_t* __restrict__ meta_host) {
+  __shared__ uint32_t pre[SCAN_NV];
+  uint32_t base[SCAN_NV], heavy;
+  if constexpr (FEW) {
+    uint32_t s[SCAN_NV], ex[SCAN_NV], tot[SCAN_NV];
+#pragma unroll
+    for (int q = 0; q < SCAN_NV; ++q)
+      s[q] = (int64_t)threadIdx.x < nch ? chunk[SCAN_NV * threadIdx.x + q] : 0u;
+    block_scan<SCAN_WAVES>(s, ex, tot);
+    if (threadIdx.x == blockIdx.x)
+#pragma unroll
+      for (int q = 0; q < SCAN_NV; ++q) pre[q] = ex[q];
+    if (blockIdx.x == 0 && threadIdx.x == 0) write_meta(tot, meta, meta_host);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SCAN_NV; ++q) base[q] = pre[q];
+    heavy = tot[1];
+  } else {
+#pragma unroll
+    for (int q = 0; q < SCAN_NV; ++q) base[q] = chunk[SCAN_NV * blockIdx.x + q];
+    heavy = meta[2];
+  }
   const int64_t p0 = (int64_t)blockIdx.x * SCAN_CHUNK + (int64_t)threadIdx.x * SCAN_PER;
-  int64_t tl[SCAN_PER];
+  int32_t tl[SCAN_PER];
   uint32_t a[SCAN_PER], b[SCAN_PER], s[SCAN_NV], ex[SCAN_NV], tot[SCAN_NV];
-  load_counts(pg, cnt_own, cnt_touch, p0, tl, a, b, s);
+  load_counts<SCAN_PER>(pg, cnt_own, cnt_touch, p0, tl, a, b, s);
   block_scan<SCAN_WAVES>(s, ex, tot);
   uint32_t run[SCAN_NV];
 #pragma unroll
-  for (int q = 0; q < SCAN_NV; ++q) run[q] = chunk[SCAN_NV * blockIdx.x + q] + ex[q];
-  run[2] += meta[2];  // the other owner tiles follow the heavy ones
-#pragma unroll
-  for (int j = 0; j < SCAN_PER; ++j) {
-    const int64_t t = tl[j];
-    if (t >= 0) {
-      start_own[t] = run[0];
-      end_own[t] = run[0] + a[j];
-      int32_t slot = -1;
-      if (a[j]) slot = (int32_t)(a[j] > HEAVY_TILE ? run[1]++ : run[2]++);
-      own_slot[t] = slot;
-      if (slot >= 0) own_tiles[slot] = (uint32_t)t;
-      if (b[j]) touch_tiles[run[3]++] = (uint32_t)t;
-      run[0] += a[j];
-      cnt_own[t] = 0u;
-      cnt_touch[t] = 0u;
-    }
-  }
+  for (int q = 0; q < SCAN_NV; ++q) run[q] = base[q] + ex[q];
+  run[2] += heavy;  // the other owner tiles follow the heavy ones
+  write_scan<SCAN_PER>(tl, a, b, run, cnt_own, cnt_touch, start_own, end_own, own_slot, own_tiles,
+                       touch_tiles);
   // this chunk's share of the force-block flags
   const int64_t per = (nbflag_words + gridDim.x - 1) / gridDim.x;
   const int64_t w1 = min(nbflag_words, per * (blockIdx.x + 1));
@@ -1726,14 +1787,18 @@ hipError_t launch_forcing(lbm_ctx* c) {
     c->meta_age = refresh ? 0u : c->meta_age + 1u;
     k_scan_totals<<<(unsigned)nch, SCAN_WG, 0, st>>>(pg, c->cnt_own, c->cnt_touch, c->chunk_tot);
     LAUNCH_CHECK();
-    k_scan_chunks<<<1, SCAN2_WG, 0, st>>>(c->chunk_tot, nch, c->meta, mh);
+    const bool few = nch <= SCAN_FEW_CHUNKS;
+    if (!few) {
+      k_scan_chunks<<<1, SCAN2_WG, 0, st>>>(c->chunk_tot, nch, c->meta, mh);
+      LAUNCH_CHECK();
+    }
+    auto kw = few ? k_scan_write<true> : k_scan_write<false>;
+    kw<<<(unsigned)nch, SCAN_WG, 0, st>>>(pg, c->cnt_own, c->cnt_touch, c->chunk_tot, nch,
+                                          c->start_own, c->end_own, c->own_slot, c->own_tiles,
+                                          c->touch_tiles, (uint32_t*)c->bflag, c->nbflag_words,
+                                          c->meta, few ? mh : nullptr);
     LAUNCH_CHECK();
     if (mh && hipEventRecord(c->meta_event, st) == hipSuccess) c->meta_pending = true;
-    k_scan_write<<<(unsigned)nch, SCAN_WG, 0, st>>>(pg, c->cnt_own, c->cnt_touch, c->chunk_tot,
-                                                    c->start_own, c->end_own, c->own_slot,
-                                                    c->own_tiles, c->touch_tiles,
-                                                    (uint32_t*)c->bflag, c->nbflag_words, c->meta);
-    LAUNCH_CHECK();
   }
   // the scatter's temporaries: base in sp_tmp, fraction in sp_g, u_b in sp_du
   // (both written by sweep 0 before they are read)
