@@ -1420,7 +1420,6 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
   __shared__ int16_t ct[3][TILE][MAXCOV], cb[3][TILE][MAXCOV];
   __shared__ int cn[3][TILE];
   __shared__ int32_t nslot[27];
-  __shared__ float nunit[27];
   __shared__ uint8_t tflag[8];
   if (gate && *gate) return;  // the forcing has already converged
   const ListRange lr = list_range(meta[1]);
@@ -1438,16 +1437,12 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
     for (int a = 0; a < 3; ++a)
       simple = simple && tc[a] >= 1 && (tc[a] + 2) * TILE <= pg.n[a];
     if (simple) {
-      // list slots and box units of the 27 tiles around this one, and the
+      // list slots of the 27 tiles around this one (the box units are
+      // loaded with the box sums, one memory round trip fewer), and the
       // flags of the tile's eight force blocks
       if (threadIdx.x < 27) {
         const int dx = threadIdx.x % 3 - 1, dy = (threadIdx.x / 3) % 3 - 1, dz = threadIdx.x / 9 - 1;
-        const int32_t slot = own_slot[tile_index(pg, tc[0] + dx, tc[1] + dy, tc[2] + dz)];
-        nslot[threadIdx.x] = slot;
-        nunit[threadIdx.x] =
-            slot >= 0 ? *reinterpret_cast<const float*>(boxbuf + (int64_t)slot * BOX_SLOT_BYTES +
-                                                        BOX_UNIT_OFF)
-                      : 0.0f;
+        nslot[threadIdx.x] = own_slot[tile_index(pg, tc[0] + dx, tc[1] + dy, tc[2] + dz)];
       } else if (threadIdx.x >= 64 && threadIdx.x < 72) {
         const int b = threadIdx.x - 64;
         const int bx = (o[0] >> FBLK_SHIFT) + (b & 1), by = (o[1] >> FBLK_SHIFT) + ((b >> 1) & 1),
@@ -1518,7 +1513,7 @@ __global__ __launch_bounds__(MERGE_WG) void k_merge_tiles(
             const int bi = nb[0][jx] + BOX * (nb[1][jy] + BOX * nb[2][jz]);
             xy[j] = reinterpret_cast<const unsigned long long*>(sl)[bi];
             zz[j] = reinterpret_cast<const int*>(sl + BOX_Z_OFF)[bi];
-            un[j] = nunit[ni];
+            un[j] = *reinterpret_cast<const float*>(sl + BOX_UNIT_OFF);
           }
         }
   #pragma unroll
