@@ -125,8 +125,8 @@ def learned_leg(torch, L, W, name="c1", n_pairs_steps=150, epochs=10, eval_steps
     rates), then the canonical case (seed 0, held out) run five ways: plain with a
     fixed 5 sweeps, plain to the residual threshold, warm-started from the
     previous step's correction (the non-learned baseline) and warm-started
-    by the network (BF16 operands on the matrix cores, and FP32 weights on
-    the vector units), each to the same threshold.  The threshold is the median
+    by the network (BF16 operands on the matrix cores, and FP32 operands on
+    the matrix cores), each to the same threshold.  The threshold is the median
     relative residual that the plain method reaches at its 5th sweep on the
     held-out case over the steps that are timed."""
     import numpy as np
@@ -504,9 +504,9 @@ def main():
     ap.add_argument("--stop-eps", type=float, default=0.0,
                     help="main run: stop the sweeps at this relative residual (at most the "
                          "workload's sweep count)")
-    ap.add_argument("--warm", default="none", choices=["none", "prev", "net"],
+    ap.add_argument("--warm", default="none", choices=["none", "prev", "net", "net32"],
                     help="main run: warm start from the previous step's correction, or from an "
-                         "untrained network (its cost only)")
+                         "untrained network (its cost only; net32: FP32 operands)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--forcing", default="guo", choices=["guo", "shift"])
     ap.add_argument("--cpu-steps", type=int, default=4)
@@ -549,8 +549,8 @@ def main():
         uflags |= L.IBM_STOP_RESIDUAL
     if args.warm == "prev":
         uflags |= L.IBM_WARM_PREV
-    elif args.warm == "net":
-        uflags |= L.IBM_WARM_START
+    elif args.warm in ("net", "net32"):
+        uflags |= L.IBM_WARM_START | (L.IBM_MLP_FP32 if args.warm == "net32" else 0)
         sim.set_mlp(W.mlp_init(5))
     sim.set_points(wl.rest, wl.area, wl.body_off, wl.bodies, wl.n_iter, uflags,
                    args.stop_eps if args.stop_eps > 0 else 0.0)

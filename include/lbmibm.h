@@ -132,9 +132,10 @@ enum {
                                 IBM_WARM_PREV.                               */
   IBM_KEEP_FEATURES = 8u,    /* compute the features in every forcing so that
                                 ibm_log_pairs can export training pairs       */
-  IBM_MLP_FP32 = 16u,        /* evaluate the warm-start network in FP32 on the
-                                vector units; default: BF16 operands on the
-                                matrix cores with FP32 accumulation           */
+  IBM_MLP_FP32 = 16u,        /* evaluate the warm-start network with FP32
+                                weights and activations (FP32 operands on the
+                                matrix cores); default: BF16 operands on the
+                                matrix cores; both accumulate in FP32         */
   IBM_WARM_PREV = 32u,       /* warm start from the previous forcing (not in
                                 the paper; the non-learned baseline of
                                 IBM_WARM_START): after the first deficit g0,

@@ -1857,7 +1857,7 @@ hipError_t launch_forcing(lbm_ctx* c) {
       const int mode = SW_INTERP | (it == 0 ? SW_FIRST : 0) | (last ? SW_SPREAD_DU : SW_SPREAD_G) |
                        ((last || (it == 0 && feats)) ? SW_STORE_G : 0);
       TRY(sweep(it, mode, nullptr, it == 0 && feats ? c->g0_orig : nullptr));
-      if (it == 0 && feats) TRY(launch_features_warm(c, false));
+      if (it == 0 && feats) TRY(launch_features_warm(c));
       TRY(merge(last, nullptr));
     }
     return hipSuccess;
@@ -1886,12 +1886,12 @@ hipError_t launch_forcing(lbm_ctx* c) {
                                            last ? 1 : 0, use_thr, c->ctl);
     TRY(hipGetLastError());
     if (it == 0 && feats) {
-      // features stored (for logging, or for the FP32 network), else
-      // computed inside the matrix-core warm-start kernel
+      // features stored for logging, else computed inside the warm-start
+      // kernel (BF16 or FP32 operands on the matrix cores)
       const bool fp32 = (c->flags & IBM_MLP_FP32) != 0;
       const bool keep = (c->flags & IBM_KEEP_FEATURES) != 0;
-      if (keep || fp32) TRY(launch_features_warm(c, warm && fp32));
-      if (warm && !fp32) TRY(launch_warm_mfma(c, keep));
+      if (keep) TRY(launch_features_warm(c));
+      if (warm) TRY(fp32 ? launch_warm_mfma32(c, keep) : launch_warm_mfma(c, keep));
     }
     if (it == 0 && warm && !last) {
       TRY(sweep(0, SW_SPREAD_DU, c->ctl, nullptr));

@@ -153,7 +153,8 @@ hipError_t launch_export_points(lbm_ctx* c, double* x, float* ub, float* g, floa
 
 // learned warm start (mlp_kernels.hip)
 hipError_t launch_neighbours(lbm_ctx* c);
-hipError_t launch_features_warm(lbm_ctx* c, bool predict);
+hipError_t launch_features_warm(lbm_ctx* c);
 hipError_t launch_export_pairs(lbm_ctx* c, float* feat, float* targets);
 hipError_t launch_mlp_pack(lbm_ctx* c);
 hipError_t launch_warm_mfma(lbm_ctx* c, bool from_stored_features);
+hipError_t launch_warm_mfma32(lbm_ctx* c, bool from_stored_features);

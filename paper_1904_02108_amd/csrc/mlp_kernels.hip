@@ -24,7 +24,7 @@ constexpr int NNBR = IBM_MLP_NNBR;
 
 __device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
 // The same with the hardware reciprocal (about 1 ulp), for the matrix-core
-// network whose BF16 operands round far more coarsely.
+// networks.
 __device__ __forceinline__ float silu_fast(float z) {
   return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
 }
@@ -368,6 +368,151 @@ __global__ __launch_bounds__(MFMA_WG) void k_warm_mfma(
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same network with FP32 operands on the matrix cores
+// (v_mfma_f32_32x32x2_f32: a 32 x 32 block, two K values per instruction,
+// one operand value per lane).  Lane l holds row / column l % 32 and the K
+// value of its half h = l / 32.  The K order of a contraction is free, so
+// step s of a hidden layer's input block b takes, in half h, hidden unit
+// 32 b + 8 (s / 4) + 4 h + s % 4: the accumulator row that the same lane
+// holds in register s.  The activations then feed the next layer from the
+// lane's own registers, with no exchange between lanes.  Step s of the
+// first layer takes feature 8 h + s (zero past the 12th).
+// Packed operand list (64 lanes x 1 FP32 each):
+//   0-15: layer 1, (block, step);        16-79: layer 2, (b_out, b_in, step);
+//   80-143: layer 3, same;               144-175: layer 4 (rows 0-2), (b_in, step).
+// ---------------------------------------------------------------------------
+constexpr int N_MFMA32 = 176;
+static_assert((size_t)N_MFMA32 * 64 * 4 == MLP_PACKED_F32_BYTES, "FP32 operand count");
+
+__device__ __forceinline__ int step_unit(int b, int s, int h) {
+  return 32 * b + 8 * (s >> 2) + 4 * h + (s & 3);
+}
+
+// theta (FP32 flat layout) -> packed32[N_MFMA32][64] A operands.
+__global__ __launch_bounds__(64) void k_mlp_pack32(const float* __restrict__ theta,
+                                                   float* __restrict__ packed32) {
+  const int m = blockIdx.x, l = threadIdx.x, i = l & 31, h = l >> 5;
+  float v = 0.0f;
+  if (m < 16) {
+    const int bo = m >> 3, k = 8 * h + (m & 7);
+    v = k < NIN ? theta[OFF_W1 + (32 * bo + i) * NIN + k] : 0.0f;
+  } else if (m < 144) {
+    const int q = (m - 16) & 63, off = m < 80 ? OFF_W2 : OFF_W3;
+    const int bo = q >> 5, bi = (q >> 4) & 1, st = q & 15;
+    v = theta[off + (32 * bo + i) * NH + step_unit(bi, st, h)];
+  } else {
+    const int q = m - 144, bi = q >> 4, st = q & 15;
+    v = i < NOUT ? theta[OFF_W4 + i * NH + step_unit(bi, st, h)] : 0.0f;
+  }
+  packed32[m * 64 + l] = v;
+}
+
+struct MfmaWeights32 {
+  float A[N_MFMA32 * 64];
+  float bias[3 * NH + NOUT];
+};
+
+__device__ __forceinline__ void load_mfma_weights32(const float* __restrict__ packed32,
+                                                    const float* __restrict__ theta,
+                                                    MfmaWeights32& W) {
+  for (int i = threadIdx.x; i < N_MFMA32 * 64; i += blockDim.x) W.A[i] = packed32[i];
+  for (int i = threadIdx.x; i < NH; i += blockDim.x) {
+    W.bias[i] = theta[OFF_B1 + i];
+    W.bias[NH + i] = theta[OFF_B2 + i];
+    W.bias[2 * NH + i] = theta[OFF_B3 + i];
+  }
+  if (threadIdx.x < NOUT) W.bias[3 * NH + threadIdx.x] = theta[OFF_B4 + threadIdx.x];
+  __syncthreads();
+}
+
+// Bias and SiLU on the two 32-row accumulator blocks of a hidden layer, in
+// place (the next layer's B operands); the reciprocal of the SiLU to about
+// 1 ulp.
+__device__ __forceinline__ void hidden_act32(f32x16 acc[2], const float* bias, int h) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[b][r] = silu_fast(acc[b][r] + bias[step_unit(b, r, h)]);
+}
+
+// Forward pass of the 32 points of one wave in FP32 (x8 and y as in
+// mlp_group_mfma).
+__device__ __forceinline__ void mlp_group_mfma32(const MfmaWeights32& W, const float x8[8],
+                                                 float y[3]) {
+  const int l = __lane_id(), h = l >> 5;
+  const f32x16 zero = {};
+  f32x16 act[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    f32x16 a = zero;
+#pragma unroll
+    for (int st = 0; st < 8; ++st)
+      a = __builtin_amdgcn_mfma_f32_32x32x2f32(W.A[(8 * b + st) * 64 + l], x8[st], a, 0, 0, 0);
+    act[b] = a;
+  }
+  hidden_act32(act, W.bias, h);
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer) {
+    const int m0 = 16 + 64 * layer;
+    f32x16 nxt[2];
+#pragma unroll
+    for (int bo = 0; bo < 2; ++bo) {
+      f32x16 a = zero;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int st = 0; st < 16; ++st)
+          a = __builtin_amdgcn_mfma_f32_32x32x2f32(W.A[(m0 + 32 * bo + 16 * bi + st) * 64 + l],
+                                                   act[bi][st], a, 0, 0, 0);
+      nxt[bo] = a;
+    }
+    act[0] = nxt[0];
+    act[1] = nxt[1];
+    hidden_act32(act, W.bias + NH * (layer + 1), h);
+  }
+  f32x16 o = zero;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int st = 0; st < 16; ++st)
+      o = __builtin_amdgcn_mfma_f32_32x32x2f32(W.A[(144 + 16 * bi + st) * 64 + l], act[bi][st], o,
+                                               0, 0, 0);
+  y[0] = o[0] + W.bias[3 * NH];
+  y[1] = o[1] + W.bias[3 * NH + 1];
+  y[2] = o[2] + W.bias[3 * NH + 2];
+}
+
+// Warm start with the FP32 network (as k_warm_mfma otherwise).
+__global__ __launch_bounds__(MFMA_WG) void k_warm_mfma32(
+    const float* __restrict__ packed32, const float* __restrict__ theta, int64_t n,
+    const float* __restrict__ feat, const int4* __restrict__ sp_base,
+    const float4* __restrict__ sp_frac, const int32_t* __restrict__ body_of,
+    const float* __restrict__ vref, const uint32_t* __restrict__ gate, float4* __restrict__ sp_du,
+    const float4* __restrict__ sp_g, const float4* __restrict__ sp_ub,
+    const float4* __restrict__ g0_orig, const int32_t* __restrict__ nbr) {
+  __shared__ MfmaWeights32 W;
+  if (*gate) return;
+  load_mfma_weights32(packed32, theta, W);
+  const int l = __lane_id(), h = l >> 5, wave = threadIdx.x >> 6;
+  const int64_t groups = (n + 31) / 32;
+  for (int64_t g = (int64_t)blockIdx.x * (MFMA_WG / 64) + wave; g < groups;
+       g += (int64_t)gridDim.x * (MFMA_WG / 64)) {
+    asm volatile("" ::: "memory");  // weights re-read from LDS for every group
+    const int64_t k = 32 * g + (l & 31);
+    float x8[8], yo[3];
+    if (feat)
+      load_x8(feat, k, n, h, x8);
+    else
+      features8(k, n, h, sp_base, sp_g, sp_ub, g0_orig, nbr, body_of, vref, x8);
+    mlp_group_mfma32(W, x8, yo);
+    if (h == 0 && k < n) {
+      const float sv = sp_frac[k].w * vref[body_of[sp_base[k].w]];
+      sp_du[k] = make_float4(yo[0] * sv, yo[1] * sv, yo[2] * sv, 0.0f);
+    }
+  }
+}
+
 unsigned mfma_grid(int64_t n) {
   const int64_t groups = (n + 31) / 32;
   const int64_t wgs = (groups + MFMA_WG / 64 - 1) / (MFMA_WG / 64);
@@ -496,21 +641,13 @@ __global__ __launch_bounds__(256) void k_neighbours(
 // ---------------------------------------------------------------------------
 // Features of every point after the first sweep (kept in sorted order for
 // logging): g0 (3), u_b (3), mean and component-wise max of g0 over N(k)
-// (3 + 3, zeros for an empty N(k)), all divided by v_ref of k's body.  With
-// theta != nullptr and the forcing not yet converged (*gate == 0) the
-// network's output y gives the warm start du = s v_ref y, which replaces the
-// correction s g0 of the first sweep.
+// (3 + 3, zeros for an empty N(k)), all divided by v_ref of k's body.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_features_warm(
-    const int4* __restrict__ sp_base, const float4* __restrict__ sp_frac,
-    const float4* __restrict__ sp_g, const float4* __restrict__ sp_ub,
-    const float4* __restrict__ g0_orig, const int32_t* __restrict__ nbr,
-    const int32_t* __restrict__ body_of, const float* __restrict__ vref, int64_t npts,
-    float* __restrict__ feat, const float* __restrict__ theta, const uint32_t* __restrict__ gate,
-    float4* __restrict__ sp_du) {
-  __shared__ float P[NPARAM];
-  const bool predict = theta != nullptr && !*gate;
-  if (predict) load_params(theta, P);
+    const int4* __restrict__ sp_base, const float4* __restrict__ sp_g,
+    const float4* __restrict__ sp_ub, const float4* __restrict__ g0_orig,
+    const int32_t* __restrict__ nbr, const int32_t* __restrict__ body_of,
+    const float* __restrict__ vref, int64_t npts, float* __restrict__ feat) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= npts) return;
   const int orig = sp_base[k].w;
@@ -539,12 +676,6 @@ __global__ __launch_bounds__(256) void k_features_warm(
     x[9 + c] = cnt ? mx[c] * inv : 0.0f;
   }
   for (int i = 0; i < NIN; ++i) feat[k * NIN + i] = x[i];
-  if (predict) {
-    float y[NOUT];
-    mlp_eval(P, x, y);
-    const float sv = sp_frac[k].w * v;
-    sp_du[k] = make_float4(y[0] * sv, y[1] * sv, y[2] * sv, 0.0f);
-  }
 }
 
 // Training pairs in caller order: the features and t = du / (s v_ref)
@@ -814,17 +945,18 @@ hipError_t launch_neighbours(lbm_ctx* c) {
   return hipGetLastError();
 }
 
-hipError_t launch_features_warm(lbm_ctx* c, bool predict) {
+hipError_t launch_features_warm(lbm_ctx* c) {
   const unsigned nb = (unsigned)((c->npts + 255) / 256);
   if (nb == 0) return hipSuccess;
-  k_features_warm<<<nb, 256, 0, c->stream>>>(c->sp_base, c->sp_frac, c->sp_g, c->sp_ub, c->g0_orig,
-                                             c->nbr, c->body_of, c->vref, c->npts, c->feat,
-                                             predict ? c->theta : nullptr, c->ctl, c->sp_du);
+  k_features_warm<<<nb, 256, 0, c->stream>>>(c->sp_base, c->sp_g, c->sp_ub, c->g0_orig, c->nbr,
+                                             c->body_of, c->vref, c->npts, c->feat);
   return hipGetLastError();
 }
 
 hipError_t launch_mlp_pack(lbm_ctx* c) {
   k_mlp_pack<<<N_MFMA, 64, 0, c->stream>>>(c->theta, (u32x4*)c->theta_packed);
+  k_mlp_pack32<<<N_MFMA32, 64, 0, c->stream>>>(
+      c->theta, (float*)((char*)c->theta_packed + MLP_PACKED_BF16_BYTES));
   return hipGetLastError();
 }
 
@@ -834,6 +966,15 @@ hipError_t launch_warm_mfma(lbm_ctx* c, bool from_stored_features) {
       (const u32x4*)c->theta_packed, c->theta, c->npts, from_stored_features ? c->feat : nullptr,
       c->sp_base, c->sp_frac, c->body_of, c->vref, c->ctl, c->sp_du, c->sp_g, c->sp_ub, c->g0_orig,
       c->nbr);
+  return hipGetLastError();
+}
+
+hipError_t launch_warm_mfma32(lbm_ctx* c, bool from_stored_features) {
+  if (c->npts == 0) return hipSuccess;
+  k_warm_mfma32<<<mfma_grid(c->npts), MFMA_WG, 0, c->stream>>>(
+      (const float*)((const char*)c->theta_packed + MLP_PACKED_BF16_BYTES), c->theta, c->npts,
+      from_stored_features ? c->feat : nullptr, c->sp_base, c->sp_frac, c->body_of, c->vref,
+      c->ctl, c->sp_du, c->sp_g, c->sp_ub, c->g0_orig, c->nbr);
   return hipGetLastError();
 }
 
