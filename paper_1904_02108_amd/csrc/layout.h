@@ -20,9 +20,9 @@ constexpr int LBM_BLOCK = 256;  // threads per workgroup of the cell and point k
 // bytes per stored spread box (11^3 cells: packed x/y sums, z sums, unit)
 constexpr int BOX_SLOT_BYTES = 16384;
 // matrix-core operands of the warm-start network: BF16 (22 operands x 64
-// lanes x 8 values), then FP32 (176 operands x 64 lanes x 1 value)
+// lanes x 8 values), then FP32 (144 operands x 64 lanes x 1 value)
 constexpr size_t MLP_PACKED_BF16_BYTES = 22 * 64 * 16;
-constexpr size_t MLP_PACKED_F32_BYTES = 176 * 64 * 4;
+constexpr size_t MLP_PACKED_F32_BYTES = 144 * 64 * 4;
 constexpr size_t MLP_PACKED_BYTES = MLP_PACKED_BF16_BYTES + MLP_PACKED_F32_BYTES;
 static_assert(MLP_PACKED_BF16_BYTES % 256 == 0, "FP32 operands 256-byte aligned");
 constexpr size_t BODY_MOTION_BYTES = 10 * sizeof(double);  // struct BodyMotion

@@ -377,12 +377,14 @@ __global__ __launch_bounds__(MFMA_WG) void k_warm_mfma(
 // 32 b + 8 (s / 4) + 4 h + s % 4: the accumulator row that the same lane
 // holds in register s.  The activations then feed the next layer from the
 // lane's own registers, with no exchange between lanes.  Step s of the
-// first layer takes feature 8 h + s (zero past the 12th).
+// first layer takes feature 8 h + s (zero past the 12th).  The output layer
+// (3 rows) runs on the vector units: a matrix instruction would compute 29
+// rows of zeros.
 // Packed operand list (64 lanes x 1 FP32 each):
 //   0-15: layer 1, (block, step);        16-79: layer 2, (b_out, b_in, step);
-//   80-143: layer 3, same;               144-175: layer 4 (rows 0-2), (b_in, step).
+//   80-143: layer 3, same.
 // ---------------------------------------------------------------------------
-constexpr int N_MFMA32 = 176;
+constexpr int N_MFMA32 = 144;
 static_assert((size_t)N_MFMA32 * 64 * 4 == MLP_PACKED_F32_BYTES, "FP32 operand count");
 
 __device__ __forceinline__ int step_unit(int b, int s, int h) {
@@ -397,19 +399,17 @@ __global__ __launch_bounds__(64) void k_mlp_pack32(const float* __restrict__ the
   if (m < 16) {
     const int bo = m >> 3, k = 8 * h + (m & 7);
     v = k < NIN ? theta[OFF_W1 + (32 * bo + i) * NIN + k] : 0.0f;
-  } else if (m < 144) {
+  } else {
     const int q = (m - 16) & 63, off = m < 80 ? OFF_W2 : OFF_W3;
     const int bo = q >> 5, bi = (q >> 4) & 1, st = q & 15;
     v = theta[off + (32 * bo + i) * NH + step_unit(bi, st, h)];
-  } else {
-    const int q = m - 144, bi = q >> 4, st = q & 15;
-    v = i < NOUT ? theta[OFF_W4 + i * NH + step_unit(bi, st, h)] : 0.0f;
   }
   packed32[m * 64 + l] = v;
 }
 
 struct MfmaWeights32 {
   float A[N_MFMA32 * 64];
+  float W4[NOUT * NH];  // output layer, row-major
   float bias[3 * NH + NOUT];
 };
 
@@ -417,6 +417,7 @@ __device__ __forceinline__ void load_mfma_weights32(const float* __restrict__ pa
                                                     const float* __restrict__ theta,
                                                     MfmaWeights32& W) {
   for (int i = threadIdx.x; i < N_MFMA32 * 64; i += blockDim.x) W.A[i] = packed32[i];
+  for (int i = threadIdx.x; i < NOUT * NH; i += blockDim.x) W.W4[i] = theta[OFF_W4 + i];
   for (int i = threadIdx.x; i < NH; i += blockDim.x) {
     W.bias[i] = theta[OFF_B1 + i];
     W.bias[NH + i] = theta[OFF_B2 + i];
@@ -471,16 +472,18 @@ __device__ __forceinline__ void mlp_group_mfma32(const MfmaWeights32& W, const f
     act[1] = nxt[1];
     hidden_act32(act, W.bias + NH * (layer + 1), h);
   }
-  f32x16 o = zero;
+  // output layer: each half-wave's 32 hidden units, then the halves added
+  float p[NOUT] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int st = 0; st < 16; ++st)
-      o = __builtin_amdgcn_mfma_f32_32x32x2f32(W.A[(144 + 16 * bi + st) * 64 + l], act[bi][st], o,
-                                               0, 0, 0);
-  y[0] = o[0] + W.bias[3 * NH];
-  y[1] = o[1] + W.bias[3 * NH + 1];
-  y[2] = o[2] + W.bias[3 * NH + 2];
+    for (int st = 0; st < 16; ++st) {
+      const int u = step_unit(bi, st, h);
+#pragma unroll
+      for (int j = 0; j < NOUT; ++j) p[j] = fmaf(W.W4[j * NH + u], act[bi][st], p[j]);
+    }
+#pragma unroll
+  for (int j = 0; j < NOUT; ++j) y[j] = p[j] + __shfl_xor(p[j], 32, 64) + W.bias[3 * NH + j];
 }
 
 // Warm start with the FP32 network (as k_warm_mfma otherwise).
